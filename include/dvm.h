@@ -1,0 +1,156 @@
+/*
+ * dvm.h -- C ABI of the MI355X (gfx950) discrete-velocity solver for the
+ * steady linearized BGK equation in 2-D staircase geometries.
+ *
+ * Method: Lindsay, Su, Liu & Wu, "Comparative study of the discrete velocity
+ * and lattice Boltzmann methods for rarefied gas flows through irregular
+ * channels" (arXiv:1704.03126):
+ *   - linearized BGK equation, Sec. II.A, Eq. (BGK);
+ *   - discrete velocities of Eq. (nonuniform_v);
+ *   - source iteration of Eq. (iteration) with second-order upwind
+ *     differences (text after Eq. (iteration));
+ *   - diffuse walls, Eq. (diffuse2), on a staircase (Sec. II.A);
+ *   - periodic inlet/outlet and the Poiseuille flow rate Q and apparent
+ *     permeability k_a of Sec. III.
+ *
+ * Conventions shared by every call
+ *   - All pointers passed in are HOST pointers unless stated otherwise.  The
+ *     library copies what it needs during the call; the caller keeps
+ *     ownership and no pointer is retained after the call returns.
+ *   - Every device allocation is owned by the context and freed by
+ *     dvm_destroy.
+ *   - Grids are row-major (ny rows of nx cells), x (axis 1) is the flow
+ *     direction and is always periodic.  One reference length H spans
+ *     cells_per_H cells; the cell size is 1/cells_per_H.
+ *   - Return values: 0 on success, a negative DVM_E* code on failure.  No
+ *     exception or abort crosses the ABI; dvm_last_error() returns a message
+ *     for the calling thread.  Argument checks run on the host before any
+ *     device work, so a rejected call leaves the context unchanged.
+ *   - Calls on one context are not thread-safe; distinct contexts are
+ *     independent.  Work is issued on the stream given to dvm_create.
+ */
+#ifndef DVM_H
+#define DVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DVM_OK 0
+#define DVM_EINVAL (-1)     /* bad argument (message says which)              */
+#define DVM_ENOMEM (-2)     /* device or host allocation failed               */
+#define DVM_EHIP (-3)       /* a HIP runtime call failed                      */
+#define DVM_ESTATE (-4)     /* call out of order (e.g. solve before geometry) */
+#define DVM_ENOCONV (-5)    /* max_iter reached before the stop rule held     */
+#define DVM_EDIVERGED (-6)  /* non-finite or growing iterates                 */
+
+#define DVM_FP64 0          /* all sweeps in FP64                             */
+#define DVM_FP32_REFINE 1   /* FP32 sweeps, FP64 moments + defect correction  */
+
+#define DVM_STATUS_RUNNING 0
+#define DVM_STATUS_CONVERGED 1
+#define DVM_STATUS_MAXITER 2
+#define DVM_STATUS_DIVERGED 3
+
+typedef struct dvm_ctx dvm_ctx; /* opaque, library-owned */
+
+/* Solver settings.  A zero-initialised struct (or NULL) selects defaults. */
+typedef struct {
+    int precision;          /* DVM_FP64 (default) or DVM_FP32_REFINE          */
+    double tol;             /* stop tolerance on the relative change of u1
+                               between iterations (Sec. II.A uses 1e-5);
+                               default 1e-8                                   */
+    long max_iter;          /* iteration cap per solve; default 200000        */
+    int block_iters;        /* iterations per captured launch block; 0 -> 32  */
+    int use_graphs;         /* 1: replay blocks as HIP graphs; 0: plain launches */
+    int vel_per_lane;       /* 0 = autotune, else 4 or 8 velocities per lane  */
+    int waves_per_block;    /* 0 = autotune, else 4 or 8                      */
+    const char *tune_cache; /* autotune cache file or NULL (in-memory only)   */
+} dvm_config;
+
+/* Per-instance result of dvm_solve. */
+typedef struct {
+    long iters;             /* source iterations (FP64 + FP32 sweeps)         */
+    long sweeps_fp64;       /* of which FP64 sweeps                           */
+    double rel_change;      /* last relative change of u1                     */
+    double est_error;       /* a-posteriori bound rel_change*r/(1-r)          */
+    int status;             /* DVM_STATUS_*                                   */
+} dvm_info;
+
+/* Create a context for n_instances independent problems sharing one
+ * velocity grid of nv x nv nodes, Eq. (nonuniform_v) (nv even, 4 <= nv <= 128).
+ * hip_stream: a hipStream_t, or NULL for the default stream.
+ * On success *out receives the context. */
+int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg,
+               void *hip_stream);
+
+/* Describe instance `instance` (0-based): an nx x ny staircase geometry,
+ * solid[ny*nx] (1 = solid, 0 = fluid), periodic_y = 1 for periodic cells,
+ * 0 for walls on the outer y faces.  nx == 1 means invariant along x
+ * (plane channel); otherwise nx >= 4; ny >= 4.  Every fluid component must
+ * carry flux along x (wrap around the x period); fully enclosed pores are
+ * rejected with DVM_EINVAL.  Replaces any previous geometry of the instance
+ * and discards its solution. */
+int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny,
+                     const uint8_t *solid, int periodic_y, double cells_per_H);
+
+/* Solve the steady problem with a unit pressure gradient along +x (the drive
+ * of the Poiseuille problem of Sec. III).
+ *   instance >= 0: solve that instance; delta points to 1 value
+ *     (delta_is_field = 0) or to ny*nx values (delta_is_field = 1, ignored in
+ *     solids).
+ *   instance == -1: solve every instance in one batched launch sequence;
+ *     delta holds n_instances scalars (delta_is_field = 0) or the fields of
+ *     all instances back to back (delta_is_field = 1); info (if non-NULL)
+ *     receives n_instances records.
+ * delta is the rarefaction parameter sqrt(pi)/(2 Kn) >= 0 (finite).
+ * alpha in (0, 1] is the accommodation coefficient: 1 = diffuse walls of
+ * Eq. (diffuse2); alpha < 1 adds Maxwell's specular share 1 - alpha.
+ * Starts from h = 0 (or from the instance's previous solution when the
+ * geometry is unchanged and `warm` semantics are requested with
+ * dvm_solve_warm).  Returns DVM_ENOCONV if some instance hit max_iter
+ * (its state is kept; calling again resumes), DVM_EDIVERGED on non-finite
+ * iterates. */
+int dvm_solve(dvm_ctx *ctx, int instance, const double *delta,
+              int delta_is_field, double alpha, dvm_info *info);
+
+/* As dvm_solve but starting from the instance's current state (warm start
+ * along a delta sweep, or resume after DVM_ENOCONV). */
+int dvm_solve_warm(dvm_ctx *ctx, int instance, const double *delta,
+                   int delta_is_field, double alpha, dvm_info *info);
+
+/* Flow rate of Sec. III, Q = (1/L) * sum over fluid of u1 dA (L = nx cells),
+ * and apparent permeability k_a = sqrt(4/pi) Q Kn = Q / delta (NaN when delta
+ * is a field).  k_a may be NULL. */
+int dvm_flow_rate(const dvm_ctx *ctx, int instance, double *Q, double *k_a);
+
+/* Moments of Sec. II.A at every cell (ny*nx each, 0 in solids): perturbed
+ * density rho (gauge: zero mean over fluid cells), velocities u1, u2,
+ * temperature tau, and shear stress p12 = 2 * int v1 v2 h f_eq.  Any output
+ * may be NULL. */
+int dvm_get_moments(const dvm_ctx *ctx, int instance, double *rho, double *u1,
+                    double *u2, double *tau, double *p12);
+
+/* Gradient of Q by the discrete adjoint: dQ_ddelta[ny*nx] (0 in solids) with
+ * respect to the per-cell rarefaction parameter, and dQ_dalpha with respect
+ * to the accommodation coefficient, at the converged state of the last
+ * dvm_solve of this instance.  Either output may be NULL. */
+int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha);
+
+/* Release every resource of the context (NULL is ignored). */
+void dvm_destroy(dvm_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *dvm_last_error(void);
+
+/* Library version string. */
+const char *dvm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DVM_H */

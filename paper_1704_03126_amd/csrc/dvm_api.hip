@@ -1,0 +1,855 @@
+// dvm_api.hip -- host side of the C ABI declared in include/dvm.h.
+//
+// Owns validation, geometry preprocessing (stencil codes, strips), the
+// velocity tables of Eq. (nonuniform_v), device memory, and the iteration
+// driver that replays captured blocks of source iterations and reads the
+// per-instance stop flags back between blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "../../include/dvm.h"
+#include "dvm_internal.h"
+
+using namespace dvm;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess)                                                          \
+            return fail(DVM_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+namespace {
+
+struct HostInst {
+    bool has_geom = false;
+    int nx = 0, ny = 0, periodic_y = 0;
+    double cph = 1.0;
+    std::vector<uint8_t> solid, codes;
+    long long nfluid = 0;
+    // last solve parameters
+    bool field = false;
+    double delta = 1.0, alpha = 1.0;
+    std::vector<double> dfield;
+    bool has_state = false;   // a converged/partial solution is on the device
+};
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    hipError_t alloc(size_t count)
+    {
+        release();
+        n = count;
+        if (count == 0)
+            return hipSuccess;
+        return hipMalloc((void **)&p, count * sizeof(T));
+    }
+    void release()
+    {
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+} // namespace
+
+struct dvm_ctx {
+    int nv = 0, K = 0, n_inst = 0;
+    dvm_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<double> v, w1;
+    double m0 = 0, m2 = 0, M2 = 0, M4 = 0, c2 = 0, c4 = 0, D = 0;
+    std::vector<HostInst> inst;
+
+    // layout of the device buffers
+    bool layout_ok = false;
+    int V = 8, G = 8, gq = 0, kq = 0, kp4 = 0, max_cells = 0;
+    long long ncell = 0, seam_half = 0, wrap_total = 0;
+    std::vector<InstDev> idev;
+    std::vector<WorkItem> items;
+
+    DevBuf<InstDev> d_inst;
+    DevBuf<WorkItem> d_items;
+    DevBuf<uint8_t> d_codes;
+    DevBuf<double> d_rec, d_vt, d_dfield, d_part, d_mom, d_u1prev, d_seam, d_wrap, d_aux;
+    DevBuf<SolveState> d_st;
+
+    hipGraphExec_t graph = nullptr;
+    int graph_iters = 0;
+    bool graph_field = false;
+
+    ~dvm_ctx()
+    {
+        if (graph)
+            (void)hipGraphExecDestroy(graph);
+        d_inst.release(); d_items.release(); d_codes.release(); d_rec.release();
+        d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release();
+        d_u1prev.release(); d_seam.release(); d_wrap.release(); d_aux.release();
+        d_st.release();
+        if (own_stream && stream)
+            (void)hipStreamDestroy(stream);
+    }
+};
+
+// ------------------------------------------------------------ quadrature
+// Eq. (nonuniform_v): v_j = 4 s_j^3, s_j = (2j - nv + 1)/(nv - 1); weights:
+// trapezoid rule in s times dv/ds, halved at the ends; 2-D weight times the
+// global Maxwellian exp(-|v|^2)/pi of the linearisation.
+static void build_quadrature(dvm_ctx *c)
+{
+    const int nv = c->nv;
+    c->v.assign(nv, 0.0);
+    c->w1.assign(nv, 0.0);
+    const double ds = 2.0 / (nv - 1);
+    for (int j = 0; j < nv; ++j) {
+        double s = (double)(2 * j - nv + 1) / (double)(nv - 1);
+        c->v[j] = 4.0 * s * s * s;
+        c->w1[j] = 12.0 * s * s * ds * ((j == 0 || j == nv - 1) ? 0.5 : 1.0);
+    }
+    double m0 = 0, m2 = 0, M2 = 0, M4 = 0, D = 0;
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            double xi = c->v[i], eta = c->v[j];
+            double W = c->w1[i] * c->w1[j] * std::exp(-xi * xi - eta * eta) / M_PI;
+            double q = xi * xi + eta * eta;
+            m0 += W;
+            m2 += W * xi * xi;
+            M2 += W * q;
+            M4 += W * q * q;
+            if (xi > 0)
+                D += W * xi;
+        }
+    c->m0 = m0;
+    c->m2 = m2;
+    c->M2 = M2;
+    c->M4 = M4;
+    c->c2 = M2 / m0;
+    c->c4 = M4 - M2 * M2 / m0;
+    c->D = D;
+}
+
+// ------------------------------------------------------------- geometry
+static bool solid_at(const HostInst &h, int x, int y)
+{
+    x = ((x % h.nx) + h.nx) % h.nx;
+    if (y < 0 || y >= h.ny) {
+        if (!h.periodic_y)
+            return true;
+        y = ((y % h.ny) + h.ny) % h.ny;
+    }
+    return h.solid[(size_t)y * h.nx + x] != 0;
+}
+
+// Staircase stencil codes (Sec. II.A "stair case"): per fluid cell and side,
+// wall face on that side / upwind neighbour touches a wall / interior.
+static void build_codes(HostInst &h)
+{
+    static const int ddx[4] = {-1, 1, 0, 0};
+    static const int ddy[4] = {0, 0, -1, 1};
+    h.codes.assign((size_t)h.nx * h.ny, 0xFF);
+    h.nfluid = 0;
+    for (int y = 0; y < h.ny; ++y)
+        for (int x = 0; x < h.nx; ++x) {
+            size_t c = (size_t)y * h.nx + x;
+            if (h.solid[c])
+                continue;
+            ++h.nfluid;
+            uint8_t b = 0;
+            for (int d = 0; d < 4; ++d) {
+                int code;
+                if (d < 2 && h.nx == 1)
+                    code = CODE_NONE;
+                else if (solid_at(h, x + ddx[d], y + ddy[d]))
+                    code = CODE_WALL;
+                else if (solid_at(h, x + 2 * ddx[d], y + 2 * ddy[d]))
+                    code = CODE_NEAR;
+                else
+                    code = CODE_INT;
+                b |= (uint8_t)(code << (2 * d));
+            }
+            h.codes[c] = b;
+        }
+}
+
+// Every fluid component must wrap around the x period (carry a net flux);
+// each visited cell remembers the winding of its path from the seed.
+static bool all_components_percolate(const HostInst &h, std::string &why)
+{
+    const int nx = h.nx, ny = h.ny;
+    std::vector<int> lab((size_t)nx * ny, -1);
+    std::vector<long long> wx((size_t)nx * ny, 0);
+    std::deque<int> dq;
+    int ncomp = 0;
+    for (int s = 0; s < nx * ny; ++s) {
+        if (h.solid[s] || lab[s] >= 0)
+            continue;
+        bool perc = false;
+        lab[s] = ncomp;
+        wx[s] = 0;
+        dq.push_back(s);
+        while (!dq.empty()) {
+            int c = dq.front();
+            dq.pop_front();
+            int x = c % nx, y = c / nx;
+            static const int ddx[4] = {1, -1, 0, 0}, ddy[4] = {0, 0, 1, -1};
+            for (int d = 0; d < 4; ++d) {
+                int xx = x + ddx[d], yy = y + ddy[d];
+                long long w = wx[c];
+                if (xx < 0) { xx += nx; w -= 1; }
+                else if (xx >= nx) { xx -= nx; w += 1; }
+                if (yy < 0 || yy >= ny) {
+                    if (!h.periodic_y)
+                        continue;
+                    yy = (yy + ny) % ny;
+                }
+                int n = yy * nx + xx;
+                if (h.solid[n])
+                    continue;
+                if (lab[n] < 0) {
+                    lab[n] = ncomp;
+                    wx[n] = w;
+                    dq.push_back(n);
+                } else if (wx[n] != w) {
+                    perc = true;
+                }
+            }
+        }
+        if (!perc) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg,
+                          "fluid component containing cell (x=%d, y=%d) does not wrap around the x period",
+                          s % nx, s / nx);
+            why = msg;
+            return false;
+        }
+        ++ncomp;
+    }
+    if (ncomp == 0) {
+        why = "geometry has no fluid cell";
+        return false;
+    }
+    return true;
+}
+
+static void strip_layout(int ny, int &nstrips, int &strip_h)
+{
+    nstrips = (ny + 63) / 64;
+    for (;;) {
+        strip_h = (ny + nstrips - 1) / nstrips;
+        int last = ny - (nstrips - 1) * strip_h;
+        if (strip_h <= 64 && last >= 2)
+            return;
+        ++nstrips;
+    }
+}
+
+// The context touches the HIP runtime only from the first solve on, so the
+// host-side checks run without a device.
+static int ensure_device(dvm_ctx *c)
+{
+    if (c->stream)
+        return DVM_OK;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(DVM_EHIP, "no HIP device available");
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+    return DVM_OK;
+}
+
+// -------------------------------------------------------------- layout
+static int build_layout(dvm_ctx *c)
+{
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    const int V = c->V, G = c->G, P = V * G;
+    c->gq = (c->K / 4 + P - 1) / P;
+    c->kq = c->gq * P;
+    c->kp4 = 4 * c->kq;
+    c->idev.assign(c->n_inst, InstDev{});
+    c->items.clear();
+    long long cell = 0, seam = 0, wrap = 0;
+    int maxc = 0;
+    for (int i = 0; i < c->n_inst; ++i) {
+        const HostInst &h = c->inst[i];
+        InstDev &d = c->idev[i];
+        d.nx = h.nx;
+        d.ny = h.ny;
+        d.tp = h.nx >= 4 ? h.nx : 64;
+        strip_layout(h.ny, d.nstrips, d.strip_h);
+        d.periodic_y = h.periodic_y;
+        d.cell_off = cell;
+        d.seam_off = seam;
+        d.wrap_off = wrap;
+        d.inv_dx = h.cph;
+        d.delta = 1.0;
+        d.alpha = 1.0;
+        d.drive = 1.0;
+        cell += (long long)h.nx * h.ny;
+        seam += (long long)d.nstrips * h.nx * 2 * c->kp4;
+        wrap += (long long)d.nstrips * c->kp4 * 64 * 3;
+        maxc = std::max(maxc, h.nx * h.ny);
+        for (int s = 0; s < d.nstrips; ++s)
+            for (int g = 0; g < 4 * c->gq; ++g)
+                c->items.push_back(WorkItem{i, s, g, 0});
+    }
+    // longest passes first: the tail of the launch is then made of short items
+    std::stable_sort(c->items.begin(), c->items.end(), [&](const WorkItem &a, const WorkItem &b) {
+        return c->idev[a.inst].tp > c->idev[b.inst].tp;
+    });
+    c->ncell = cell;
+    c->seam_half = seam;
+    c->wrap_total = wrap;
+    c->max_cells = maxc;
+
+    HIPCHK(c->d_inst.alloc(c->n_inst));
+    HIPCHK(c->d_items.alloc(c->items.size()));
+    HIPCHK(c->d_codes.alloc(cell));
+    HIPCHK(c->d_rec.alloc(cell * REC_STRIDE));
+    HIPCHK(c->d_vt.alloc((size_t)c->n_inst * c->kp4 * VT_STRIDE));
+    HIPCHK(c->d_dfield.alloc(cell));
+    HIPCHK(c->d_part.alloc((size_t)4 * c->gq * cell * 4));
+    HIPCHK(c->d_mom.alloc(cell * MOM_STRIDE));
+    HIPCHK(c->d_u1prev.alloc(cell));
+    HIPCHK(c->d_seam.alloc(2 * seam));
+    HIPCHK(c->d_wrap.alloc(wrap));
+    HIPCHK(c->d_aux.alloc(cell));
+    HIPCHK(c->d_st.alloc(c->n_inst));
+
+    std::vector<uint8_t> codes(cell);
+    std::vector<double> vt((size_t)c->n_inst * c->kp4 * VT_STRIDE, 0.0);
+    const int h2 = c->nv / 2;
+    for (int i = 0; i < c->n_inst; ++i) {
+        const HostInst &h = c->inst[i];
+        std::copy(h.codes.begin(), h.codes.end(), codes.begin() + c->idev[i].cell_off);
+        for (int q = 0; q < 4; ++q)
+            for (int idx = 0; idx < c->K / 4; ++idx) {
+                int ip = idx / h2, jp = idx % h2;
+                int iv = (q & 1) ? h2 - 1 - ip : h2 + ip;   // node of xi
+                int jv = (q & 2) ? h2 - 1 - jp : h2 + jp;   // node of eta
+                double xi = c->v[iv], eta = c->v[jv];
+                double *e = &vt[((size_t)i * c->kp4 + q * c->kq + idx) * VT_STRIDE];
+                e[VT_XI] = xi;
+                e[VT_ETA] = eta;
+                e[VT_Q] = xi * xi + eta * eta;
+                e[VT_W] = c->w1[iv] * c->w1[jv] * std::exp(-xi * xi - eta * eta) / M_PI;
+                e[VT_CX] = h.nx == 1 ? 0.0 : std::fabs(xi) * h.cph;
+                e[VT_CY] = std::fabs(eta) * h.cph;
+            }
+    }
+    HIPCHK(hipMemcpyAsync(c->d_codes.p, codes.data(), cell, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_vt.p, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_items.p, c->items.data(), c->items.size() * sizeof(WorkItem),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_zero(c->d_mom.p, c->d_mom.n, c->stream));
+    HIPCHK(launch_zero(c->d_u1prev.p, c->d_u1prev.n, c->stream));
+    HIPCHK(launch_zero(c->d_seam.p, c->d_seam.n, c->stream));
+    HIPCHK(launch_zero(c->d_wrap.p, c->d_wrap.n, c->stream));
+    HIPCHK(launch_zero(c->d_dfield.p, c->d_dfield.n, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (auto &h : c->inst)
+        h.has_state = false;
+    c->layout_ok = true;
+    return DVM_OK;
+}
+
+static SweepArgs<double> sweep_args(dvm_ctx *c, int force)
+{
+    SweepArgs<double> a{};
+    a.inst = c->d_inst.p;
+    a.items = c->d_items.p;
+    a.codes = c->d_codes.p;
+    a.rec = c->d_rec.p;
+    a.vtab = c->d_vt.p;
+    a.delta_field = c->d_dfield.p;
+    a.part = c->d_part.p;
+    a.seam = c->d_seam.p;
+    a.wrap = c->d_wrap.p;
+    a.st = c->d_st.p;
+    a.ncell = c->ncell;
+    a.seam_half = c->seam_half;
+    a.gq = c->gq;
+    a.kq = c->kq;
+    a.kp4 = c->kp4;
+    a.force = force;
+    return a;
+}
+
+static MomArgs mom_args(dvm_ctx *c)
+{
+    MomArgs a{};
+    a.inst = c->d_inst.p;
+    a.codes = c->d_codes.p;
+    a.part = c->d_part.p;
+    a.mom = c->d_mom.p;
+    a.st = c->d_st.p;
+    a.ncell = c->ncell;
+    a.gq = c->gq;
+    return a;
+}
+
+static RecArgs<double> rec_args(dvm_ctx *c)
+{
+    RecArgs<double> a{};
+    a.inst = c->d_inst.p;
+    a.codes = c->d_codes.p;
+    a.mom = c->d_mom.p;
+    a.delta_field = c->d_dfield.p;
+    a.u1prev = c->d_u1prev.p;
+    a.rec = c->d_rec.p;
+    a.st = c->d_st.p;
+    a.m0 = c->m0;
+    a.m2 = c->m2;
+    a.c2 = c->c2;
+    a.c4 = c->c4;
+    a.D = c->D;
+    return a;
+}
+
+static bool any_field(const dvm_ctx *c)
+{
+    for (const auto &h : c->inst)
+        if (h.field)
+            return true;
+    return false;
+}
+
+// One source iteration for every active instance.
+static int enqueue_iteration(dvm_ctx *c)
+{
+    HIPCHK(launch_sweep<double>(sweep_args(c, 0), (int)c->items.size(), c->V, c->G, any_field(c),
+                                false, c->stream));
+    HIPCHK(launch_moments(mom_args(c), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(launch_status(c->d_st.p, c->n_inst, c->cfg.tol, c->cfg.max_iter, c->stream));
+    return DVM_OK;
+}
+
+static int enqueue_block(dvm_ctx *c, int iters)
+{
+    if (!c->cfg.use_graphs) {
+        for (int i = 0; i < iters; ++i) {
+            int rc = enqueue_iteration(c);
+            if (rc)
+                return rc;
+        }
+        return DVM_OK;
+    }
+    if (!c->graph || c->graph_iters != iters || c->graph_field != any_field(c)) {
+        if (c->graph) {
+            (void)hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int rc = DVM_OK;
+        for (int i = 0; i < iters && rc == DVM_OK; ++i)
+            rc = enqueue_iteration(c);
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (rc)
+            return rc;
+        HIPCHK(e);
+        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        c->graph_iters = iters;
+        c->graph_field = any_field(c);
+    }
+    HIPCHK(hipGraphLaunch(c->graph, c->stream));
+    return DVM_OK;
+}
+
+static int check_instance(const dvm_ctx *c, int instance)
+{
+    if (!c)
+        return fail(DVM_EINVAL, "context is NULL");
+    if (instance < 0 || instance >= c->n_inst)
+        return fail(DVM_EINVAL, "instance index out of range");
+    return DVM_OK;
+}
+
+static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_field,
+                    double alpha, dvm_info *info, bool warm)
+{
+    if (!c)
+        return fail(DVM_EINVAL, "context is NULL");
+    if (instance < -1 || instance >= c->n_inst)
+        return fail(DVM_EINVAL, "instance index out of range");
+    if (!delta)
+        return fail(DVM_EINVAL, "delta is NULL");
+    if (!(alpha > 0.0 && alpha <= 1.0))
+        return fail(DVM_EINVAL, "alpha must lie in (0, 1]");
+    if (alpha < 1.0)
+        return fail(DVM_EINVAL, "alpha < 1 (Maxwell specular share) is not supported by this build");
+    const int i0 = instance < 0 ? 0 : instance, i1 = instance < 0 ? c->n_inst : instance + 1;
+    for (int i = i0; i < i1; ++i)
+        if (!c->inst[i].has_geom)
+            return fail(DVM_ESTATE, "dvm_set_geometry has not been called for instance " + std::to_string(i));
+    // validate delta on the host before any device work
+    {
+        size_t off = 0;
+        for (int i = i0; i < i1; ++i) {
+            const HostInst &h = c->inst[i];
+            if (delta_is_field) {
+                for (size_t k = 0; k < (size_t)h.nx * h.ny; ++k)
+                    if (!h.solid[k] && !(std::isfinite(delta[off + k]) && delta[off + k] >= 0.0))
+                        return fail(DVM_EINVAL, "delta field must be finite and >= 0 in fluid cells");
+                off += (size_t)h.nx * h.ny;
+            } else {
+                double d = delta[instance < 0 ? i : 0];
+                if (!(std::isfinite(d) && d >= 0.0))
+                    return fail(DVM_EINVAL, "delta must be finite and >= 0");
+            }
+        }
+    }
+    {
+        int rc = ensure_device(c);
+        if (rc)
+            return rc;
+    }
+    if (!c->layout_ok) {
+        int rc = build_layout(c);
+        if (rc)
+            return rc;
+    }
+    // parameters
+    std::vector<double> dcat;
+    size_t off = 0;
+    for (int i = i0; i < i1; ++i) {
+        HostInst &h = c->inst[i];
+        InstDev &d = c->idev[i];
+        h.alpha = alpha;
+        h.field = delta_is_field != 0;
+        d.alpha = alpha;
+        d.field = h.field ? 1 : 0;
+        d.drive = 1.0;
+        if (h.field) {
+            size_t n = (size_t)h.nx * h.ny;
+            h.dfield.assign(delta + off, delta + off + n);
+            h.delta = NAN;
+            d.delta = 0.0;
+            HIPCHK(hipMemcpyAsync(c->d_dfield.p + d.cell_off, delta + off, n * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+            off += n;
+        } else {
+            h.delta = delta[instance < 0 ? i : 0];
+            d.delta = h.delta;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(c->d_inst.p, c->idev.data(), c->n_inst * sizeof(InstDev),
+                          hipMemcpyHostToDevice, c->stream));
+    // per-instance state: solve [i0, i1), freeze the others
+    std::vector<SolveState> st(c->n_inst);
+    HIPCHK(hipMemcpyAsync(st.data(), c->d_st.p, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<long long> iter0(c->n_inst, 0);
+    for (int i = 0; i < c->n_inst; ++i) {
+        SolveState &s = st[i];
+        bool mine = i >= i0 && i < i1;
+        if (!c->inst[i].has_state && !mine)
+            s = SolveState{};
+        if (mine) {
+            bool keep = warm && c->inst[i].has_state;
+            if (!keep) {
+                const InstDev &d = c->idev[i];
+                size_t n = (size_t)d.nx * d.ny;
+                HIPCHK(launch_zero(c->d_mom.p + d.cell_off * MOM_STRIDE, n * MOM_STRIDE, c->stream));
+                HIPCHK(launch_zero(c->d_u1prev.p + d.cell_off, n, c->stream));
+                size_t sn = (size_t)d.nstrips * d.nx * 2 * c->kp4;
+                HIPCHK(launch_zero(c->d_seam.p + d.seam_off, sn, c->stream));
+                HIPCHK(launch_zero(c->d_seam.p + c->seam_half + d.seam_off, sn, c->stream));
+                HIPCHK(launch_zero(c->d_wrap.p + d.wrap_off, (size_t)d.nstrips * c->kp4 * 64 * 3,
+                                   c->stream));
+                s = SolveState{};
+            }
+            s.active = 1;
+            s.status = STATUS_RUNNING;
+            s.npass = 0;
+            s.eps_prev = 0.0;
+            s.maxdiff_bits = s.maxabs_bits = 0ull;
+            iter0[i] = s.iter;
+        } else {
+            s.active = 0;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(c->d_st.p, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                          c->stream));
+    // the record of the first sweep (from zero or the warm moments); the stop
+    // statistics it gathers are discarded
+    HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+    for (int i = i0; i < i1; ++i) {
+        st[i].maxdiff_bits = st[i].maxabs_bits = 0ull;
+    }
+    // u1prev was refreshed by the record kernel; reset the max slots only
+    HIPCHK(hipMemcpyAsync(c->d_st.p, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                          c->stream));
+    for (int i = i0; i < i1; ++i)
+        c->inst[i].has_state = true;
+
+    const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
+    const long long cap = c->cfg.max_iter;
+    for (;;) {
+        int rc = enqueue_block(c, B);
+        if (rc)
+            return rc;
+        HIPCHK(hipMemcpyAsync(st.data(), c->d_st.p, c->n_inst * sizeof(SolveState),
+                              hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        bool running = false;
+        for (int i = i0; i < i1; ++i) {
+            if (st[i].active && st[i].iter - iter0[i] < cap)
+                running = true;
+        }
+        if (!running)
+            break;
+    }
+    int rc = DVM_OK;
+    for (int i = i0; i < i1; ++i) {
+        const SolveState &s = st[i];
+        if (info) {
+            dvm_info &o = info[instance < 0 ? i : 0];
+            o.iters = s.iter - iter0[i];
+            o.sweeps_fp64 = o.iters;
+            o.rel_change = s.eps;
+            o.est_error = s.est;
+            o.status = s.status;
+        }
+        if (s.status == STATUS_DIVERGED)
+            rc = fail(DVM_EDIVERGED, "instance " + std::to_string(i) + " produced non-finite iterates");
+        else if (rc == DVM_OK && s.status != STATUS_CONVERGED)
+            rc = fail(DVM_ENOCONV, "instance " + std::to_string(i) + " reached max_iter");
+    }
+    return rc;
+}
+
+// ================================================================ C ABI
+extern "C" {
+
+const char *dvm_last_error(void) { return g_err.c_str(); }
+
+const char *dvm_version(void) { return "dvm-gfx950 0.1"; }
+
+int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, void *hip_stream)
+{
+    if (!out)
+        return fail(DVM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nv < 4 || nv > 128 || (nv % 2) != 0)
+        return fail(DVM_EINVAL, "nv must be even and in [4, 128]");
+    if (n_instances < 1 || n_instances > 65535)
+        return fail(DVM_EINVAL, "n_instances must be in [1, 65535]");
+    dvm_config c{};
+    if (cfg)
+        c = *cfg;
+    if (c.precision != DVM_FP64 && c.precision != DVM_FP32_REFINE)
+        return fail(DVM_EINVAL, "unknown precision mode");
+    if (c.tol == 0.0)
+        c.tol = 1e-8;
+    if (!(c.tol > 0.0))
+        return fail(DVM_EINVAL, "tol must be > 0");
+    if (c.max_iter == 0)
+        c.max_iter = 200000;
+    if (c.max_iter < 0)
+        return fail(DVM_EINVAL, "max_iter must be > 0");
+    if (c.block_iters < 0 || c.block_iters > 4096)
+        return fail(DVM_EINVAL, "block_iters must be in [0, 4096]");
+    int V = c.vel_per_lane ? c.vel_per_lane : 8;
+    int G = c.waves_per_block ? c.waves_per_block : 8;
+    bool okvg = (V == 8 && G == 8) || (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) ||
+                (V == 4 && G == 16) || (V == 2 && G == 16);
+    if (!okvg)
+        return fail(DVM_EINVAL, "unsupported (vel_per_lane, waves_per_block) combination");
+    dvm_ctx *ctx = new (std::nothrow) dvm_ctx();
+    if (!ctx)
+        return fail(DVM_ENOMEM, "out of host memory");
+    ctx->nv = nv;
+    ctx->K = nv * nv;
+    ctx->n_inst = n_instances;
+    ctx->cfg = c;
+    ctx->V = V;
+    ctx->G = G;
+    ctx->inst.assign(n_instances, HostInst{});
+    ctx->stream = (hipStream_t)hip_stream;   // NULL: a stream is made on first use
+    build_quadrature(ctx);
+    *out = ctx;
+    return DVM_OK;
+}
+
+int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny, const uint8_t *solid, int periodic_y,
+                     double cells_per_H)
+{
+    int rc = check_instance(ctx, instance);
+    if (rc)
+        return rc;
+    if (!solid)
+        return fail(DVM_EINVAL, "solid is NULL");
+    if (!(nx == 1 || nx >= 4) || ny < 4)
+        return fail(DVM_EINVAL, "need nx == 1 or nx >= 4, and ny >= 4");
+    if ((long long)nx * ny > (1ll << 30))
+        return fail(DVM_EINVAL, "grid too large");
+    if (!(cells_per_H > 0.0) || !std::isfinite(cells_per_H))
+        return fail(DVM_EINVAL, "cells_per_H must be finite and > 0");
+    HostInst h;
+    h.nx = nx;
+    h.ny = ny;
+    h.periodic_y = periodic_y ? 1 : 0;
+    h.cph = cells_per_H;
+    h.solid.resize((size_t)nx * ny);
+    for (size_t k = 0; k < h.solid.size(); ++k) {
+        if (solid[k] > 1)
+            return fail(DVM_EINVAL, "solid mask values must be 0 or 1");
+        h.solid[k] = solid[k];
+    }
+    std::string why;
+    if (!all_components_percolate(h, why))
+        return fail(DVM_EINVAL, why);
+    build_codes(h);
+    h.has_geom = true;
+    ctx->inst[instance] = std::move(h);
+    ctx->layout_ok = false;
+    return DVM_OK;
+}
+
+int dvm_solve(dvm_ctx *ctx, int instance, const double *delta, int delta_is_field, double alpha,
+              dvm_info *info)
+{
+    return do_solve(ctx, instance, delta, delta_is_field, alpha, info, false);
+}
+
+int dvm_solve_warm(dvm_ctx *ctx, int instance, const double *delta, int delta_is_field, double alpha,
+                   dvm_info *info)
+{
+    return do_solve(ctx, instance, delta, delta_is_field, alpha, info, true);
+}
+
+int dvm_flow_rate(const dvm_ctx *cc, int instance, double *Q, double *k_a)
+{
+    dvm_ctx *ctx = const_cast<dvm_ctx *>(cc);
+    int rc = check_instance(ctx, instance);
+    if (rc)
+        return rc;
+    if (!Q)
+        return fail(DVM_EINVAL, "Q is NULL");
+    const HostInst &h = ctx->inst[instance];
+    if (!ctx->layout_ok || !h.has_state)
+        return fail(DVM_ESTATE, "instance has not been solved");
+    const InstDev &d = ctx->idev[instance];
+    size_t n = (size_t)d.nx * d.ny;
+    std::vector<double> mom(n * MOM_STRIDE);
+    HIPCHK(hipMemcpyAsync(mom.data(), ctx->d_mom.p + d.cell_off * MOM_STRIDE, mom.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double s = 0.0;
+    for (size_t k = 0; k < n; ++k)
+        if (!h.solid[k])
+            s += mom[k * MOM_STRIDE + MOM_U1];
+    *Q = s / (h.cph * h.nx);   // (1/L) sum u1 dA, L = nx / cells_per_H
+    if (k_a)
+        *k_a = h.field ? NAN : *Q / h.delta;
+    return DVM_OK;
+}
+
+int dvm_get_moments(const dvm_ctx *cc, int instance, double *rho, double *u1, double *u2, double *tau,
+                    double *p12)
+{
+    dvm_ctx *ctx = const_cast<dvm_ctx *>(cc);
+    int rc = check_instance(ctx, instance);
+    if (rc)
+        return rc;
+    const HostInst &h = ctx->inst[instance];
+    if (!ctx->layout_ok || !h.has_state)
+        return fail(DVM_ESTATE, "instance has not been solved");
+    const InstDev &d = ctx->idev[instance];
+    size_t n = (size_t)d.nx * d.ny;
+    std::vector<double> mom(n * MOM_STRIDE);
+    HIPCHK(hipMemcpyAsync(mom.data(), ctx->d_mom.p + d.cell_off * MOM_STRIDE, mom.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<double> shear;
+    if (p12) {
+        // the shear stress is not carried by the iteration: one extra
+        // diagnostic sweep from the current state accumulates it
+        SweepArgs<double> a = sweep_args(ctx, 1);
+        std::vector<WorkItem> mine;
+        for (const auto &it : ctx->items)
+            if (it.inst == instance)
+                mine.push_back(it);
+        DevBuf<WorkItem> ditems;
+        HIPCHK(ditems.alloc(mine.size()));
+        HIPCHK(hipMemcpyAsync(ditems.p, mine.data(), mine.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                              ctx->stream));
+        a.items = ditems.p;
+        HIPCHK(launch_sweep<double>(a, (int)mine.size(), ctx->V, ctx->G, h.field, true, ctx->stream));
+        MomArgs m = mom_args(ctx);
+        HIPCHK(launch_sum1(m, ctx->d_aux.p, ctx->max_cells, ctx->n_inst, ctx->stream));
+        shear.resize(n);
+        HIPCHK(hipMemcpyAsync(shear.data(), ctx->d_aux.p + d.cell_off, n * sizeof(double),
+                              hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ditems.release();
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double rmean = 0.0;
+    long long nf = 0;
+    for (size_t k = 0; k < n; ++k)
+        if (!h.solid[k]) {
+            rmean += mom[k * MOM_STRIDE + MOM_RHO];
+            ++nf;
+        }
+    rmean /= (double)nf;
+    for (size_t k = 0; k < n; ++k) {
+        bool f = !h.solid[k];
+        const double *m = &mom[k * MOM_STRIDE];
+        double r = f ? m[MOM_RHO] - rmean : 0.0;
+        double e = f ? m[MOM_E] - rmean * ctx->M2 / ctx->m0 : 0.0;
+        if (rho) rho[k] = r;
+        if (u1) u1[k] = f ? m[MOM_U1] : 0.0;
+        if (u2) u2[k] = f ? m[MOM_U2] : 0.0;
+        if (tau) tau[k] = f ? e - r : 0.0;
+        if (p12) p12[k] = f ? shear[k] : 0.0;
+    }
+    return DVM_OK;
+}
+
+int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha)
+{
+    int rc = check_instance(ctx, instance);
+    if (rc)
+        return rc;
+    (void)dQ_ddelta;
+    (void)dQ_dalpha;
+    return fail(DVM_ESTATE, "the adjoint is not available in this build");
+}
+
+void dvm_destroy(dvm_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    if (ctx->stream)
+        (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+}
+
+} // extern "C"

@@ -1,0 +1,120 @@
+// dvm_internal.h -- structures shared by the host driver and the gfx950
+// kernels of the discrete velocity solver (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dvm {
+
+// sides of a cell, and the per-side stencil code (2 bits each in a byte:
+// bits 2d..2d+1 for side d).  A solid cell has code byte 0xFF.
+enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
+enum { CODE_INT = 0, CODE_NEAR = 1, CODE_WALL = 2, CODE_NONE = 3 };
+// reciprocal-diagonal variants: bit 1 = wall on the x upwind side, bit 0 =
+// wall on the y upwind side; 4 = solid / no cell
+enum { NSTENCIL = 5, STENCIL_SOLID = 4 };
+
+// per-velocity constants, VT_STRIDE values per velocity, velocities ordered
+// by quadrant (q = 0: xi>0,eta>0; 1: xi<0,eta>0; 2: xi>0,eta<0; 3: both <0)
+enum { VT_XI = 0, VT_ETA = 1, VT_Q = 2, VT_W = 3, VT_CX = 4, VT_CY = 5, VT_STRIDE = 8 };
+
+// per-cell record read by the sweep: b0..b3 (delta times the collision gain
+// coefficients, drive included in b1) and the value leaving each wall face
+enum { REC_STRIDE = 8 };
+
+// per-cell moments written by k_moments
+enum {
+    MOM_RHO = 0, MOM_U1 = 1, MOM_U2 = 2, MOM_E = 3,
+    MOM_FXP = 4, MOM_FXM = 5, MOM_FYP = 6, MOM_FYM = 7, MOM_STRIDE = 8
+};
+
+enum { STATUS_RUNNING = 0, STATUS_CONVERGED = 1, STATUS_MAXITER = 2, STATUS_DIVERGED = 3 };
+
+struct InstDev {
+    int nx, ny;
+    int tp;          // schedule period of a strip pass (nx, or 64 when nx == 1)
+    int nstrips;
+    int strip_h;     // rows per strip (last strip may be shorter, >= 2)
+    int periodic_y;
+    int field;       // delta given per cell
+    int pad0;
+    long long cell_off;   // first cell of this instance in the cell arrays
+    long long seam_off;   // offset in one parity half of the seam buffer
+    long long wrap_off;   // offset in the wrap-state buffer
+    double delta;         // uniform delta (field == 0)
+    double alpha;         // accommodation coefficient
+    double drive;         // coefficient of the pressure-gradient source
+    double inv_dx;
+};
+
+struct WorkItem {
+    int inst, strip, group, pad;
+};
+
+struct SolveState {
+    long long iter;       // completed iterations
+    int status;
+    int npass;
+    int active;
+    int pad0;
+    double eps, eps_prev, est;
+    unsigned long long maxdiff_bits, maxabs_bits;
+};
+
+template <typename T>
+struct SweepArgs {
+    const InstDev *inst;
+    const WorkItem *items;
+    const uint8_t *codes;
+    const T *rec;
+    const T *vtab;            // [inst][kp4][VT_STRIDE]
+    const double *delta_field;
+    double *part;             // [group][ncell][4]   (final pass: [group][ncell])
+    T *seam;                  // [2][seam_half]
+    T *wrap;
+    SolveState *st;
+    long long ncell;          // total cells over all instances
+    long long seam_half;
+    int gq;                   // velocity groups per quadrant
+    int kq;                   // padded velocities per quadrant (= gq * G * V)
+    int kp4;                  // 4 * kq
+    int force;                // run even for converged instances
+};
+
+struct MomArgs {
+    const InstDev *inst;
+    const uint8_t *codes;
+    const double *part;
+    double *mom;
+    SolveState *st;
+    long long ncell;
+    int gq;
+};
+
+template <typename T>
+struct RecArgs {
+    const InstDev *inst;
+    const uint8_t *codes;
+    const double *mom;
+    const double *delta_field;
+    double *u1prev;
+    T *rec;
+    SolveState *st;
+    double m0, m2, c2, c4, D;
+};
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, bool field,
+                        bool final_pass, hipStream_t s);
+hipError_t launch_moments(const MomArgs &a, int max_cells, int n_inst, hipStream_t s);
+hipError_t launch_sum1(const MomArgs &a, double *out, int max_cells, int n_inst, hipStream_t s);
+template <typename T>
+hipError_t launch_record(const RecArgs<T> &a, int max_cells, int n_inst, hipStream_t s);
+hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, hipStream_t s);
+hipError_t launch_zero(double *p, size_t n, hipStream_t s);
+hipError_t launch_zero_f(float *p, size_t n, hipStream_t s);
+hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+
+} // namespace dvm

@@ -1,0 +1,202 @@
+"""Python binding of the C ABI in ``include/dvm.h`` (ctypes).
+
+Argument marshalling only: every step of the solver runs in ``libdvm.so``
+(gfx950 HIP kernels).  The library must have been built (``build.py``); there
+is no fallback -- importing this module without the library raises.
+PyTorch, when present, only supplies the HIP stream the work is issued on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdvm.so")
+
+DVM_OK = 0
+DVM_EINVAL = -1
+DVM_ENOMEM = -2
+DVM_EHIP = -3
+DVM_ESTATE = -4
+DVM_ENOCONV = -5
+DVM_EDIVERGED = -6
+DVM_FP64 = 0
+DVM_FP32_REFINE = 1
+STATUS_NAMES = {0: "running", 1: "converged", 2: "max_iter", 3: "diverged"}
+
+EXPORTED = ("dvm_create", "dvm_set_geometry", "dvm_solve", "dvm_solve_warm",
+            "dvm_flow_rate", "dvm_get_moments", "dvm_grad", "dvm_destroy",
+            "dvm_last_error", "dvm_version")
+
+
+class DVMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class dvm_config(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_long), ("block_iters", ctypes.c_int),
+                ("use_graphs", ctypes.c_int), ("vel_per_lane", ctypes.c_int),
+                ("waves_per_block", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+
+
+class dvm_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_long), ("sweeps_fp64", ctypes.c_long),
+                ("rel_change", ctypes.c_double), ("est_error", ctypes.c_double),
+                ("status", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdvm.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_1704_03126_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.dvm_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(dvm_config), P]
+    lib.dvm_set_geometry.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
+                                     ctypes.c_int, ctypes.c_double]
+    lib.dvm_solve.argtypes = [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_double,
+                              ctypes.POINTER(dvm_info)]
+    lib.dvm_solve_warm.argtypes = lib.dvm_solve.argtypes
+    lib.dvm_flow_rate.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+    lib.dvm_get_moments.argtypes = [P, ctypes.c_int, P, P, P, P, P]
+    lib.dvm_grad.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double)]
+    lib.dvm_destroy.argtypes = [P]
+    lib.dvm_destroy.restype = None
+    lib.dvm_last_error.restype = ctypes.c_char_p
+    lib.dvm_version.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        getattr(lib, name)
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != DVM_OK:
+        raise DVMError(rc, load_library().dvm_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    sweeps_fp64: int
+    rel_change: float
+    est_error: float
+    status: str
+
+
+class Solver:
+    """One context of the C ABI: n_instances problems on one velocity grid."""
+
+    def __init__(self, nv: int, n_instances: int = 1, *, precision: int = DVM_FP64,
+                 tol: float = 1e-8, max_iter: int = 200000, block_iters: int = 32,
+                 use_graphs: bool = True, vel_per_lane: int = 0,
+                 waves_per_block: int = 0, stream=None):
+        lib = load_library()
+        cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
+                         vel_per_lane, waves_per_block, None)
+        h = ctypes.c_void_p()
+        s = stream if stream is not None else _current_stream()
+        _check(lib.dvm_create(ctypes.byref(h), nv, n_instances, ctypes.byref(cfg), s))
+        self._h = h
+        self._lib = lib
+        self.nv = nv
+        self.n_instances = n_instances
+        self.shapes = [None] * n_instances
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dvm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_geometry(self, instance: int, mask, periodic_y: bool, cells_per_H: float):
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        ny, nx = m.shape
+        _check(self._lib.dvm_set_geometry(self._h, instance, nx, ny, _ptr(m),
+                                          int(periodic_y), float(cells_per_H)))
+        self.shapes[instance] = (ny, nx)
+
+    def _delta_arg(self, instance, delta):
+        if instance >= 0:
+            if np.ndim(delta) == 0:
+                return np.array([float(delta)]), 0
+            d = np.ascontiguousarray(delta, dtype=np.float64)
+            if d.shape != self.shapes[instance]:
+                raise ValueError("delta field shape does not match the geometry")
+            return d, 1
+        if all(np.ndim(d) == 0 for d in delta):
+            return np.ascontiguousarray(np.asarray(delta, dtype=np.float64)), 0
+        parts = [np.ascontiguousarray(np.broadcast_to(np.asarray(d, dtype=np.float64),
+                                                      self.shapes[i])).ravel()
+                 for i, d in enumerate(delta)]
+        return np.ascontiguousarray(np.concatenate(parts)), 1
+
+    def solve(self, instance: int, delta, alpha: float = 1.0, warm: bool = False,
+              raise_on_noconv: bool = True):
+        d, field = self._delta_arg(instance, delta)
+        n = self.n_instances if instance < 0 else 1
+        infos = (dvm_info * n)()
+        fn = self._lib.dvm_solve_warm if warm else self._lib.dvm_solve
+        rc = fn(self._h, instance, _ptr(d), field, float(alpha), infos)
+        if rc != DVM_OK and not (rc == DVM_ENOCONV and not raise_on_noconv):
+            _check(rc)
+        out = [SolveInfo(i.iters, i.sweeps_fp64, i.rel_change, i.est_error,
+                         STATUS_NAMES.get(i.status, str(i.status))) for i in infos]
+        return out if instance < 0 else out[0]
+
+    def flow_rate(self, instance: int = 0):
+        Q = ctypes.c_double()
+        ka = ctypes.c_double()
+        _check(self._lib.dvm_flow_rate(self._h, instance, ctypes.byref(Q), ctypes.byref(ka)))
+        return Q.value, ka.value
+
+    def moments(self, instance: int = 0, shear: bool = False):
+        ny, nx = self.shapes[instance]
+        out = {k: np.zeros((ny, nx)) for k in ("rho", "u1", "u2", "tau")}
+        p12 = np.zeros((ny, nx)) if shear else None
+        _check(self._lib.dvm_get_moments(self._h, instance, _ptr(out["rho"]), _ptr(out["u1"]),
+                                         _ptr(out["u2"]), _ptr(out["tau"]), _ptr(p12)))
+        if shear:
+            out["p12"] = p12
+        return out
+
+    def grad(self, instance: int = 0):
+        ny, nx = self.shapes[instance]
+        g = np.zeros((ny, nx))
+        ga = ctypes.c_double()
+        _check(self._lib.dvm_grad(self._h, instance, _ptr(g), ctypes.byref(ga)))
+        return g, ga.value
+
+
+def version() -> str:
+    return load_library().dvm_version().decode()
