@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 linearized-BGK DVM solver (one JSON line).
+
+Workload: the rough-surface channel -- a periodic cell 2H x H at 256 x 128
+cells with rectangular blocks 0.2H high over half the period on both walls,
+64 x 64 velocities of Eq. (nonuniform_v), delta in {0.1, 1, 10}.  One step is
+the whole hot path on that input: the source iteration of Eq. (iteration)
+run to the stop rule (relative change of u1, tolerance 1e-8 with the
+a-posteriori bound) for each of the three delta values, followed by the flow
+rate Q.  Inputs (geometry tables) are resident on the GPU before timing.
+
+Reported: fluid-cell x velocity updates per second over the timed steps,
+time to the converged flow rate per delta, the roofline of the dominant
+kernel (the sweep) measured with HIP events on the solver's stream, and the
+CPU oracle timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("cell×velocity updates/s + % HBM peak; "
+          "time-to-converged flow rate (1e-6) vs plain FP64")
+DELTAS = (0.1, 1.0, 10.0)
+NV = 64
+TOL = 1e-8
+FP64_VALU_PEAK = 78.6e12          # MI355X FP64 vector FLOP/s
+# arithmetic the sweep performs per fluid cell x velocity update (FMA = 2):
+# collision gain 3 FMA, upwind terms 2 x 2 FMA, combination 2 FMA,
+# reciprocal-diagonal scaling 1 MUL, quadrature moments 1 MUL + 1 ADD + 3 FMA
+FLOPS_PER_UPDATE = 6 + 8 + 4 + 1 + 8
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--precision", choices=["fp64"], default="fp64")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="budget of the CPU-oracle baseline sample")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--vel", type=int, default=0)
+    p.add_argument("--waves", type=int, default=0)
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                          "the solver has no multi-GPU path", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU available"}))
+        sys.exit(1)
+    import paper_1704_03126_amd.dvm as dvm
+    from paper_1704_03126_amd.geometry import cfg_rough_channel
+
+    g = cfg_rough_channel()
+    nf = g.n_fluid
+    K = NV * NV
+    solver = dvm.Solver(NV, 1, tol=TOL, vel_per_lane=args.vel, waves_per_block=args.waves)
+    solver.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+
+    def step():
+        its, Qs, tts = [], [], []
+        for d in DELTAS:
+            t0 = time.perf_counter()
+            info = solver.solve(0, d)
+            Q, _ = solver.flow_rate(0)
+            tts.append(time.perf_counter() - t0)
+            its.append(info.iters)
+            Qs.append(Q)
+        return its, Qs, tts
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_its, all_tts = [], []
+    for _ in range(args.steps):
+        its, Qs, tts = step()
+        all_its.append(its)
+        all_tts.append(tts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    iters = int(np.sum(all_its))
+    updates = float(iters) * nf * K
+    value = updates / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # roofline of the sweep: one more step with every sweep bracketed by HIP
+    # events on the solver's stream
+    prof = dvm.Solver(NV, 1, tol=TOL, profile=True, vel_per_lane=args.vel,
+                      waves_per_block=args.waves)
+    prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    for d in DELTAS:
+        prof.solve(0, d)
+    sweep_ms, n_sweeps, other_ms = prof.profile()
+    prof.close()
+    avg_sweep_s = sweep_ms / max(n_sweeps, 1) / 1e3
+    flops_per_launch = float(nf) * K * FLOPS_PER_UPDATE
+    achieved = flops_per_launch / avg_sweep_s
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
+                "kernel": "k_sweep<double>", "avg_launch_ms": avg_sweep_s * 1e3,
+                "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": nf * K,
+                "sweep_share_of_iteration": sweep_ms / max(sweep_ms + other_ms, 1e-30)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(g, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
+                   "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
+                   "deltas": list(DELTAS), "tol": TOL, "precision": "fp64",
+                   "parallelism": "single_gpu"},
+        "iterations_per_delta": all_its[-1],
+        "time_to_solution_s": dict(zip([str(d) for d in DELTAS],
+                                       np.mean(np.array(all_tts), axis=0).tolist())),
+        "Q": dict(zip([str(d) for d in DELTAS], Qs)),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    solver.close()
+    print(json.dumps(out))
+
+
+def cpu_baseline(g, budget_s):
+    """The CPU oracle (FP64 source iteration) on a bounded sample of the same
+    workload: full geometry and velocity grid, a fixed number of iterations
+    scaled to take about `budget_s` seconds."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.si_solve(g.mask, 1.0, NV, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
+                    tol=-1.0, max_iter=1)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.si_solve(g.mask, 1.0, NV, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
+                    tol=-1.0, max_iter=n)
+    dt = time.perf_counter() - t0
+    ups = n * g.n_fluid * NV * NV / dt
+    return {"value": ups, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} source iterations of the full workload at delta=1 "
+                      f"({g.nx}x{g.ny} cells, {NV}x{NV} velocities), {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -69,6 +69,9 @@ typedef struct {
     int vel_per_lane;       /* 0 = autotune, else 4 or 8 velocities per lane  */
     int waves_per_block;    /* 0 = autotune, else 4 or 8                      */
     const char *tune_cache; /* autotune cache file or NULL (in-memory only)   */
+    int profile;            /* 1: time every sweep launch with HIP events on
+                               the context's stream (replaces graph replay);
+                               read the totals with dvm_profile              */
 } dvm_config;
 
 /* Per-instance result of dvm_solve. */
@@ -139,6 +142,12 @@ int dvm_get_moments(const dvm_ctx *ctx, int instance, double *rho, double *u1,
  * to the accommodation coefficient, at the converged state of the last
  * dvm_solve of this instance.  Either output may be NULL. */
 int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha);
+
+/* Kernel timings gathered while cfg.profile == 1, since the previous call:
+ * total milliseconds spent in sweep launches and their count, and total
+ * milliseconds of the other kernels of the iterations (moments, record,
+ * stop rule).  Resets the totals.  Any output may be NULL. */
+int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms);
 
 /* Release every resource of the context (NULL is ignored). */
 void dvm_destroy(dvm_ctx *ctx);

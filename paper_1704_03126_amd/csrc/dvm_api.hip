@@ -98,10 +98,19 @@ struct dvm_ctx {
     int graph_iters = 0;
     bool graph_field = false;
 
+    // profiling (cfg.profile): event pairs around sweep launches
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_other;
+    size_t ev_next = 0;
+    double prof_sweep_ms = 0.0, prof_other_ms = 0.0;
+    long prof_sweeps = 0;
+
     ~dvm_ctx()
     {
         if (graph)
             (void)hipGraphExecDestroy(graph);
+        for (auto e : ev_pool)
+            (void)hipEventDestroy(e);
         d_inst.release(); d_items.release(); d_codes.release(); d_rec.release();
         d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release();
         d_u1prev.release(); d_seam.release(); d_wrap.release(); d_aux.release();
@@ -297,7 +306,7 @@ static int build_layout(dvm_ctx *c)
         InstDev &d = c->idev[i];
         d.nx = h.nx;
         d.ny = h.ny;
-        d.tp = h.nx >= 4 ? h.nx : 64;
+        d.tp = h.nx >= WRAP_MIN ? h.nx : h.nx + 63;
         strip_layout(h.ny, d.nstrips, d.strip_h);
         d.periodic_y = h.periodic_y;
         d.cell_off = cell;
@@ -436,20 +445,68 @@ static bool any_field(const dvm_ctx *c)
     return false;
 }
 
+static int next_event(dvm_ctx *c, hipEvent_t *e)
+{
+    if (c->ev_next == c->ev_pool.size()) {
+        hipEvent_t n;
+        HIPCHK(hipEventCreate(&n));
+        c->ev_pool.push_back(n);
+    }
+    *e = c->ev_pool[c->ev_next++];
+    return DVM_OK;
+}
+
+// Fold the recorded event pairs into the totals (the stream is idle).
+static int collect_profile(dvm_ctx *c)
+{
+    for (auto &p : c->ev_sweep) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+        c->prof_sweep_ms += ms;
+        ++c->prof_sweeps;
+    }
+    for (auto &p : c->ev_other) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+        c->prof_other_ms += ms;
+    }
+    c->ev_sweep.clear();
+    c->ev_other.clear();
+    c->ev_next = 0;
+    return DVM_OK;
+}
+
 // One source iteration for every active instance.
 static int enqueue_iteration(dvm_ctx *c)
 {
+    const bool prof = c->cfg.profile != 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (prof) {
+        int rc = next_event(c, &e0);
+        if (!rc) rc = next_event(c, &e1);
+        if (!rc) rc = next_event(c, &e2);
+        if (rc)
+            return rc;
+        HIPCHK(hipEventRecord(e0, c->stream));
+    }
     HIPCHK(launch_sweep<double>(sweep_args(c, 0), (int)c->items.size(), c->V, c->G, any_field(c),
                                 false, c->stream));
+    if (prof)
+        HIPCHK(hipEventRecord(e1, c->stream));
     HIPCHK(launch_moments(mom_args(c), c->max_cells, c->n_inst, c->stream));
     HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
     HIPCHK(launch_status(c->d_st.p, c->n_inst, c->cfg.tol, c->cfg.max_iter, c->stream));
+    if (prof) {
+        HIPCHK(hipEventRecord(e2, c->stream));
+        c->ev_sweep.emplace_back(e0, e1);
+        c->ev_other.emplace_back(e1, e2);
+    }
     return DVM_OK;
 }
 
 static int enqueue_block(dvm_ctx *c, int iters)
 {
-    if (!c->cfg.use_graphs) {
+    if (!c->cfg.use_graphs || c->cfg.profile) {
         for (int i = 0; i < iters; ++i) {
             int rc = enqueue_iteration(c);
             if (rc)
@@ -590,6 +647,7 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
             s.npass = 0;
             s.eps_prev = 0.0;
             s.maxdiff_bits = s.maxabs_bits = 0ull;
+            s.iter0 = s.iter;
             iter0[i] = s.iter;
         } else {
             s.active = 0;
@@ -618,6 +676,11 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
         HIPCHK(hipMemcpyAsync(st.data(), c->d_st.p, c->n_inst * sizeof(SolveState),
                               hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->cfg.profile) {
+            int prc = collect_profile(c);
+            if (prc)
+                return prc;
+        }
         bool running = false;
         for (int i = i0; i < i1; ++i) {
             if (st[i].active && st[i].iter - iter0[i] < cap)
@@ -841,6 +904,21 @@ int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha)
     (void)dQ_ddelta;
     (void)dQ_dalpha;
     return fail(DVM_ESTATE, "the adjoint is not available in this build");
+}
+
+int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms)
+{
+    if (!ctx)
+        return fail(DVM_EINVAL, "context is NULL");
+    if (sweep_ms)
+        *sweep_ms = ctx->prof_sweep_ms;
+    if (n_sweeps)
+        *n_sweeps = ctx->prof_sweeps;
+    if (other_ms)
+        *other_ms = ctx->prof_other_ms;
+    ctx->prof_sweep_ms = ctx->prof_other_ms = 0.0;
+    ctx->prof_sweeps = 0;
+    return DVM_OK;
 }
 
 void dvm_destroy(dvm_ctx *ctx)

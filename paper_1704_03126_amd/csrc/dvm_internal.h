@@ -34,7 +34,7 @@ enum { STATUS_RUNNING = 0, STATUS_CONVERGED = 1, STATUS_MAXITER = 2, STATUS_DIVE
 
 struct InstDev {
     int nx, ny;
-    int tp;          // schedule period of a strip pass (nx, or 64 when nx == 1)
+    int tp;          // steps of a strip pass: nx (wrap-around) or nx + 63 (skewed)
     int nstrips;
     int strip_h;     // rows per strip (last strip may be shorter, >= 2)
     int periodic_y;
@@ -53,8 +53,12 @@ struct WorkItem {
     int inst, strip, group, pad;
 };
 
+// grids at least this wide use the wrap-around diagonal schedule
+enum { WRAP_MIN = 8 };
+
 struct SolveState {
     long long iter;       // completed iterations
+    long long iter0;      // iterations completed before the current solve
     int status;
     int npass;
     int active;

@@ -11,7 +11,10 @@
 //             previous results (x direction) and the results of lanes l-1,
 //             l-2 one and two steps earlier (y direction, moved with DPP
 //             wave_shr).  Each lane carries V velocities at once; velocity
-//             constants are wave-uniform.  The perturbation h is never
+//             constants are wave-uniform.  Grids narrower than WRAP_MIN
+//             use a skewed schedule without wrap-around (lane l treats x at
+//             step x + l), which lags only the periodic seam.  The
+//             perturbation h is never
 //             written to memory: the lane accumulates the quadrature moments
 //             of its V velocities, the G waves of the group add theirs in
 //             LDS, and the group writes one partial per cell.  Values that
@@ -175,6 +178,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                 acc[m] = 0.0;
             if (t < nsteps) {
                 const int cl = strip_cell(in, y0, hs, xpos, ypos, t, lane);
+                const bool xact = wrap_mod(t - lane, in.tp) < in.nx;
                 const long long cg = cbase + (cl < 0 ? 0 : cl);
                 const int code = cl < 0 ? 0xFF : a.codes[cg];
                 const int cxc = (code >> (2 * dxs)) & 3;
@@ -241,9 +245,17 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                         acc[3] = fma((double)qq, hw, acc[3]);
                     }
                     hout[v] = h;
-                    hs1p[v] = hS1;
-                    prev2[v] = prev1[v];
-                    prev1[v] = h;
+                    if (in.tp == in.nx) {
+                        hs1p[v] = hS1;
+                        prev2[v] = prev1[v];
+                        prev1[v] = h;
+                    } else {
+                        // skewed schedule: outside its window of the pass a
+                        // lane keeps the results it will need next
+                        hs1p[v] = xact ? hS1 : hs1p[v];
+                        prev2[v] = xact ? prev1[v] : prev2[v];
+                        prev1[v] = xact ? h : prev1[v];
+                    }
                 }
                 // the top two rows of the strip feed the next strip next iteration
                 if (!FINAL && has_down && cl >= 0 && lane >= hs - 2) {
@@ -444,7 +456,9 @@ __global__ void k_status(SolveState *st, int n, double tol, long long max_iter)
     s.maxabs_bits = 0ull;
     s.iter += 1;
     double eps = amax > 0.0 ? dmax / amax : (dmax == 0.0 ? 0.0 : __builtin_inf());
-    if (!(amax < __builtin_inf()) || eps != eps) {
+    // iterates of this linear problem are O(delta) at most; values beyond
+    // 1e30 (or non-finite) mean the lagged iteration is amplifying errors
+    if (!(amax < 1e30) || eps != eps) {
         s.status = STATUS_DIVERGED;
         s.active = 0;
         s.eps = eps;
@@ -469,7 +483,7 @@ __global__ void k_status(SolveState *st, int n, double tol, long long max_iter)
     if (s.npass >= 3) {
         s.status = STATUS_CONVERGED;
         s.active = 0;
-    } else if (s.iter >= max_iter) {
+    } else if (s.iter - s.iter0 >= max_iter) {
         s.status = STATUS_MAXITER;
         s.active = 0;
     }

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "running", 1: "converged", 2: "max_iter", 3: "diverged"}
 
 EXPORTED = ("dvm_create", "dvm_set_geometry", "dvm_solve", "dvm_solve_warm",
             "dvm_flow_rate", "dvm_get_moments", "dvm_grad", "dvm_destroy",
-            "dvm_last_error", "dvm_version")
+            "dvm_last_error", "dvm_version", "dvm_profile")
 
 
 class DVMError(RuntimeError):
@@ -42,7 +42,8 @@ class dvm_config(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_long), ("block_iters", ctypes.c_int),
                 ("use_graphs", ctypes.c_int), ("vel_per_lane", ctypes.c_int),
-                ("waves_per_block", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+                ("waves_per_block", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
+                ("profile", ctypes.c_int)]
 
 
 class dvm_info(ctypes.Structure):
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(ctypes.c_double)]
     lib.dvm_get_moments.argtypes = [P, ctypes.c_int, P, P, P, P, P]
     lib.dvm_grad.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double)]
+    lib.dvm_profile.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long),
+                                ctypes.POINTER(ctypes.c_double)]
     lib.dvm_destroy.argtypes = [P]
     lib.dvm_destroy.restype = None
     lib.dvm_last_error.restype = ctypes.c_char_p
@@ -118,10 +121,10 @@ class Solver:
     def __init__(self, nv: int, n_instances: int = 1, *, precision: int = DVM_FP64,
                  tol: float = 1e-8, max_iter: int = 200000, block_iters: int = 32,
                  use_graphs: bool = True, vel_per_lane: int = 0,
-                 waves_per_block: int = 0, stream=None):
+                 waves_per_block: int = 0, profile: bool = False, stream=None):
         lib = load_library()
         cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
-                         vel_per_lane, waves_per_block, None)
+                         vel_per_lane, waves_per_block, None, int(profile))
         h = ctypes.c_void_p()
         s = stream if stream is not None else _current_stream()
         _check(lib.dvm_create(ctypes.byref(h), nv, n_instances, ctypes.byref(cfg), s))
@@ -189,6 +192,12 @@ class Solver:
         if shear:
             out["p12"] = p12
         return out
+
+    def profile(self):
+        """(sweep_ms_total, n_sweeps, other_ms_total) since the last call."""
+        sm, n, om = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
+        _check(self._lib.dvm_profile(self._h, ctypes.byref(sm), ctypes.byref(n), ctypes.byref(om)))
+        return sm.value, n.value, om.value
 
     def grad(self, instance: int = 0):
         ny, nx = self.shapes[instance]

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def _ctx(lib, nv=8, n=1, **kw):
     cfg = dvm.dvm_config(kw.get("precision", 0), kw.get("tol", 1e-8), kw.get("max_iter", 1000),
-                         kw.get("block_iters", 0), 1, kw.get("vel", 0), kw.get("waves", 0), None)
+                         kw.get("block_iters", 0), 1, kw.get("vel", 0), kw.get("waves", 0), None, 0)
     h = ctypes.c_void_p()
     rc = lib.dvm_create(ctypes.byref(h), nv, n, ctypes.byref(cfg), None)
     return rc, h
