@@ -90,8 +90,11 @@ struct dvm_ctx {
 
     DevBuf<InstDev> d_inst;
     DevBuf<WorkItem> d_items;
-    DevBuf<uint8_t> d_codes;
-    DevBuf<double> d_rec, d_vt, d_dfield, d_part, d_mom, d_u1prev, d_seam, d_wrap, d_aux;
+    DevBuf<uint8_t> d_codes, d_scode;
+    DevBuf<int> d_smap;
+    DevBuf<long long> d_spos;
+    DevBuf<double> d_srec, d_vt, d_dfield, d_part, d_mom, d_u1prev, d_seam, d_wrap, d_aux;
+    long long sk_total = 0;
     DevBuf<SolveState> d_st;
 
     hipGraphExec_t graph = nullptr;
@@ -111,7 +114,8 @@ struct dvm_ctx {
             (void)hipGraphExecDestroy(graph);
         for (auto e : ev_pool)
             (void)hipEventDestroy(e);
-        d_inst.release(); d_items.release(); d_codes.release(); d_rec.release();
+        d_inst.release(); d_items.release(); d_codes.release(); d_srec.release();
+        d_scode.release(); d_smap.release(); d_spos.release();
         d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release();
         d_u1prev.release(); d_seam.release(); d_wrap.release(); d_aux.release();
         d_st.release();
@@ -299,7 +303,7 @@ static int build_layout(dvm_ctx *c)
     c->kp4 = 4 * c->kq;
     c->idev.assign(c->n_inst, InstDev{});
     c->items.clear();
-    long long cell = 0, seam = 0, wrap = 0;
+    long long cell = 0, seam = 0, wrap = 0, sk = 0;
     int maxc = 0;
     for (int i = 0; i < c->n_inst; ++i) {
         const HostInst &h = c->inst[i];
@@ -312,6 +316,7 @@ static int build_layout(dvm_ctx *c)
         d.cell_off = cell;
         d.seam_off = seam;
         d.wrap_off = wrap;
+        d.sk_off = sk;
         d.inv_dx = h.cph;
         d.delta = 1.0;
         d.alpha = 1.0;
@@ -319,6 +324,7 @@ static int build_layout(dvm_ctx *c)
         cell += (long long)h.nx * h.ny;
         seam += (long long)d.nstrips * h.nx * 2 * c->kp4;
         wrap += (long long)d.nstrips * c->kp4 * 64 * 3;
+        sk += 4ll * d.nstrips * d.tp * 64;
         maxc = std::max(maxc, h.nx * h.ny);
         for (int s = 0; s < d.nstrips; ++s)
             for (int g = 0; g < 4 * c->gq; ++g)
@@ -331,12 +337,16 @@ static int build_layout(dvm_ctx *c)
     c->ncell = cell;
     c->seam_half = seam;
     c->wrap_total = wrap;
+    c->sk_total = sk;
     c->max_cells = maxc;
 
     HIPCHK(c->d_inst.alloc(c->n_inst));
     HIPCHK(c->d_items.alloc(c->items.size()));
     HIPCHK(c->d_codes.alloc(cell));
-    HIPCHK(c->d_rec.alloc(cell * REC_STRIDE));
+    HIPCHK(c->d_srec.alloc(sk * REC_STRIDE));
+    HIPCHK(c->d_scode.alloc(sk));
+    HIPCHK(c->d_smap.alloc(sk));
+    HIPCHK(c->d_spos.alloc(cell * 4));
     HIPCHK(c->d_vt.alloc((size_t)c->n_inst * c->kp4 * VT_STRIDE));
     HIPCHK(c->d_dfield.alloc(cell));
     HIPCHK(c->d_part.alloc((size_t)4 * c->gq * cell * 4));
@@ -368,7 +378,45 @@ static int build_layout(dvm_ctx *c)
                 e[VT_CY] = std::fabs(eta) * h.cph;
             }
     }
+    // skewed sweep order of every (instance, quadrant, strip): lane l treats
+    // x_r = (t - l) mod tp at step t, rows run away from the upwind side
+    std::vector<uint8_t> scode(sk, 0x1F);
+    std::vector<int> smap(sk, -1);
+    std::vector<long long> spos(cell * 4, -1);
+    for (int i = 0; i < c->n_inst; ++i) {
+        const HostInst &h = c->inst[i];
+        const InstDev &d = c->idev[i];
+        for (int q = 0; q < 4; ++q) {
+            const bool xpos = (q & 1) == 0, ypos = (q & 2) == 0;
+            const int dxs = xpos ? SIDE_W : SIDE_E, dys = ypos ? SIDE_S : SIDE_N;
+            for (int st = 0; st < d.nstrips; ++st) {
+                const int y0 = st * d.strip_h;
+                const int hs = std::min(d.strip_h, d.ny - y0);
+                for (int t = 0; t < d.tp; ++t)
+                    for (int l = 0; l < 64; ++l) {
+                        const long long e = d.sk_off + (((long long)q * d.nstrips + st) * d.tp + t) * 64 + l;
+                        const int xr = ((t - l) % d.tp + d.tp) % d.tp;
+                        if (l >= hs || xr >= d.nx)
+                            continue;
+                        const int x = xpos ? xr : d.nx - 1 - xr;
+                        const int row = ypos ? y0 + l : y0 + hs - 1 - l;
+                        const int cl = row * d.nx + x;
+                        smap[e] = cl;
+                        const uint8_t code = h.codes[cl];
+                        if (code != 0xFF) {
+                            scode[e] = (uint8_t)(((code >> (2 * dxs)) & 3) | (((code >> (2 * dys)) & 3) << 2));
+                            spos[(d.cell_off + cl) * 4 + q] = e;
+                        }
+                    }
+            }
+        }
+    }
     HIPCHK(hipMemcpyAsync(c->d_codes.p, codes.data(), cell, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_scode.p, scode.data(), sk, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_smap.p, smap.data(), sk * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_spos.p, spos.data(), spos.size() * sizeof(long long), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(launch_zero(c->d_srec.p, c->d_srec.n, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_vt.p, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_items.p, c->items.data(), c->items.size() * sizeof(WorkItem),
                           hipMemcpyHostToDevice, c->stream));
@@ -389,8 +437,9 @@ static SweepArgs<double> sweep_args(dvm_ctx *c, int force)
     SweepArgs<double> a{};
     a.inst = c->d_inst.p;
     a.items = c->d_items.p;
-    a.codes = c->d_codes.p;
-    a.rec = c->d_rec.p;
+    a.srec = c->d_srec.p;
+    a.scode = c->d_scode.p;
+    a.smap = c->d_smap.p;
     a.vtab = c->d_vt.p;
     a.delta_field = c->d_dfield.p;
     a.part = c->d_part.p;
@@ -427,7 +476,8 @@ static RecArgs<double> rec_args(dvm_ctx *c)
     a.mom = c->d_mom.p;
     a.delta_field = c->d_dfield.p;
     a.u1prev = c->d_u1prev.p;
-    a.rec = c->d_rec.p;
+    a.srec = c->d_srec.p;
+    a.spos = c->d_spos.p;
     a.st = c->d_st.p;
     a.m0 = c->m0;
     a.m2 = c->m2;

@@ -20,8 +20,11 @@ enum { NSTENCIL = 5, STENCIL_SOLID = 4 };
 // by quadrant (q = 0: xi>0,eta>0; 1: xi<0,eta>0; 2: xi>0,eta<0; 3: both <0)
 enum { VT_XI = 0, VT_ETA = 1, VT_Q = 2, VT_W = 3, VT_CX = 4, VT_CY = 5, VT_STRIDE = 8 };
 
-// per-cell record read by the sweep: b0..b3 (delta times the collision gain
-// coefficients, drive included in b1) and the value leaving each wall face
+// record read by the sweep, one per (quadrant, strip, step, lane) entry in
+// that quadrant's sweep order: b0..b3 (delta times the collision gain
+// coefficients, drive included in b1), the values leaving the wall faces on
+// the x and y upwind sides, delta, pad.  The per-entry code byte holds the x
+// and y stencil codes (bits 0-1, 2-3) and a no-cell flag (bit 4).
 enum { REC_STRIDE = 8 };
 
 // per-cell moments written by k_moments
@@ -43,6 +46,7 @@ struct InstDev {
     long long cell_off;   // first cell of this instance in the cell arrays
     long long seam_off;   // offset in one parity half of the seam buffer
     long long wrap_off;   // offset in the wrap-state buffer
+    long long sk_off;     // first skewed entry: 4 quadrants x nstrips x tp x 64
     double delta;         // uniform delta (field == 0)
     double alpha;         // accommodation coefficient
     double drive;         // coefficient of the pressure-gradient source
@@ -71,8 +75,9 @@ template <typename T>
 struct SweepArgs {
     const InstDev *inst;
     const WorkItem *items;
-    const uint8_t *codes;
-    const T *rec;
+    const T *srec;            // skewed records [entry][REC_STRIDE]
+    const uint8_t *scode;     // skewed stencil codes [entry]
+    const int *smap;          // skewed entry -> cell of the instance, -1 none
     const T *vtab;            // [inst][kp4][VT_STRIDE]
     const double *delta_field;
     double *part;             // [group][ncell][4]   (final pass: [group][ncell])
@@ -104,7 +109,8 @@ struct RecArgs {
     const double *mom;
     const double *delta_field;
     double *u1prev;
-    T *rec;
+    T *srec;
+    const long long *spos;    // [cell][quadrant] -> skewed entry
     SolveState *st;
     double m0, m2, c2, c4, D;
 };

@@ -76,30 +76,38 @@ __device__ __forceinline__ int wrap_mod(int a, int n)
     return r < 0 ? r + n : r;
 }
 
-// Cell handled by lane `l` at step `t` of a strip pass.  Returns -1 when the
-// lane has no cell at that step (beyond the strip, or x outside the grid when
-// the schedule period exceeds nx).
-__device__ __forceinline__ int strip_cell(const InstDev &in, int y0, int hs,
-                                          bool xpos, bool ypos, int t, int l)
+// ------------------------------------------------------------------- sweep
+// Velocity constants are read through the constant address space so that the
+// compiler keeps them on the scalar path (they are wave-uniform).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ T ldc(cptr<T> p, int i)
 {
-    if (l >= hs)
-        return -1;
-    int xr = wrap_mod(t - l, in.tp);
-    if (xr >= in.nx)
-        return -1;
-    int x = xpos ? xr : in.nx - 1 - xr;
-    int row = ypos ? y0 + l : y0 + hs - 1 - l;
-    return row * in.nx + x;
+    return p[i];
 }
 
-// ------------------------------------------------------------------- sweep
+// Steps of a pass staged per chunk; sized so that the staging buffers and the
+// per-wave moment partials fit the LDS of one workgroup.
+template <typename T, int G>
+struct SweepChunk {
+    static constexpr int C = (G >= 16) ? 2 : 4;
+};
+
 template <typename T, int V, int G, bool FIELD, bool FINAL>
 __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
 {
-    constexpr int S = 2;                 // steps per moment flush
-    constexpr int NM = FINAL ? 1 : 4;    // moments accumulated
-    __shared__ double lds_part[2][S][G][64][NM];
-    __shared__ T lds_rinv[G * V][NSTENCIL];
+    constexpr int C = SweepChunk<T, G>::C;     // steps per chunk
+    constexpr int NM = FINAL ? 1 : 4;          // moments accumulated
+    constexpr int P = G * V;                   // velocities of the group
+    constexpr int UPE = 8 * sizeof(T) / 16;    // 16-byte units per record
+    __shared__ __attribute__((aligned(16))) T st_rec[2][C][64][8];
+    __shared__ uint8_t st_code[2][C][64];
+    __shared__ int st_cell[2][C][64];
+    __shared__ T st_seam[2][C][2][P];
+    __shared__ double lds_part[C][G][64][NM];
+    __shared__ T lds_rinv[P][NSTENCIL];
     __shared__ T lds_pq[4][2];
 
     const WorkItem it = a.items[blockIdx.x];
@@ -112,25 +120,28 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = it.group / a.gq;
     const bool xpos = (q & 1) == 0, ypos = (q & 2) == 0;
-    const int dxs = xpos ? SIDE_W : SIDE_E;     // side the flow comes from
-    const int dys = ypos ? SIDE_S : SIDE_N;
-    const int kq0 = q * a.kq + (it.group % a.gq) * (G * V);   // first velocity
-    const int kw = kq0 + wave * V;                              // this wave's
-    const T *__restrict__ vt = a.vtab + (size_t)it.inst * a.kp4 * VT_STRIDE;
+    const int kq0 = q * a.kq + (it.group % a.gq) * P;   // first velocity of the group
+    const int kw = kq0 + wave * V;                      // first velocity of this wave
+    cptr<T> vt = (cptr<T>)(a.vtab + (size_t)it.inst * a.kp4 * VT_STRIDE);
 
     const int y0 = it.strip * in.strip_h;
     const int hs = min(in.strip_h, in.ny - y0);
     const long long iter = a.st[it.inst].iter;
     const int par_w = (int)(iter & 1), par_r = par_w ^ 1;
+    const int tp = in.tp, nx = in.nx;
+    // skewed entries of this (quadrant, strip): entry (t, lane)
+    const size_t ebase = (size_t)in.sk_off + ((size_t)(q * in.nstrips + it.strip) * tp) * 64;
+    const T *__restrict__ srec = a.srec + ebase * 8;
+    const uint8_t *__restrict__ scode = a.scode + ebase;
+    const int *__restrict__ smap = a.smap + ebase;
 
-    // per-group tables in LDS: reciprocal diagonals and stencil weights
     if (!FIELD) {
-        for (int e = tid; e < G * V * NSTENCIL; e += 64 * G) {
-            int v = e / NSTENCIL, ci = e % NSTENCIL;
-            const T *c = vt + (size_t)(kq0 + v) * VT_STRIDE;
-            T cx = c[VT_CX], cy = c[VT_CY], w = c[VT_W];
-            T ax = (ci & 2) ? T(1) : T(1.5), ay = (ci & 1) ? T(1) : T(1.5);
-            T den = T(in.delta) + ax * cx + ay * cy;
+        for (int e = tid; e < P * NSTENCIL; e += 64 * G) {
+            const int v = e / NSTENCIL, ci = e % NSTENCIL;
+            const T cx = vt[(kq0 + v) * VT_STRIDE + VT_CX], cy = vt[(kq0 + v) * VT_STRIDE + VT_CY];
+            const T w = vt[(kq0 + v) * VT_STRIDE + VT_W];
+            const T ax = (ci & 2) ? T(1) : T(1.5), ay = (ci & 1) ? T(1) : T(1.5);
+            const T den = T(in.delta) + ax * cx + ay * cy;
             lds_rinv[v][ci] = (ci == STENCIL_SOLID || w == T(0) || den == T(0)) ? T(0) : T(1) / den;
         }
     }
@@ -138,26 +149,91 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         lds_pq[tid][0] = tid == CODE_INT ? T(2) : (tid == CODE_NEAR ? T(1.5) : T(0));
         lds_pq[tid][1] = tid == CODE_INT ? T(-0.5) : T(0);
     }
-    __syncthreads();
 
-    // the strip upstream of this one (values lagged by one iteration)
     const bool has_up = ypos ? (it.strip > 0 || in.periodic_y)
                              : (it.strip < in.nstrips - 1 || in.periodic_y);
-    const int s_up = ypos ? (it.strip + in.nstrips - 1) % in.nstrips
-                          : (it.strip + 1) % in.nstrips;
+    const int s_up = ypos ? (it.strip + in.nstrips - 1) % in.nstrips : (it.strip + 1) % in.nstrips;
     const bool has_down = ypos ? (it.strip < in.nstrips - 1 || in.periodic_y)
                                : (it.strip > 0 || in.periodic_y);
-    const size_t seam_row = (size_t)2 * a.kp4;   // values per x position
-    const T *seam_in = a.seam + (size_t)par_r * a.seam_half + in.seam_off +
-                       (size_t)s_up * in.nx * seam_row;
-    T *seam_out = a.seam + (size_t)par_w * a.seam_half + in.seam_off +
-                  (size_t)it.strip * in.nx * seam_row;
-    const bool x_coupled = in.nx > 1;
+    const size_t seam_row = (size_t)2 * a.kp4;
+    const T *seam_in = a.seam + (size_t)par_r * a.seam_half + in.seam_off + (size_t)s_up * nx * seam_row;
+    T *seam_out = a.seam + (size_t)par_w * a.seam_half + in.seam_off + (size_t)it.strip * nx * seam_row;
+    const bool x_coupled = nx > 1;
+
+    // ---- staging of one chunk of steps into LDS buffer b (global loads are
+    //      issued into registers first, stored after the current chunk)
+    constexpr int REC_UNITS = C * 64 * UPE;
+    constexpr int RU_PER_T = (REC_UNITS + 64 * G - 1) / (64 * G);
+    constexpr int SEAM_VALS = C * 2 * P;
+    constexpr int SV_PER_T = (SEAM_VALS + 64 * G - 1) / (64 * G);
+    constexpr int CC_PER_T = (C * 64 + 64 * G - 1) / (64 * G);
+    uint4 ru[RU_PER_T];
+    T sv[SV_PER_T];
+    int cc[CC_PER_T];
+    uint8_t cb[CC_PER_T];
+    auto issue = [&](int c) {
+        const int t0 = c * C;
+#pragma unroll
+        for (int r = 0; r < RU_PER_T; ++r) {
+            const int u = tid + r * 64 * G;
+            ru[r] = make_uint4(0, 0, 0, 0);
+            if (u < REC_UNITS) {
+                const int e = u / UPE;             // entry within chunk: s * 64 + lane
+                if (t0 + e / 64 < tp)
+                    ru[r] = reinterpret_cast<const uint4 *>(srec + ((size_t)t0 * 64) * 8)[u];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < CC_PER_T; ++r) {
+            const int e = tid + r * 64 * G;
+            cc[r] = -1;
+            cb[r] = 0x1F;
+            if (e < C * 64 && t0 + e / 64 < tp) {
+                cc[r] = smap[(size_t)t0 * 64 + e];
+                cb[r] = scode[(size_t)t0 * 64 + e];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < SV_PER_T; ++r) {
+            const int e = tid + r * 64 * G;       // (s, slot, j)
+            sv[r] = T(0);
+            if (e < SEAM_VALS && has_up) {
+                const int sidx = e / (2 * P), slot = (e / P) & 1, j = e % P;
+                const int t = t0 + sidx;
+                const int xr = t < tp ? t : tp;   // lane 0 treats xr = t
+                if (xr < nx) {
+                    const int x0 = xpos ? xr : nx - 1 - xr;
+                    sv[r] = seam_in[(size_t)x0 * seam_row + (size_t)slot * a.kp4 + kq0 + j];
+                }
+            }
+        }
+    };
+    auto commit = [&](int b) {
+#pragma unroll
+        for (int r = 0; r < RU_PER_T; ++r) {
+            const int u = tid + r * 64 * G;
+            if (u < REC_UNITS)
+                reinterpret_cast<uint4 *>(&st_rec[b][0][0][0])[u] = ru[r];
+        }
+#pragma unroll
+        for (int r = 0; r < CC_PER_T; ++r) {
+            const int e = tid + r * 64 * G;
+            if (e < C * 64) {
+                (&st_cell[b][0][0])[e] = cc[r];
+                (&st_code[b][0][0])[e] = cb[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < SV_PER_T; ++r) {
+            const int e = tid + r * 64 * G;
+            if (e < SEAM_VALS)
+                (&st_seam[b][0][0][0])[e] = sv[r];
+        }
+    };
 
     // wrap-around state: this lane's last two results and the last y-upstream
     T prev1[V], prev2[V], hs1p[V];
-    T *wrapp = a.wrap + in.wrap_off +
-               (((size_t)it.strip * (a.kp4 / V) + kw / V) * 64 + lane) * (3 * V);
+    T *wrapp = a.wrap + in.wrap_off + (((size_t)it.strip * (a.kp4 / V) + kw / V) * 64 + lane) * (3 * V);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         prev1[v] = x_coupled ? wrapp[v] : T(0);
@@ -166,63 +242,49 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     }
 
     const long long cbase = in.cell_off;
-    const int nsteps = in.tp;
-    double acc[NM];
-    int buf = 0;
-    for (int t0 = 0; t0 < nsteps; t0 += S) {
+    const int nchunks = (tp + C - 1) / C;
+    issue(0);
+    commit(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int b = c & 1;
+        if (c + 1 < nchunks)
+            issue(c + 1);
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int t = t0 + s;
+        for (int s = 0; s < C; ++s) {
+            const int t = c * C + s;
+            double acc[NM];
 #pragma unroll
             for (int m = 0; m < NM; ++m)
                 acc[m] = 0.0;
-            if (t < nsteps) {
-                const int cl = strip_cell(in, y0, hs, xpos, ypos, t, lane);
-                const bool xact = wrap_mod(t - lane, in.tp) < in.nx;
-                const long long cg = cbase + (cl < 0 ? 0 : cl);
-                const int code = cl < 0 ? 0xFF : a.codes[cg];
-                const int cxc = (code >> (2 * dxs)) & 3;
-                const int cyc = (code >> (2 * dys)) & 3;
-                const T *rec = a.rec + cg * REC_STRIDE;
-                T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
-                T gx = rec[4 + dxs], gy = rec[4 + dys];
-                T px = lds_pq[cxc][0], qx = lds_pq[cxc][1];
-                T py = lds_pq[cyc][0], qy = lds_pq[cyc][1];
-                const int ci = code == 0xFF ? STENCIL_SOLID
-                                            : ((cxc == CODE_WALL) ? 2 : 0) + ((cyc == CODE_WALL) ? 1 : 0);
+            if (t < tp) {
+                const T *rec = &st_rec[b][s][lane][0];
+                const int code = st_code[b][s][lane];
+                const int cxc = code & 3, cyc = (code >> 2) & 3;
+                const bool solid = (code >> 4) != 0;
+                const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
+                const T gx = rec[4], gy = rec[5];
+                const T px = lds_pq[cxc][0], qx = lds_pq[cxc][1];
+                const T py = lds_pq[cyc][0], qy = lds_pq[cyc][1];
+                const int ci = solid ? STENCIL_SOLID : ((cxc == CODE_WALL) ? 2 : 0) + ((cyc == CODE_WALL) ? 1 : 0);
                 T dl = T(0), ax = T(0), ay = T(0);
                 if (FIELD) {
-                    dl = T(a.delta_field[cg]);
+                    dl = rec[6];
                     ax = (cxc == CODE_WALL) ? T(1) : T(1.5);
                     ay = (cyc == CODE_WALL) ? T(1) : T(1.5);
                 }
-                if (code == 0xFF) {
-                    b0 = b1 = b2 = b3 = gx = gy = T(0);
-                }
-                // lagged rows of the upstream strip for lane 0
-                T sm1[V], sm2[V];
-                const int x0 = xpos ? wrap_mod(t, in.tp) : in.nx - 1 - wrap_mod(t, in.tp);
-                if (has_up && lane == 0 && wrap_mod(t, in.tp) < in.nx) {
-                    const T *sp = seam_in + (size_t)x0 * seam_row;
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        sm2[v] = sp[kw + v];
-                        sm1[v] = sp[a.kp4 + kw + v];
-                    }
-                } else {
-#pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        sm1[v] = sm2[v] = T(0);
-                }
+                const bool xact = (t - lane >= 0 ? (t - lane) % tp : (t - lane) % tp + tp) < nx;
                 T hout[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const T *c = vt + (size_t)(kw + v) * VT_STRIDE;
-                    const T xi = c[VT_XI], eta = c[VT_ETA], qq = c[VT_Q];
-                    const T cx = c[VT_CX], cy = c[VT_CY];
-                    const double w = (double)c[VT_W];
-                    const T hS1 = dpp_shr1(sm1[v], prev1[v]);
-                    const T hS2 = dpp_shr1(sm2[v], hs1p[v]);
+                    const int k = (kw + v) * VT_STRIDE;
+                    const T xi = ldc(vt, k + VT_XI), eta = ldc(vt, k + VT_ETA), qq = ldc(vt, k + VT_Q);
+                    const T cx = ldc(vt, k + VT_CX), cy = ldc(vt, k + VT_CY);
+                    const double w = (double)ldc(vt, k + VT_W);
+                    const T sm1 = st_seam[b][s][1][wave * V + v];
+                    const T sm2 = st_seam[b][s][0][wave * V + v];
+                    const T hS1 = dpp_shr1(sm1, prev1[v]);
+                    const T hS2 = dpp_shr1(sm2, hs1p[v]);
                     const T S = fma(b3, qq, fma(b2, eta, fma(b1, xi, b0)));
                     const T ux = fma(px, prev1[v], fma(qx, prev2[v], gx));
                     const T uy = fma(py, hS1, fma(qy, hS2, gy));
@@ -230,7 +292,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                     T rinv;
                     if (FIELD) {
                         const T den = fma(ax, cx, fma(ay, cy, dl));
-                        rinv = (ci == STENCIL_SOLID || w == 0.0) ? T(0) : rcp_full(den);
+                        rinv = (solid || w == 0.0) ? T(0) : rcp_full(den);
                     } else {
                         rinv = lds_rinv[wave * V + v][ci];
                     }
@@ -245,7 +307,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                         acc[3] = fma((double)qq, hw, acc[3]);
                     }
                     hout[v] = h;
-                    if (in.tp == in.nx) {
+                    if (tp == nx) {
                         hs1p[v] = hS1;
                         prev2[v] = prev1[v];
                         prev1[v] = h;
@@ -257,37 +319,38 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                         prev1[v] = xact ? h : prev1[v];
                     }
                 }
-                // the top two rows of the strip feed the next strip next iteration
-                if (!FINAL && has_down && cl >= 0 && lane >= hs - 2) {
-                    const int slot = lane - (hs - 2);
-                    const int xx = cl % in.nx;
-                    T *sp = seam_out + (size_t)xx * seam_row + (size_t)slot * a.kp4 + kw;
+                // the last two rows of the strip feed the next strip next iteration
+                if (!FINAL && has_down && lane >= hs - 2 && lane < hs) {
+                    const int cl = st_cell[b][s][lane];
+                    if (cl >= 0) {
+                        const int slot = lane - (hs - 2);
+                        T *sp = seam_out + (size_t)(cl % nx) * seam_row + (size_t)slot * a.kp4 + kw;
 #pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        sp[v] = hout[v];
+                        for (int v = 0; v < V; ++v)
+                            sp[v] = hout[v];
+                    }
                 }
             }
 #pragma unroll
             for (int m = 0; m < NM; ++m)
-                lds_part[buf][s][wave][lane][m] = acc[m];
+                lds_part[s][wave][lane][m] = acc[m];
         }
+        if (c + 1 < nchunks)
+            commit(b ^ 1);
         __syncthreads();
-        // group-wide sum of the partial moments of the S steps just done
-        for (int e = tid; e < S * 64 * NM; e += 64 * G) {
+        // group-wide sum of the partial moments of this chunk
+        for (int e = tid; e < C * 64 * NM; e += 64 * G) {
             const int s = e / (64 * NM), l = (e / NM) % 64, m = e % NM;
-            const int t = t0 + s;
-            if (t >= nsteps)
-                continue;
-            const int cl = strip_cell(in, y0, hs, xpos, ypos, t, l);
-            if (cl < 0)
+            const int cl = st_cell[b][s][l];
+            if (cl < 0 || (st_code[b][s][l] >> 4))
                 continue;
             double sum = 0.0;
 #pragma unroll
             for (int w = 0; w < G; ++w)
-                sum += lds_part[buf][s][w][l][m];
+                sum += lds_part[s][w][l][m];
             a.part[((size_t)it.group * a.ncell + cbase + cl) * NM + m] = sum;
         }
-        buf ^= 1;
+        __syncthreads();
     }
     if (!FINAL && x_coupled) {
 #pragma unroll
@@ -372,20 +435,20 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
     double diff = 0.0, absu = 0.0;
     if (c < in.nx * in.ny) {
         const long long cg = in.cell_off + c;
-        T *rec = a.rec + cg * REC_STRIDE;
         const int code = a.codes[cg];
-        if (code == 0xFF) {
-            for (int i = 0; i < REC_STRIDE; ++i)
-                rec[i] = T(0);
-        } else {
+        if (code != 0xFF) {
             const double *m = a.mom + cg * MOM_STRIDE;
             const double r = m[MOM_RHO], u1 = m[MOM_U1], u2 = m[MOM_U2], e = m[MOM_E];
             const double t = (e - r * a.c2) / a.c4;
             const double dl = in.field ? a.delta_field[cg] : in.delta;
+            T rec[8];
             rec[0] = T(dl * (r / a.m0 - t * a.c2));
             rec[1] = T(dl * (u1 / a.m2) + in.drive);
             rec[2] = T(dl * (u2 / a.m2));
             rec[3] = T(dl * t);
+            rec[6] = T(dl);
+            rec[7] = T(0);
+            double gside[4];
             const int x = c % in.nx, y = c / in.nx;
             for (int d = 0; d < 4; ++d) {
                 const int cd = (code >> (2 * d)) & 3;
@@ -412,7 +475,16 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
                     }
                     gval = in.alpha * sgn * f / a.D;
                 }
-                rec[4 + d] = T(gval);
+                gside[d] = gval;
+            }
+            // one copy per quadrant, in that quadrant's sweep order
+            for (int qd = 0; qd < 4; ++qd) {
+                rec[4] = T(gside[(qd & 1) ? SIDE_E : SIDE_W]);
+                rec[5] = T(gside[(qd & 2) ? SIDE_N : SIDE_S]);
+                const long long pos = a.spos[cg * 4 + qd];
+                T *dst = a.srec + pos * 8;
+                for (int i = 0; i < 8; ++i)
+                    dst[i] = rec[i];
             }
             const double up = a.u1prev[cg];
             diff = fabs(u1 - up);
