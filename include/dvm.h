@@ -66,8 +66,10 @@ typedef struct {
     long max_iter;          /* iteration cap per solve; default 200000        */
     int block_iters;        /* iterations per captured launch block; 0 -> 32  */
     int use_graphs;         /* 1: replay blocks as HIP graphs; 0: plain launches */
-    int vel_per_lane;       /* 0 = autotune, else 4 or 8 velocities per lane  */
-    int waves_per_block;    /* 0 = autotune, else 4 or 8                      */
+    int vel_per_lane;       /* velocities per lane: 0 = default, 2, 4 or 8    */
+    int waves_per_block;    /* waves per workgroup: 0 = default, 4 or 8;
+                               supported pairs (V, G): (4,8) (8,4) (4,4)
+                               (2,8)                                          */
     const char *tune_cache; /* autotune cache file or NULL (in-memory only)   */
     int profile;            /* 1: time every sweep launch with HIP events on
                                the context's stream (replaces graph replay);

@@ -789,10 +789,9 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
         return fail(DVM_EINVAL, "max_iter must be > 0");
     if (c.block_iters < 0 || c.block_iters > 4096)
         return fail(DVM_EINVAL, "block_iters must be in [0, 4096]");
-    int V = c.vel_per_lane ? c.vel_per_lane : 8;
+    int V = c.vel_per_lane ? c.vel_per_lane : 4;
     int G = c.waves_per_block ? c.waves_per_block : 8;
-    bool okvg = (V == 8 && G == 8) || (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) ||
-                (V == 4 && G == 16) || (V == 2 && G == 16);
+    bool okvg = (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) || (V == 2 && G == 8);
     if (!okvg)
         return fail(DVM_EINVAL, "unsupported (vel_per_lane, waves_per_block) combination");
     dvm_ctx *ctx = new (std::nothrow) dvm_ctx();

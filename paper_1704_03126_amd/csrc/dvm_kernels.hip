@@ -88,27 +88,69 @@ __device__ __forceinline__ T ldc(cptr<T> p, int i)
     return p[i];
 }
 
-// Steps of a pass staged per chunk; sized so that the staging buffers and the
-// per-wave moment partials fit the LDS of one workgroup.
-template <typename T, int G>
-struct SweepChunk {
-    static constexpr int C = (G >= 16) ? 2 : 4;
-};
+// Steps of a pass staged per chunk: a multiple of 6 so that the 3-register
+// rotation of the x-upwind values and the 2-register rotation of the
+// y-upwind value are pure renaming inside a chunk.
+constexpr int SWEEP_C = 6;
+
+// One velocity of one step for one lane (see k_sweep).  xa: the lane has a
+// cell at this step (false keeps the registers, used off the lane's window).
+template <typename T, bool FIELD, bool FINAL, bool HOLD>
+__device__ __forceinline__ void sweep_update(
+    T &p1, T &p2, T &pn, T &hs1p, T &hs1n, T &hout, double *acc,
+    T sm1, T sm2, T b0, T b1, T b2, T b3, T gx, T gy, T px, T qx, T py, T qy,
+    T rinv_or_dl, T ax, T ay, bool solid, bool xa,
+    T xi, T eta, T qq, T cx, T cy, double w, double wxi, double weta, double wq)
+{
+    const T hS1 = dpp_shr1(sm1, p1);
+    const T hS2 = dpp_shr1(sm2, hs1p);
+    const T S = fma(b3, qq, fma(b2, eta, fma(b1, xi, b0)));
+    const T ux = fma(px, p1, fma(qx, p2, gx));
+    const T uy = fma(py, hS1, fma(qy, hS2, gy));
+    const T g = fma(cx, ux, fma(cy, uy, S));
+    T rinv;
+    if (FIELD) {
+        const T den = fma(ax, cx, fma(ay, cy, rinv_or_dl));
+        rinv = (solid || w == 0.0) ? T(0) : rcp_full(den);
+    } else {
+        rinv = rinv_or_dl;
+    }
+    const T h = g * rinv;
+    const double hd = (double)h;
+    if (FINAL) {
+        acc[0] = fma(wxi * (double)eta, hd, acc[0]);
+    } else {
+        acc[0] = fma(w, hd, acc[0]);
+        acc[1] = fma(wxi, hd, acc[1]);
+        acc[2] = fma(weta, hd, acc[2]);
+        acc[3] = fma(wq, hd, acc[3]);
+    }
+    hout = h;
+    if (HOLD) {
+        // keep prev1/prev2/hs1 when the lane has no cell at this step
+        pn = xa ? h : p1;
+        p1 = xa ? p1 : p2;        // becomes prev2 of the next step
+        hs1n = xa ? hS1 : hs1p;
+    } else {
+        pn = h;
+        hs1n = hS1;
+    }
+}
 
 template <typename T, int V, int G, bool FIELD, bool FINAL>
 __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
 {
-    constexpr int C = SweepChunk<T, G>::C;     // steps per chunk
+    constexpr int C = SWEEP_C;                 // steps per chunk
     constexpr int NM = FINAL ? 1 : 4;          // moments accumulated
     constexpr int P = G * V;                   // velocities of the group
     constexpr int UPE = 8 * sizeof(T) / 16;    // 16-byte units per record
     __shared__ __attribute__((aligned(16))) T st_rec[2][C][64][8];
     __shared__ uint8_t st_code[2][C][64];
     __shared__ int st_cell[2][C][64];
-    __shared__ T st_seam[2][C][2][P];
+    __shared__ __attribute__((aligned(16))) T st_seam[2][C][2][P];
     __shared__ double lds_part[C][G][64][NM];
     __shared__ T lds_rinv[P][NSTENCIL];
-    __shared__ T lds_pq[4][2];
+    __shared__ __attribute__((aligned(16))) T lds_pq[4][2];
 
     const WorkItem it = a.items[blockIdx.x];
     const InstDev in = a.inst[it.inst];
@@ -129,7 +171,6 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     const long long iter = a.st[it.inst].iter;
     const int par_w = (int)(iter & 1), par_r = par_w ^ 1;
     const int tp = in.tp, nx = in.nx;
-    // skewed entries of this (quadrant, strip): entry (t, lane)
     const size_t ebase = (size_t)in.sk_off + ((size_t)(q * in.nstrips + it.strip) * tp) * 64;
     const T *__restrict__ srec = a.srec + ebase * 8;
     const uint8_t *__restrict__ scode = a.scode + ebase;
@@ -161,7 +202,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     const bool x_coupled = nx > 1;
 
     // ---- staging of one chunk of steps into LDS buffer b (global loads are
-    //      issued into registers first, stored after the current chunk)
+    //      issued into registers first and stored after the current chunk)
     constexpr int REC_UNITS = C * 64 * UPE;
     constexpr int RU_PER_T = (REC_UNITS + 64 * G - 1) / (64 * G);
     constexpr int SEAM_VALS = C * 2 * P;
@@ -177,11 +218,8 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         for (int r = 0; r < RU_PER_T; ++r) {
             const int u = tid + r * 64 * G;
             ru[r] = make_uint4(0, 0, 0, 0);
-            if (u < REC_UNITS) {
-                const int e = u / UPE;             // entry within chunk: s * 64 + lane
-                if (t0 + e / 64 < tp)
-                    ru[r] = reinterpret_cast<const uint4 *>(srec + ((size_t)t0 * 64) * 8)[u];
-            }
+            if (u < REC_UNITS && t0 + (u / UPE) / 64 < tp)
+                ru[r] = reinterpret_cast<const uint4 *>(srec + ((size_t)t0 * 64) * 8)[u];
         }
 #pragma unroll
         for (int r = 0; r < CC_PER_T; ++r) {
@@ -199,8 +237,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             sv[r] = T(0);
             if (e < SEAM_VALS && has_up) {
                 const int sidx = e / (2 * P), slot = (e / P) & 1, j = e % P;
-                const int t = t0 + sidx;
-                const int xr = t < tp ? t : tp;   // lane 0 treats xr = t
+                const int xr = t0 + sidx;            // lane 0 treats x_r = t
                 if (xr < nx) {
                     const int x0 = xpos ? xr : nx - 1 - xr;
                     sv[r] = seam_in[(size_t)x0 * seam_row + (size_t)slot * a.kp4 + kq0 + j];
@@ -231,110 +268,141 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         }
     };
 
-    // wrap-around state: this lane's last two results and the last y-upstream
-    T prev1[V], prev2[V], hs1p[V];
+    // velocity constants of this wave, for the whole pass
+    T cxi[V], ceta[V], cqq[V], ccx[V], ccy[V];
+    double cw[V], cwxi[V], cweta[V], cwq[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int k = (kw + v) * VT_STRIDE;
+        cxi[v] = ldc(vt, k + VT_XI);
+        ceta[v] = ldc(vt, k + VT_ETA);
+        cqq[v] = ldc(vt, k + VT_Q);
+        ccx[v] = ldc(vt, k + VT_CX);
+        ccy[v] = ldc(vt, k + VT_CY);
+        cw[v] = (double)ldc(vt, k + VT_W);
+        cwxi[v] = cw[v] * (double)cxi[v];
+        cweta[v] = cw[v] * (double)ceta[v];
+        cwq[v] = cw[v] * (double)cqq[v];
+    }
+
+    // rotating registers: x-upwind values A (prev1), B (prev2), X (free);
+    // y-upwind chain H0 (current hs1), H1 (free)
+    T rA[V], rB[V], rX[V], rH0[V], rH1[V];
     T *wrapp = a.wrap + in.wrap_off + (((size_t)it.strip * (a.kp4 / V) + kw / V) * 64 + lane) * (3 * V);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        prev1[v] = x_coupled ? wrapp[v] : T(0);
-        prev2[v] = x_coupled ? wrapp[V + v] : T(0);
-        hs1p[v] = x_coupled ? wrapp[2 * V + v] : T(0);
+        rA[v] = x_coupled ? wrapp[v] : T(0);
+        rB[v] = x_coupled ? wrapp[V + v] : T(0);
+        rH0[v] = x_coupled ? wrapp[2 * V + v] : T(0);
+        rX[v] = T(0);
+        rH1[v] = T(0);
     }
 
     const long long cbase = in.cell_off;
     const int nchunks = (tp + C - 1) / C;
+    const bool skew = tp != nx;
+    // x position (in sweep order) of this lane's cell at the chunk start
+    int xr0 = (tp - (lane % tp)) % tp;
+
     issue(0);
     commit(0);
     __syncthreads();
+
+    // one step: s-th step of the chunk in buffer b; (PA, PB, PX) and (HA, HB)
+    // are the register roles of this step in the rotation
+    auto step = [&](int b, int s, int t, T *PA, T *PB, T *PX, T *HA, T *HB, bool hold, bool xa) {
+        double acc[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+            acc[m] = 0.0;
+        const T *rec = &st_rec[b][s][lane][0];
+        const int code = st_code[b][s][lane];
+        const int cxc = code & 3, cyc = (code >> 2) & 3;
+        const bool solid = (code >> 4) != 0;
+        const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
+        const T gx = rec[4], gy = rec[5];
+        const T px = lds_pq[cxc][0], qx = lds_pq[cxc][1];
+        const T py = lds_pq[cyc][0], qy = lds_pq[cyc][1];
+        const int ci = solid ? STENCIL_SOLID : ((cxc == CODE_WALL) ? 2 : 0) + ((cyc == CODE_WALL) ? 1 : 0);
+        T ax = T(0), ay = T(0), rdl[V];
+        if (FIELD) {
+            ax = (cxc == CODE_WALL) ? T(1) : T(1.5);
+            ay = (cyc == CODE_WALL) ? T(1) : T(1.5);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                rdl[v] = rec[6];
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                rdl[v] = lds_rinv[wave * V + v][ci];
+        }
+        T sm1[V], sm2[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            sm1[v] = has_up ? st_seam[b][s][1][wave * V + v] : T(0);
+            sm2[v] = has_up ? st_seam[b][s][0][wave * V + v] : T(0);
+        }
+        T hout[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (hold)
+                sweep_update<T, FIELD, FINAL, true>(PA[v], PB[v], PX[v], HA[v], HB[v], hout[v], acc,
+                                                    sm1[v], sm2[v], b0, b1, b2, b3, gx, gy, px, qx, py, qy,
+                                                    rdl[v], ax, ay, solid, xa, cxi[v], ceta[v], cqq[v],
+                                                    ccx[v], ccy[v], cw[v], cwxi[v], cweta[v], cwq[v]);
+            else
+                sweep_update<T, FIELD, FINAL, false>(PA[v], PB[v], PX[v], HA[v], HB[v], hout[v], acc,
+                                                     sm1[v], sm2[v], b0, b1, b2, b3, gx, gy, px, qx, py, qy,
+                                                     rdl[v], ax, ay, solid, xa, cxi[v], ceta[v], cqq[v],
+                                                     ccx[v], ccy[v], cw[v], cwxi[v], cweta[v], cwq[v]);
+        }
+        // the last two rows of the strip feed the next strip next iteration
+        if (!FINAL && has_down && t < tp && lane >= hs - 2 && lane < hs) {
+            const int cl = st_cell[b][s][lane];
+            if (cl >= 0) {
+                const int slot = lane - (hs - 2);
+                T *sp = seam_out + (size_t)(cl % nx) * seam_row + (size_t)slot * a.kp4 + kw;
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    sp[v] = hout[v];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+            lds_part[s][wave][lane][m] = acc[m];
+    };
+
     for (int c = 0; c < nchunks; ++c) {
         const int b = c & 1;
+        const int t0 = c * C;
         if (c + 1 < nchunks)
             issue(c + 1);
+        // register roles cycle with period 6: (A,B,X)(H0,H1) -> (X,A,B)(H1,H0) -> ...
+        if (!skew && t0 + C <= tp) {
+            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, false, true);
+            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, false, true);
+            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, false, true);
+            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, false, true);
+            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, false, true);
+            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, false, true);
+        } else {
+            // skewed schedule or the partial last chunk: lanes keep their
+            // registers at steps where they have no cell
+            int xr = xr0;
+            bool xa[C];
 #pragma unroll
-        for (int s = 0; s < C; ++s) {
-            const int t = c * C + s;
-            double acc[NM];
-#pragma unroll
-            for (int m = 0; m < NM; ++m)
-                acc[m] = 0.0;
-            if (t < tp) {
-                const T *rec = &st_rec[b][s][lane][0];
-                const int code = st_code[b][s][lane];
-                const int cxc = code & 3, cyc = (code >> 2) & 3;
-                const bool solid = (code >> 4) != 0;
-                const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
-                const T gx = rec[4], gy = rec[5];
-                const T px = lds_pq[cxc][0], qx = lds_pq[cxc][1];
-                const T py = lds_pq[cyc][0], qy = lds_pq[cyc][1];
-                const int ci = solid ? STENCIL_SOLID : ((cxc == CODE_WALL) ? 2 : 0) + ((cyc == CODE_WALL) ? 1 : 0);
-                T dl = T(0), ax = T(0), ay = T(0);
-                if (FIELD) {
-                    dl = rec[6];
-                    ax = (cxc == CODE_WALL) ? T(1) : T(1.5);
-                    ay = (cyc == CODE_WALL) ? T(1) : T(1.5);
-                }
-                const bool xact = (t - lane >= 0 ? (t - lane) % tp : (t - lane) % tp + tp) < nx;
-                T hout[V];
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const int k = (kw + v) * VT_STRIDE;
-                    const T xi = ldc(vt, k + VT_XI), eta = ldc(vt, k + VT_ETA), qq = ldc(vt, k + VT_Q);
-                    const T cx = ldc(vt, k + VT_CX), cy = ldc(vt, k + VT_CY);
-                    const double w = (double)ldc(vt, k + VT_W);
-                    const T sm1 = st_seam[b][s][1][wave * V + v];
-                    const T sm2 = st_seam[b][s][0][wave * V + v];
-                    const T hS1 = dpp_shr1(sm1, prev1[v]);
-                    const T hS2 = dpp_shr1(sm2, hs1p[v]);
-                    const T S = fma(b3, qq, fma(b2, eta, fma(b1, xi, b0)));
-                    const T ux = fma(px, prev1[v], fma(qx, prev2[v], gx));
-                    const T uy = fma(py, hS1, fma(qy, hS2, gy));
-                    const T g = fma(cx, ux, fma(cy, uy, S));
-                    T rinv;
-                    if (FIELD) {
-                        const T den = fma(ax, cx, fma(ay, cy, dl));
-                        rinv = (solid || w == 0.0) ? T(0) : rcp_full(den);
-                    } else {
-                        rinv = lds_rinv[wave * V + v][ci];
-                    }
-                    const T h = g * rinv;
-                    const double hw = (double)h * w;
-                    if (FINAL) {
-                        acc[0] = fma((double)xi * (double)eta, hw, acc[0]);
-                    } else {
-                        acc[0] += hw;
-                        acc[1] = fma((double)xi, hw, acc[1]);
-                        acc[2] = fma((double)eta, hw, acc[2]);
-                        acc[3] = fma((double)qq, hw, acc[3]);
-                    }
-                    hout[v] = h;
-                    if (tp == nx) {
-                        hs1p[v] = hS1;
-                        prev2[v] = prev1[v];
-                        prev1[v] = h;
-                    } else {
-                        // skewed schedule: outside its window of the pass a
-                        // lane keeps the results it will need next
-                        hs1p[v] = xact ? hS1 : hs1p[v];
-                        prev2[v] = xact ? prev1[v] : prev2[v];
-                        prev1[v] = xact ? h : prev1[v];
-                    }
-                }
-                // the last two rows of the strip feed the next strip next iteration
-                if (!FINAL && has_down && lane >= hs - 2 && lane < hs) {
-                    const int cl = st_cell[b][s][lane];
-                    if (cl >= 0) {
-                        const int slot = lane - (hs - 2);
-                        T *sp = seam_out + (size_t)(cl % nx) * seam_row + (size_t)slot * a.kp4 + kw;
-#pragma unroll
-                        for (int v = 0; v < V; ++v)
-                            sp[v] = hout[v];
-                    }
-                }
+            for (int s = 0; s < C; ++s) {
+                xa[s] = (t0 + s < tp) && (xr < nx);
+                xr = (xr + 1 == tp) ? 0 : xr + 1;
             }
-#pragma unroll
-            for (int m = 0; m < NM; ++m)
-                lds_part[s][wave][lane][m] = acc[m];
+            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, true, xa[0]);
+            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, true, xa[1]);
+            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, true, xa[2]);
+            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, true, xa[3]);
+            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, true, xa[4]);
+            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, true, xa[5]);
         }
+        xr0 = (xr0 + C) % tp;
         if (c + 1 < nchunks)
             commit(b ^ 1);
         __syncthreads();
@@ -355,9 +423,9 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     if (!FINAL && x_coupled) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            wrapp[v] = prev1[v];
-            wrapp[V + v] = prev2[v];
-            wrapp[2 * V + v] = hs1p[v];
+            wrapp[v] = rA[v];
+            wrapp[V + v] = rB[v];
+            wrapp[2 * V + v] = rH0[v];
         }
     }
 }
@@ -603,12 +671,10 @@ hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, bool fi
         return field ? launch_sweep_t<T, VV, GG, true, false>(a, nitems, s)              \
                      : launch_sweep_t<T, VV, GG, false, false>(a, nitems, s);            \
     }
-    DVM_SW(8, 8)
     DVM_SW(4, 8)
     DVM_SW(8, 4)
     DVM_SW(4, 4)
-    DVM_SW(4, 16)
-    DVM_SW(2, 16)
+    DVM_SW(2, 8)
 #undef DVM_SW
     return hipErrorInvalidValue;
 }

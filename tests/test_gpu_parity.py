@@ -119,7 +119,7 @@ def test_delta_field_and_padding(dvm):
     assert np.isnan(ka)
 
 
-@pytest.mark.parametrize("vel,waves", [(4, 8), (8, 4), (4, 4), (4, 16), (2, 16)])
+@pytest.mark.parametrize("vel,waves", [(8, 4), (4, 4), (2, 8)])
 def test_launch_shapes_agree(dvm, vel, waves):
     g = rough_channel(48, 20, 4, 24)
     base = gpu_solve(dvm, g, 1.0, 16, tol=1e-12)
