@@ -50,6 +50,14 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--vel", type=int, default=0)
     p.add_argument("--waves", type=int, default=0)
+    p.add_argument("--no-roofline", action="store_true",
+                   help="skip the event-timed roofline pass (for profiler runs)")
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="first run a plain device copy of this many MiB (the "
+                        "reference for profiler byte counters)")
+    p.add_argument("--traffic-json", default=None,
+                   help="HBM bytes per sweep launch measured by a profiler "
+                        "(JSON {fetch_bytes, write_bytes}) to report as traffic")
     return p.parse_args()
 
 
@@ -65,6 +73,14 @@ def main():
         sys.exit(1)
     import paper_1704_03126_amd.dvm as dvm
     from paper_1704_03126_amd.geometry import cfg_rough_channel
+
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     g = cfg_rough_channel()
     nf = g.n_fluid
@@ -99,23 +115,34 @@ def main():
     value = updates / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
 
-    # roofline of the sweep: one more step with every sweep bracketed by HIP
-    # events on the solver's stream
-    prof = dvm.Solver(NV, 1, tol=TOL, profile=True, vel_per_lane=args.vel,
-                      waves_per_block=args.waves)
-    prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
-    for d in DELTAS:
-        prof.solve(0, d)
-    sweep_ms, n_sweeps, other_ms = prof.profile()
-    prof.close()
-    avg_sweep_s = sweep_ms / max(n_sweeps, 1) / 1e3
-    flops_per_launch = float(nf) * K * FLOPS_PER_UPDATE
-    achieved = flops_per_launch / avg_sweep_s
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
-                "kernel": "k_sweep<double>", "avg_launch_ms": avg_sweep_s * 1e3,
-                "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": nf * K,
-                "sweep_share_of_iteration": sweep_ms / max(sweep_ms + other_ms, 1e-30)}
+    roofline = None
+    if not args.no_roofline:
+        # roofline of the sweep: one more step with every sweep bracketed by
+        # HIP events on the solver's stream
+        prof = dvm.Solver(NV, 1, tol=TOL, profile=True, vel_per_lane=args.vel,
+                          waves_per_block=args.waves)
+        prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        for d in DELTAS:
+            prof.solve(0, d)
+        sweep_ms, n_sweeps, other_ms = prof.profile()
+        prof.close()
+        avg_sweep_s = sweep_ms / max(n_sweeps, 1) / 1e3
+        flops_per_launch = float(nf) * K * FLOPS_PER_UPDATE
+        achieved = flops_per_launch / avg_sweep_s
+        traffic = None
+        if args.traffic_json:
+            with open(args.traffic_json) as f:
+                tr = json.load(f)
+            traffic = {"fetch_bytes_per_launch": tr["fetch_bytes"],
+                       "write_bytes_per_launch": tr["write_bytes"],
+                       "bytes_per_update": (tr["fetch_bytes"] + tr["write_bytes"]) / (nf * K),
+                       "hbm_GBps_at_avg_launch": (tr["fetch_bytes"] + tr["write_bytes"]) / avg_sweep_s / 1e9,
+                       "source": tr.get("source", "")}
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": traffic,
+                    "kernel": "k_sweep<double>", "avg_launch_ms": avg_sweep_s * 1e3,
+                    "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": nf * K,
+                    "sweep_share_of_iteration": sweep_ms / max(sweep_ms + other_ms, 1e-30)}
 
     cpu = None
     if not args.no_cpu:
@@ -157,9 +184,9 @@ def cpu_baseline(g, budget_s):
     oracle.build(force=False)
     t0 = time.perf_counter()
     oracle.si_solve(g.mask, 1.0, NV, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
-                    tol=-1.0, max_iter=1)
-    t1 = time.perf_counter() - t0
-    n = max(1, int(budget_s / max(t1, 1e-3)))
+                    tol=-1.0, max_iter=2)
+    t1 = (time.perf_counter() - t0) / 2.0
+    n = max(2, int(budget_s / max(t1, 1e-3)))
     t0 = time.perf_counter()
     oracle.si_solve(g.mask, 1.0, NV, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
                     tol=-1.0, max_iter=n)
