@@ -130,9 +130,13 @@ def main():
         flops_per_launch = float(nf) * K * FLOPS_PER_UPDATE
         achieved = flops_per_launch / avg_sweep_s
         traffic = None
+        tr = None
         if args.traffic_json:
             with open(args.traffic_json) as f:
                 tr = json.load(f)
+        else:
+            tr = measured_traffic()
+        if tr is not None:
             traffic = {"fetch_bytes_per_launch": tr["fetch_bytes"],
                        "write_bytes_per_launch": tr["write_bytes"],
                        "bytes_per_update": (tr["fetch_bytes"] + tr["write_bytes"]) / (nf * K),
@@ -174,6 +178,23 @@ def main():
     }
     solver.close()
     print(json.dumps(out))
+
+
+def measured_traffic():
+    """Profiler-measured HBM bytes per sweep launch (profiles/), valid only
+    while the kernel source is the one that was profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sweep_traffic.json")
+    src = os.path.join(ROOT, "paper_1704_03126_amd", "csrc", "dvm_kernels.hip")
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if not sha.startswith(tr.get("kernel_source_sha256_prefix", "-")):
+        return None
+    return tr
 
 
 def cpu_baseline(g, budget_s):
