@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--schedule", choices=["skew", "wrap"], default="skew",
+                   help="sweep order: skew (lags periodic/strip seams only) or the "
+                        "wrap-around diagonal (fewer steps, not unconditionally stable)")
     p.add_argument("--vel", type=int, default=0)
     p.add_argument("--waves", type=int, default=0)
     p.add_argument("--no-roofline", action="store_true",
@@ -85,7 +88,9 @@ def main():
     g = cfg_rough_channel()
     nf = g.n_fluid
     K = NV * NV
-    solver = dvm.Solver(NV, 1, tol=TOL, vel_per_lane=args.vel, waves_per_block=args.waves)
+    sched = dvm.DVM_SCHED_WRAP if args.schedule == "wrap" else dvm.DVM_SCHED_SKEW
+    solver = dvm.Solver(NV, 1, tol=TOL, vel_per_lane=args.vel, waves_per_block=args.waves,
+                        schedule=sched)
     solver.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
 
     def step():
@@ -120,7 +125,7 @@ def main():
         # roofline of the sweep: one more step with every sweep bracketed by
         # HIP events on the solver's stream
         prof = dvm.Solver(NV, 1, tol=TOL, profile=True, vel_per_lane=args.vel,
-                          waves_per_block=args.waves)
+                          waves_per_block=args.waves, schedule=sched)
         prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
         for d in DELTAS:
             prof.solve(0, d)
@@ -168,7 +173,7 @@ def main():
         "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
                    "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
                    "deltas": list(DELTAS), "tol": TOL, "precision": "fp64",
-                   "parallelism": "single_gpu"},
+                   "schedule": args.schedule, "parallelism": "single_gpu"},
         "iterations_per_delta": all_its[-1],
         "time_to_solution_s": dict(zip([str(d) for d in DELTAS],
                                        np.mean(np.array(all_tts), axis=0).tolist())),

@@ -50,6 +50,9 @@ extern "C" {
 #define DVM_FP64 0          /* all sweeps in FP64                             */
 #define DVM_FP32_REFINE 1   /* FP32 sweeps, FP64 moments + defect correction  */
 
+#define DVM_SCHED_SKEW 0    /* sweep order with lags at periodic/strip seams only */
+#define DVM_SCHED_WRAP 1    /* wrap-around diagonal: fewer steps on wide grids  */
+
 #define DVM_STATUS_RUNNING 0
 #define DVM_STATUS_CONVERGED 1
 #define DVM_STATUS_MAXITER 2
@@ -74,6 +77,16 @@ typedef struct {
     int profile;            /* 1: time every sweep launch with HIP events on
                                the context's stream (replaces graph replay);
                                read the totals with dvm_profile              */
+    int schedule;           /* order of the cells within a sweep (the fixed
+                               point does not depend on it):
+                               DVM_SCHED_SKEW (default) lags only the values
+                               that cross periodic seams and 64-row strip
+                               boundaries, as the paper's iteration lags its
+                               periodic seam; DVM_SCHED_WRAP (grids with
+                               nx >= 8) also lags the y coupling along one
+                               diagonal per strip, saving 63 steps per pass,
+                               but the iteration can then diverge (seen with
+                               a solid block inside a periodic cell)         */
 } dvm_config;
 
 /* Per-instance result of dvm_solve. */

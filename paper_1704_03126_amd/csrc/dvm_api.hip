@@ -42,11 +42,16 @@ struct HostInst {
     double cph = 1.0;
     std::vector<uint8_t> solid, codes;
     long long nfluid = 0;
+    // wall faces: local id per (cell, side) (-1 none), cell-major order
+    std::vector<int> face_of;
+    int nfaces = 0;
+    long long face_base = 0;  // first global face id (set by the layout)
     // last solve parameters
     bool field = false;
     double delta = 1.0, alpha = 1.0;
     std::vector<double> dfield;
     bool has_state = false;   // a converged/partial solution is on the device
+    bool converged = false;   // the last solve met the stop rule
 };
 
 template <typename T>
@@ -93,13 +98,27 @@ struct dvm_ctx {
     DevBuf<uint8_t> d_codes, d_scode;
     DevBuf<int> d_smap;
     DevBuf<long long> d_spos;
-    DevBuf<double> d_srec, d_vt, d_dfield, d_part, d_mom, d_u1prev, d_seam, d_wrap, d_aux;
-    long long sk_total = 0;
+    DevBuf<FaceRec> d_sface;
+    DevBuf<double> d_srec, d_vt, d_dfield, d_part, d_mom, d_u1prev, d_seam, d_wrap, d_aux, d_fb;
+    long long sk_total = 0, nfaces = 0;
     DevBuf<SolveState> d_st;
 
-    hipGraphExec_t graph = nullptr;
-    int graph_iters = 0;
-    bool graph_field = false;
+    // adjoint problem (allocated by the first dvm_grad)
+    bool adj_ready = false;
+    std::vector<uint8_t> h_scode_adj;
+    std::vector<FaceRec> h_sface_adj;
+    std::vector<int> h_face_cell, h_face_side, h_face_inst;
+    DevBuf<uint8_t> d_scode_adj;
+    DevBuf<FaceRec> d_sface_adj;
+    DevBuf<int> d_face_cell, d_face_side, d_face_inst;
+    DevBuf<double> d_srec_adj, d_mom_adj, d_u1prev_adj, d_seam_adj, d_wrap_adj, d_fb_adj;
+    DevBuf<double> d_ckpt, d_part5, d_momg, d_dqda;
+    DevBuf<SolveState> d_st_adj;
+
+    // captured iteration blocks: [0] forward, [1] adjoint
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_iters[2] = {0, 0};
+    int graph_mode[2] = {-1, -1};
 
     // profiling (cfg.profile): event pairs around sweep launches
     std::vector<hipEvent_t> ev_pool;
@@ -110,15 +129,20 @@ struct dvm_ctx {
 
     ~dvm_ctx()
     {
-        if (graph)
-            (void)hipGraphExecDestroy(graph);
+        for (auto &g : graph)
+            if (g)
+                (void)hipGraphExecDestroy(g);
         for (auto e : ev_pool)
             (void)hipEventDestroy(e);
         d_inst.release(); d_items.release(); d_codes.release(); d_srec.release();
         d_scode.release(); d_smap.release(); d_spos.release();
         d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release();
         d_u1prev.release(); d_seam.release(); d_wrap.release(); d_aux.release();
-        d_st.release();
+        d_st.release(); d_sface.release(); d_fb.release();
+        d_scode_adj.release(); d_sface_adj.release(); d_face_cell.release(); d_face_side.release();
+        d_face_inst.release(); d_srec_adj.release(); d_mom_adj.release(); d_u1prev_adj.release();
+        d_seam_adj.release(); d_wrap_adj.release(); d_fb_adj.release(); d_ckpt.release();
+        d_part5.release(); d_momg.release(); d_dqda.release(); d_st_adj.release();
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
     }
@@ -202,6 +226,45 @@ static void build_codes(HostInst &h)
             }
             h.codes[c] = b;
         }
+    h.face_of.assign((size_t)h.nx * h.ny * 4, -1);
+    h.nfaces = 0;
+    for (size_t c = 0; c < h.codes.size(); ++c)
+        if (h.codes[c] != 0xFF)
+            for (int d = 0; d < 4; ++d)
+                if (((h.codes[c] >> (2 * d)) & 3) == CODE_WALL)
+                    h.face_of[c * 4 + d] = h.nfaces++;
+}
+
+// neighbour cell on side d (x periodic; y periodic or -1 beyond the outer walls)
+static long long neighbour(const HostInst &h, long long c, int d)
+{
+    int x = (int)(c % h.nx), y = (int)(c / h.nx);
+    if (d == SIDE_W) x = (x + h.nx - 1) % h.nx;
+    else if (d == SIDE_E) x = (x + 1) % h.nx;
+    else if (d == SIDE_S) y -= 1;
+    else y += 1;
+    if (y < 0 || y >= h.ny) {
+        if (!h.periodic_y)
+            return -1;
+        y = (y + h.ny) % h.ny;
+    }
+    return (long long)y * h.nx + x;
+}
+
+// Stencil nibble of the transposed transport along one axis for a velocity
+// whose upwind side has forward code `up` and downstream side `down`:
+// diagonal weight from the downstream code (the forward row of the cell for
+// the reversed velocity), first-neighbour weight from the upwind neighbour's
+// forward code facing the cell, second-neighbour weight when both upwind
+// neighbours are fluid.
+static uint8_t adjoint_nibble(int up, int down)
+{
+    if (up == CODE_NONE)
+        return CODE_NONE;
+    const int ai = down == CODE_WALL ? 1 : 0;
+    const int pi = up == CODE_WALL ? 2 : (down == CODE_WALL ? 1 : 0);
+    const int qi = up == CODE_INT ? 0 : 1;
+    return (uint8_t)(NIB_ADJ0 + 6 * ai + 2 * pi + qi);
 }
 
 // Every fluid component must wrap around the x period (carry a net flux);
@@ -291,26 +354,36 @@ static int ensure_device(dvm_ctx *c)
 }
 
 // -------------------------------------------------------------- layout
+static void drop_graphs(dvm_ctx *c)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (c->graph[i])
+            (void)hipGraphExecDestroy(c->graph[i]);
+        c->graph[i] = nullptr;
+        c->graph_mode[i] = -1;
+    }
+}
+
 static int build_layout(dvm_ctx *c)
 {
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_graphs(c);
+    c->adj_ready = false;
     const int V = c->V, G = c->G, P = V * G;
     c->gq = (c->K / 4 + P - 1) / P;
     c->kq = c->gq * P;
     c->kp4 = 4 * c->kq;
     c->idev.assign(c->n_inst, InstDev{});
     c->items.clear();
-    long long cell = 0, seam = 0, wrap = 0, sk = 0;
+    long long cell = 0, seam = 0, wrap = 0, sk = 0, faces = 0;
     int maxc = 0;
     for (int i = 0; i < c->n_inst; ++i) {
-        const HostInst &h = c->inst[i];
+        HostInst &h = c->inst[i];
         InstDev &d = c->idev[i];
+        h.face_base = faces;
+        faces += h.nfaces;
         d.nx = h.nx;
         d.ny = h.ny;
-        d.tp = h.nx >= WRAP_MIN ? h.nx : h.nx + 63;
+        d.tp = (c->cfg.schedule == DVM_SCHED_WRAP && h.nx >= WRAP_MIN) ? h.nx : h.nx + 63;
         strip_layout(h.ny, d.nstrips, d.strip_h);
         d.periodic_y = h.periodic_y;
         d.cell_off = cell;
@@ -338,6 +411,7 @@ static int build_layout(dvm_ctx *c)
     c->seam_half = seam;
     c->wrap_total = wrap;
     c->sk_total = sk;
+    c->nfaces = faces;
     c->max_cells = maxc;
 
     HIPCHK(c->d_inst.alloc(c->n_inst));
@@ -356,6 +430,9 @@ static int build_layout(dvm_ctx *c)
     HIPCHK(c->d_wrap.alloc(wrap));
     HIPCHK(c->d_aux.alloc(cell));
     HIPCHK(c->d_st.alloc(c->n_inst));
+    HIPCHK(c->d_sface.alloc(sk));
+    HIPCHK(c->d_fb.alloc((size_t)2 * std::max<long long>(faces, 1) * c->kp4));
+    HIPCHK(c->d_part5.alloc((size_t)4 * c->gq * cell));
 
     std::vector<uint8_t> codes(cell);
     std::vector<double> vt((size_t)c->n_inst * c->kp4 * VT_STRIDE, 0.0);
@@ -379,16 +456,38 @@ static int build_layout(dvm_ctx *c)
             }
     }
     // skewed sweep order of every (instance, quadrant, strip): lane l treats
-    // x_r = (t - l) mod tp at step t, rows run away from the upwind side
-    std::vector<uint8_t> scode(sk, 0x1F);
+    // x_r = (t - l) mod tp at step t, rows run away from the upwind side.
+    // Per entry: the fluid cell (-1 for none or solid), the x / y stencil
+    // nibbles of the forward and the adjoint problem, and the wall faces each
+    // problem reads and writes.
+    const FaceRec none{-1, -1, -1, -1, 0.f, 0.f, 0.f, 0.f};
+    std::vector<uint8_t> scode(sk, 0x33), scode_adj(sk, 0x33);
     std::vector<int> smap(sk, -1);
     std::vector<long long> spos(cell * 4, -1);
+    std::vector<FaceRec> sface(sk, none), sface_adj(sk, none);
+    c->h_face_cell.assign(faces, 0);
+    c->h_face_side.assign(faces, 0);
+    c->h_face_inst.assign(faces, 0);
     for (int i = 0; i < c->n_inst; ++i) {
         const HostInst &h = c->inst[i];
         const InstDev &d = c->idev[i];
+        auto gface = [&](long long cl, int side) -> int {
+            const int f = h.face_of[cl * 4 + side];
+            return f < 0 ? -1 : (int)(h.face_base + f);
+        };
+        for (long long cl = 0; cl < (long long)h.nx * h.ny; ++cl)
+            for (int side = 0; side < 4; ++side) {
+                const int f = gface(cl, side);
+                if (f >= 0) {
+                    c->h_face_cell[f] = (int)(d.cell_off + cl);
+                    c->h_face_side[f] = side;
+                    c->h_face_inst[f] = i;
+                }
+            }
         for (int q = 0; q < 4; ++q) {
             const bool xpos = (q & 1) == 0, ypos = (q & 2) == 0;
             const int dxs = xpos ? SIDE_W : SIDE_E, dys = ypos ? SIDE_S : SIDE_N;
+            const int dxd = dxs ^ 1, dyd = dys ^ 1;
             for (int st = 0; st < d.nstrips; ++st) {
                 const int y0 = st * d.strip_h;
                 const int hs = std::min(d.strip_h, d.ny - y0);
@@ -400,22 +499,58 @@ static int build_layout(dvm_ctx *c)
                             continue;
                         const int x = xpos ? xr : d.nx - 1 - xr;
                         const int row = ypos ? y0 + l : y0 + hs - 1 - l;
-                        const int cl = row * d.nx + x;
-                        smap[e] = cl;
+                        const long long cl = (long long)row * d.nx + x;
                         const uint8_t code = h.codes[cl];
-                        if (code != 0xFF) {
-                            scode[e] = (uint8_t)(((code >> (2 * dxs)) & 3) | (((code >> (2 * dys)) & 3) << 2));
-                            spos[(d.cell_off + cl) * 4 + q] = e;
-                        }
+                        if (code == 0xFF)
+                            continue;
+                        smap[e] = (int)cl;
+                        spos[(d.cell_off + cl) * 4 + q] = e;
+                        const int cxu = (code >> (2 * dxs)) & 3, cxd = (code >> (2 * dxd)) & 3;
+                        const int cyu = (code >> (2 * dys)) & 3, cyd = (code >> (2 * dyd)) & 3;
+                        scode[e] = (uint8_t)(cxu | (cyu << 4));
+                        scode_adj[e] = (uint8_t)(adjoint_nibble(cxu, cxd) | (adjoint_nibble(cyu, cyd) << 4));
+                        // forward: the wall value on an upwind wall face has a
+                        // specular share of that face's incident values; the
+                        // cell sends incident values through downstream walls
+                        FaceRec &fr = sface[e];
+                        fr.rdx = cxu == CODE_WALL ? gface(cl, dxs) : -1;
+                        fr.rdy = cyu == CODE_WALL ? gface(cl, dys) : -1;
+                        fr.wrx = cxd == CODE_WALL ? gface(cl, dxd) : -1;
+                        fr.wry = cyd == CODE_WALL ? gface(cl, dyd) : -1;
+                        fr.kx = fr.ky = 1.f;
+                        // adjoint: the upwind wall face of the cell (weight
+                        // 1.5, or 1 with a wall on the far side too) or of its
+                        // upwind neighbour (weight -0.5)
+                        FaceRec &fa = sface_adj[e];
+                        auto adj_face = [&](int up, int down, int side, int &rd, float &k) {
+                            rd = -1;
+                            k = 0.f;
+                            if (up == CODE_WALL) {
+                                rd = gface(cl, side);
+                                k = (down == CODE_WALL || down == CODE_NONE) ? 1.f : 1.5f;
+                            } else if (up == CODE_NEAR) {
+                                const long long u1 = neighbour(h, cl, side);
+                                rd = gface(u1, side);
+                                k = -0.5f;
+                            }
+                        };
+                        adj_face(cxu, cxd, dxs, fa.rdx, fa.kx);
+                        adj_face(cyu, cyd, dys, fa.rdy, fa.ky);
+                        fa.wrx = fr.wrx;
+                        fa.wry = fr.wry;
                     }
             }
         }
     }
+    c->h_scode_adj.swap(scode_adj);
+    c->h_sface_adj.swap(sface_adj);
     HIPCHK(hipMemcpyAsync(c->d_codes.p, codes.data(), cell, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_scode.p, scode.data(), sk, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_smap.p, smap.data(), sk * sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_spos.p, spos.data(), spos.size() * sizeof(long long), hipMemcpyHostToDevice,
                           c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_sface.p, sface.data(), sk * sizeof(FaceRec), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_zero(c->d_fb.p, c->d_fb.n, c->stream));
     HIPCHK(launch_zero(c->d_srec.p, c->d_srec.n, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_vt.p, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_items.p, c->items.data(), c->items.size() * sizeof(WorkItem),
@@ -432,22 +567,28 @@ static int build_layout(dvm_ctx *c)
     return DVM_OK;
 }
 
-static SweepArgs<double> sweep_args(dvm_ctx *c, int force)
+// Arguments of the forward (adj = false) or adjoint iteration.
+static SweepArgs<double> sweep_args(dvm_ctx *c, int force, bool adj = false)
 {
     SweepArgs<double> a{};
     a.inst = c->d_inst.p;
     a.items = c->d_items.p;
-    a.srec = c->d_srec.p;
-    a.scode = c->d_scode.p;
+    a.srec = adj ? c->d_srec_adj.p : c->d_srec.p;
+    a.scode = adj ? c->d_scode_adj.p : c->d_scode.p;
     a.smap = c->d_smap.p;
+    a.sface = adj ? c->d_sface_adj.p : c->d_sface.p;
+    a.fb = adj ? c->d_fb_adj.p : c->d_fb.p;
+    a.ckpt = c->d_ckpt.p;
+    a.part5 = c->d_part5.p;
     a.vtab = c->d_vt.p;
     a.delta_field = c->d_dfield.p;
     a.part = c->d_part.p;
-    a.seam = c->d_seam.p;
-    a.wrap = c->d_wrap.p;
-    a.st = c->d_st.p;
+    a.seam = adj ? c->d_seam_adj.p : c->d_seam.p;
+    a.wrap = adj ? c->d_wrap_adj.p : c->d_wrap.p;
+    a.st = adj ? c->d_st_adj.p : c->d_st.p;
     a.ncell = c->ncell;
     a.seam_half = c->seam_half;
+    a.fb_half = std::max<long long>(c->nfaces, 1) * c->kp4;
     a.gq = c->gq;
     a.kq = c->kq;
     a.kp4 = c->kp4;
@@ -455,30 +596,32 @@ static SweepArgs<double> sweep_args(dvm_ctx *c, int force)
     return a;
 }
 
-static MomArgs mom_args(dvm_ctx *c)
+static MomArgs mom_args(dvm_ctx *c, bool adj = false, int force = 0)
 {
     MomArgs a{};
     a.inst = c->d_inst.p;
     a.codes = c->d_codes.p;
     a.part = c->d_part.p;
-    a.mom = c->d_mom.p;
-    a.st = c->d_st.p;
+    a.mom = adj ? c->d_mom_adj.p : c->d_mom.p;
+    a.st = adj ? c->d_st_adj.p : c->d_st.p;
     a.ncell = c->ncell;
     a.gq = c->gq;
+    a.force = force;
     return a;
 }
 
-static RecArgs<double> rec_args(dvm_ctx *c)
+static RecArgs<double> rec_args(dvm_ctx *c, bool adj = false)
 {
     RecArgs<double> a{};
+    a.adjoint = adj ? 1 : 0;
     a.inst = c->d_inst.p;
     a.codes = c->d_codes.p;
-    a.mom = c->d_mom.p;
+    a.mom = adj ? c->d_mom_adj.p : c->d_mom.p;
     a.delta_field = c->d_dfield.p;
-    a.u1prev = c->d_u1prev.p;
-    a.srec = c->d_srec.p;
+    a.u1prev = adj ? c->d_u1prev_adj.p : c->d_u1prev.p;
+    a.srec = adj ? c->d_srec_adj.p : c->d_srec.p;
     a.spos = c->d_spos.p;
-    a.st = c->d_st.p;
+    a.st = adj ? c->d_st_adj.p : c->d_st.p;
     a.m0 = c->m0;
     a.m2 = c->m2;
     a.c2 = c->c2;
@@ -487,12 +630,17 @@ static RecArgs<double> rec_args(dvm_ctx *c)
     return a;
 }
 
-static bool any_field(const dvm_ctx *c)
+// sweep mode of the instances being solved: per-cell delta, specular walls
+static int solve_mode(const dvm_ctx *c)
 {
-    for (const auto &h : c->inst)
+    int m = 0;
+    for (const auto &h : c->inst) {
         if (h.field)
-            return true;
-    return false;
+            m |= MODE_FIELD;
+        if (h.alpha < 1.0)
+            m |= MODE_SPEC;
+    }
+    return m;
 }
 
 static int next_event(dvm_ctx *c, hipEvent_t *e)
@@ -526,10 +674,11 @@ static int collect_profile(dvm_ctx *c)
     return DVM_OK;
 }
 
-// One source iteration for every active instance.
-static int enqueue_iteration(dvm_ctx *c)
+// One source iteration for every active instance of the forward or the
+// adjoint problem.
+static int enqueue_iteration(dvm_ctx *c, bool adj)
 {
-    const bool prof = c->cfg.profile != 0;
+    const bool prof = c->cfg.profile != 0 && !adj;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     if (prof) {
         int rc = next_event(c, &e0);
@@ -539,13 +688,14 @@ static int enqueue_iteration(dvm_ctx *c)
             return rc;
         HIPCHK(hipEventRecord(e0, c->stream));
     }
-    HIPCHK(launch_sweep<double>(sweep_args(c, 0), (int)c->items.size(), c->V, c->G, any_field(c),
-                                false, c->stream));
+    const int mode = solve_mode(c) | (adj ? MODE_ADJ : 0);
+    HIPCHK(launch_sweep<double>(sweep_args(c, 0, adj), (int)c->items.size(), c->V, c->G, mode, c->stream));
     if (prof)
         HIPCHK(hipEventRecord(e1, c->stream));
-    HIPCHK(launch_moments(mom_args(c), c->max_cells, c->n_inst, c->stream));
-    HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
-    HIPCHK(launch_status(c->d_st.p, c->n_inst, c->cfg.tol, c->cfg.max_iter, c->stream));
+    HIPCHK(launch_moments(mom_args(c, adj), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(launch_record<double>(rec_args(c, adj), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(launch_status(adj ? c->d_st_adj.p : c->d_st.p, c->n_inst, c->cfg.tol, c->cfg.max_iter,
+                         c->stream));
     if (prof) {
         HIPCHK(hipEventRecord(e2, c->stream));
         c->ev_sweep.emplace_back(e0, e1);
@@ -554,38 +704,68 @@ static int enqueue_iteration(dvm_ctx *c)
     return DVM_OK;
 }
 
-static int enqueue_block(dvm_ctx *c, int iters)
+static int enqueue_block(dvm_ctx *c, int iters, bool adj)
 {
     if (!c->cfg.use_graphs || c->cfg.profile) {
         for (int i = 0; i < iters; ++i) {
-            int rc = enqueue_iteration(c);
+            int rc = enqueue_iteration(c, adj);
             if (rc)
                 return rc;
         }
         return DVM_OK;
     }
-    if (!c->graph || c->graph_iters != iters || c->graph_field != any_field(c)) {
-        if (c->graph) {
-            (void)hipGraphExecDestroy(c->graph);
-            c->graph = nullptr;
+    const int slot = adj ? 1 : 0;
+    const int mode = solve_mode(c);
+    if (!c->graph[slot] || c->graph_iters[slot] != iters || c->graph_mode[slot] != mode) {
+        if (c->graph[slot]) {
+            (void)hipGraphExecDestroy(c->graph[slot]);
+            c->graph[slot] = nullptr;
         }
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         int rc = DVM_OK;
         for (int i = 0; i < iters && rc == DVM_OK; ++i)
-            rc = enqueue_iteration(c);
+            rc = enqueue_iteration(c, adj);
         hipError_t e = hipStreamEndCapture(c->stream, &g);
         if (rc)
             return rc;
         HIPCHK(e);
-        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&c->graph[slot], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIPCHK(e);
-        c->graph_iters = iters;
-        c->graph_field = any_field(c);
+        c->graph_iters[slot] = iters;
+        c->graph_mode[slot] = mode;
     }
-    HIPCHK(hipGraphLaunch(c->graph, c->stream));
+    HIPCHK(hipGraphLaunch(c->graph[slot], c->stream));
     return DVM_OK;
+}
+
+// Replay blocks of iterations until no instance of [i0, i1) is active.
+static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, bool adj,
+                      std::vector<SolveState> &st)
+{
+    const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
+    const long long cap = c->cfg.max_iter;
+    SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
+    for (;;) {
+        int rc = enqueue_block(c, B, adj);
+        if (rc)
+            return rc;
+        HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->cfg.profile) {
+            int prc = collect_profile(c);
+            if (prc)
+                return prc;
+        }
+        bool running = false;
+        for (int i = i0; i < i1; ++i)
+            if (st[i].active && st[i].iter - iter0[i] < cap)
+                running = true;
+        if (!running)
+            return DVM_OK;
+    }
 }
 
 static int check_instance(const dvm_ctx *c, int instance)
@@ -608,8 +788,6 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
         return fail(DVM_EINVAL, "delta is NULL");
     if (!(alpha > 0.0 && alpha <= 1.0))
         return fail(DVM_EINVAL, "alpha must lie in (0, 1]");
-    if (alpha < 1.0)
-        return fail(DVM_EINVAL, "alpha < 1 (Maxwell specular share) is not supported by this build");
     const int i0 = instance < 0 ? 0 : instance, i1 = instance < 0 ? c->n_inst : instance + 1;
     for (int i = i0; i < i1; ++i)
         if (!c->inst[i].has_geom)
@@ -690,6 +868,11 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
                 HIPCHK(launch_zero(c->d_seam.p + c->seam_half + d.seam_off, sn, c->stream));
                 HIPCHK(launch_zero(c->d_wrap.p + d.wrap_off, (size_t)d.nstrips * c->kp4 * 64 * 3,
                                    c->stream));
+                const HostInst &h = c->inst[i];
+                const size_t fh = (size_t)std::max<long long>(c->nfaces, 1) * c->kp4;
+                for (int par = 0; par < 2; ++par)
+                    HIPCHK(launch_zero(c->d_fb.p + par * fh + (size_t)h.face_base * c->kp4,
+                                       (size_t)h.nfaces * c->kp4, c->stream));
                 s = SolveState{};
             }
             s.active = 1;
@@ -717,27 +900,10 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
     for (int i = i0; i < i1; ++i)
         c->inst[i].has_state = true;
 
-    const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
-    const long long cap = c->cfg.max_iter;
-    for (;;) {
-        int rc = enqueue_block(c, B);
+    {
+        int rc = run_blocks(c, i0, i1, iter0, false, st);
         if (rc)
             return rc;
-        HIPCHK(hipMemcpyAsync(st.data(), c->d_st.p, c->n_inst * sizeof(SolveState),
-                              hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (c->cfg.profile) {
-            int prc = collect_profile(c);
-            if (prc)
-                return prc;
-        }
-        bool running = false;
-        for (int i = i0; i < i1; ++i) {
-            if (st[i].active && st[i].iter - iter0[i] < cap)
-                running = true;
-        }
-        if (!running)
-            break;
     }
     int rc = DVM_OK;
     for (int i = i0; i < i1; ++i) {
@@ -750,12 +916,180 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
             o.est_error = s.est;
             o.status = s.status;
         }
+        c->inst[i].converged = s.status == STATUS_CONVERGED;
         if (s.status == STATUS_DIVERGED)
             rc = fail(DVM_EDIVERGED, "instance " + std::to_string(i) + " produced non-finite iterates");
         else if (rc == DVM_OK && s.status != STATUS_CONVERGED)
             rc = fail(DVM_ENOCONV, "instance " + std::to_string(i) + " reached max_iter");
     }
     return rc;
+}
+
+// ------------------------------------------------------------- adjoint
+static int ensure_adjoint(dvm_ctx *c)
+{
+    if (c->adj_ready)
+        return DVM_OK;
+    const long long sk = c->sk_total, cell = c->ncell, nf = std::max<long long>(c->nfaces, 1);
+    HIPCHK(c->d_scode_adj.alloc(sk));
+    HIPCHK(c->d_sface_adj.alloc(sk));
+    HIPCHK(c->d_face_cell.alloc(nf));
+    HIPCHK(c->d_face_side.alloc(nf));
+    HIPCHK(c->d_face_inst.alloc(nf));
+    HIPCHK(c->d_srec_adj.alloc(sk * REC_STRIDE));
+    HIPCHK(c->d_mom_adj.alloc(cell * MOM_STRIDE));
+    HIPCHK(c->d_u1prev_adj.alloc(cell));
+    HIPCHK(c->d_seam_adj.alloc(2 * c->seam_half));
+    HIPCHK(c->d_wrap_adj.alloc(c->wrap_total));
+    HIPCHK(c->d_fb_adj.alloc((size_t)2 * nf * c->kp4));
+    HIPCHK(c->d_ckpt.alloc((size_t)cell * c->kp4));
+    HIPCHK(c->d_momg.alloc(cell * MOM_STRIDE));
+    HIPCHK(c->d_dqda.alloc(nf));
+    HIPCHK(c->d_st_adj.alloc(c->n_inst));
+    HIPCHK(hipMemcpyAsync(c->d_scode_adj.p, c->h_scode_adj.data(), sk, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_sface_adj.p, c->h_sface_adj.data(), sk * sizeof(FaceRec), hipMemcpyHostToDevice,
+                          c->stream));
+    if (c->nfaces > 0) {
+        HIPCHK(hipMemcpyAsync(c->d_face_cell.p, c->h_face_cell.data(), c->nfaces * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->d_face_side.p, c->h_face_side.data(), c->nfaces * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->d_face_inst.p, c->h_face_inst.data(), c->nfaces * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(launch_zero(c->d_srec_adj.p, c->d_srec_adj.n, c->stream));
+    HIPCHK(launch_zero(c->d_ckpt.p, c->d_ckpt.n, c->stream));
+    std::vector<SolveState> st(c->n_inst);
+    HIPCHK(hipMemcpyAsync(c->d_st_adj.p, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->adj_ready = true;
+    return DVM_OK;
+}
+
+// Discrete adjoint of the flow rate at the converged state of one instance:
+//  1. one more forward sweep that keeps h (all velocities) and the incident
+//     wall-face values, and the moments of that h;
+//  2. source iteration of the transposed problem for nu(c, v) =
+//     lambda(c, -v) / W(v), driven by -(dx / nx) xi -- the same sweeps with
+//     transposed stencil weights and wall couplings;
+//  3. one more adjoint sweep that accumulates sum_v W nu h(-v) per cell and
+//     keeps nu on the wall faces; then the per-cell and per-face assembly.
+static int grad_instance(dvm_ctx *c, int instance, double *dqdd_out, double *dqda_out)
+{
+    int rc = ensure_adjoint(c);
+    if (rc)
+        return rc;
+    const HostInst &h = c->inst[instance];
+    const InstDev &d = c->idev[instance];
+    const size_t n = (size_t)d.nx * d.ny;
+    const size_t fh = (size_t)std::max<long long>(c->nfaces, 1) * c->kp4;
+    std::vector<WorkItem> mine;
+    for (const auto &it : c->items)
+        if (it.inst == instance)
+            mine.push_back(it);
+    DevBuf<WorkItem> ditems;
+    HIPCHK(ditems.alloc(mine.size()));
+    HIPCHK(hipMemcpyAsync(ditems.p, mine.data(), mine.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                          c->stream));
+    const int base = (h.field ? MODE_FIELD : 0) | (h.alpha < 1.0 ? MODE_SPEC : 0);
+    std::vector<SolveState> st(c->n_inst);
+    HIPCHK(hipMemcpyAsync(st.data(), c->d_st.p, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int par_f = (int)(st[instance].iter & 1);
+
+    // 1. forward checkpoint
+    {
+        SweepArgs<double> a = sweep_args(c, 1, false);
+        a.items = ditems.p;
+        HIPCHK(launch_sweep<double>(a, (int)mine.size(), c->V, c->G, MODE_CKPT | base, c->stream));
+        MomArgs m = mom_args(c, false, 1);
+        m.mom = c->d_momg.p;
+        HIPCHK(launch_moments(m, c->max_cells, c->n_inst, c->stream));
+    }
+    // 2. adjoint source iteration (cold start)
+    HIPCHK(launch_zero(c->d_mom_adj.p + d.cell_off * MOM_STRIDE, n * MOM_STRIDE, c->stream));
+    HIPCHK(launch_zero(c->d_u1prev_adj.p + d.cell_off, n, c->stream));
+    {
+        size_t sn = (size_t)d.nstrips * d.nx * 2 * c->kp4;
+        HIPCHK(launch_zero(c->d_seam_adj.p + d.seam_off, sn, c->stream));
+        HIPCHK(launch_zero(c->d_seam_adj.p + c->seam_half + d.seam_off, sn, c->stream));
+        HIPCHK(launch_zero(c->d_wrap_adj.p + d.wrap_off, (size_t)d.nstrips * c->kp4 * 64 * 3, c->stream));
+        for (int par = 0; par < 2; ++par)
+            HIPCHK(launch_zero(c->d_fb_adj.p + par * fh + (size_t)h.face_base * c->kp4,
+                               (size_t)h.nfaces * c->kp4, c->stream));
+    }
+    std::vector<SolveState> sa(c->n_inst);
+    sa[instance].active = 1;
+    sa[instance].status = STATUS_RUNNING;
+    HIPCHK(hipMemcpyAsync(c->d_st_adj.p, sa.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(launch_record<double>(rec_args(c, true), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_st_adj.p, sa.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                          c->stream));
+    {
+        std::vector<long long> iter0(c->n_inst, 0);
+        rc = run_blocks(c, instance, instance + 1, iter0, true, sa);
+        if (rc)
+            return rc;
+    }
+    if (sa[instance].status == STATUS_DIVERGED)
+        return fail(DVM_EDIVERGED, "adjoint iteration produced non-finite iterates");
+    if (sa[instance].status != STATUS_CONVERGED)
+        return fail(DVM_ENOCONV, "adjoint iteration reached max_iter");
+    const int par_a = (int)(sa[instance].iter & 1);
+
+    // 3. gradient sweep and assembly
+    {
+        SweepArgs<double> a = sweep_args(c, 1, true);
+        a.items = ditems.p;
+        HIPCHK(launch_sweep<double>(a, (int)mine.size(), c->V, c->G, MODE_ADJ | MODE_GRAD | base, c->stream));
+        HIPCHK(launch_moments(mom_args(c, true, 1), c->max_cells, c->n_inst, c->stream));
+    }
+    GradArgs g{};
+    g.inst = c->d_inst.p;
+    g.codes = c->d_codes.p;
+    g.mom_fwd = c->d_momg.p;
+    g.mom_adj = c->d_mom_adj.p;
+    g.part5 = c->d_part5.p;
+    g.dqdd = c->d_aux.p;
+    g.face_cell = c->d_face_cell.p;
+    g.face_side = c->d_face_side.p;
+    g.face_inst = c->d_face_inst.p;
+    g.fb_fwd = c->d_fb.p + par_f * fh;
+    g.fb_adj = c->d_fb_adj.p + par_a * fh;
+    g.vtab = c->d_vt.p;
+    g.dqda_face = c->d_dqda.p;
+    g.ncell = c->ncell;
+    g.ngroups = 4 * c->gq;
+    g.kq = c->kq;
+    g.kp4 = c->kp4;
+    g.face0 = (int)h.face_base;
+    g.nfaces = h.nfaces;
+    g.m0 = c->m0;
+    g.m2 = c->m2;
+    g.c2 = c->c2;
+    g.c4 = c->c4;
+    g.D = c->D;
+    HIPCHK(launch_grad(g, instance, (int)n, c->stream));
+    std::vector<double> dqdd(n), dqda(h.nfaces);
+    HIPCHK(hipMemcpyAsync(dqdd.data(), c->d_aux.p + d.cell_off, n * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    if (h.nfaces > 0)
+        HIPCHK(hipMemcpyAsync(dqda.data(), c->d_dqda.p + h.face_base, h.nfaces * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ditems.release();
+    if (dqdd_out)
+        std::copy(dqdd.begin(), dqdd.end(), dqdd_out);
+    if (dqda_out) {
+        double sum = 0.0;
+        for (double v : dqda)
+            sum += v;
+        *dqda_out = sum;
+    }
+    return DVM_OK;
 }
 
 // ================================================================ C ABI
@@ -789,6 +1123,8 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
         return fail(DVM_EINVAL, "max_iter must be > 0");
     if (c.block_iters < 0 || c.block_iters > 4096)
         return fail(DVM_EINVAL, "block_iters must be in [0, 4096]");
+    if (c.schedule != DVM_SCHED_SKEW && c.schedule != DVM_SCHED_WRAP)
+        return fail(DVM_EINVAL, "unknown schedule");
     int V = c.vel_per_lane ? c.vel_per_lane : 4;
     int G = c.waves_per_block ? c.waves_per_block : 8;
     bool okvg = (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) || (V == 2 && G == 8);
@@ -913,9 +1249,10 @@ int dvm_get_moments(const dvm_ctx *cc, int instance, double *rho, double *u1, do
         HIPCHK(hipMemcpyAsync(ditems.p, mine.data(), mine.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
                               ctx->stream));
         a.items = ditems.p;
-        HIPCHK(launch_sweep<double>(a, (int)mine.size(), ctx->V, ctx->G, h.field, true, ctx->stream));
+        const int mode = MODE_P12 | (h.field ? MODE_FIELD : 0) | (h.alpha < 1.0 ? MODE_SPEC : 0);
+        HIPCHK(launch_sweep<double>(a, (int)mine.size(), ctx->V, ctx->G, mode, ctx->stream));
         MomArgs m = mom_args(ctx);
-        HIPCHK(launch_sum1(m, ctx->d_aux.p, ctx->max_cells, ctx->n_inst, ctx->stream));
+        HIPCHK(launch_sum1(m, ctx->d_part5.p, ctx->d_aux.p, 2.0, ctx->max_cells, ctx->n_inst, ctx->stream));
         shear.resize(n);
         HIPCHK(hipMemcpyAsync(shear.data(), ctx->d_aux.p + d.cell_off, n * sizeof(double),
                               hipMemcpyDeviceToHost, ctx->stream));
@@ -950,9 +1287,10 @@ int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha)
     int rc = check_instance(ctx, instance);
     if (rc)
         return rc;
-    (void)dQ_ddelta;
-    (void)dQ_dalpha;
-    return fail(DVM_ESTATE, "the adjoint is not available in this build");
+    const HostInst &h = ctx->inst[instance];
+    if (!ctx->layout_ok || !h.has_state || !h.converged)
+        return fail(DVM_ESTATE, "instance has no converged solution (call dvm_solve first)");
+    return grad_instance(ctx, instance, dQ_ddelta, dQ_dalpha);
 }
 
 int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms)

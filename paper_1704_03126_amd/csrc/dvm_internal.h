@@ -8,13 +8,33 @@
 
 namespace dvm {
 
-// sides of a cell, and the per-side stencil code (2 bits each in a byte:
-// bits 2d..2d+1 for side d).  A solid cell has code byte 0xFF.
+// sides of a cell, and the per-side stencil code of the forward problem
+// (2 bits each in a byte: bits 2d..2d+1 for side d).  A solid cell has code
+// byte 0xFF.
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 enum { CODE_INT = 0, CODE_NEAR = 1, CODE_WALL = 2, CODE_NONE = 3 };
-// reciprocal-diagonal variants: bit 1 = wall on the x upwind side, bit 0 =
-// wall on the y upwind side; 4 = solid / no cell
+// reciprocal-diagonal variants: bit 1 = x diagonal weight 1 (else 1.5),
+// bit 0 = same for y; 4 = no cell
 enum { NSTENCIL = 5, STENCIL_SOLID = 4 };
+
+// Per-axis stencil nibble of a sweep entry (low nibble x, high nibble y).
+// Each nibble indexes a table of (w1, w2, diagonal weight 1?) so that the
+// sweep evaluates  diag * h = ... + c (w1 h_1 + w2 h_2 + face term).
+//   0..3  forward codes: INT (2, -0.5, 1.5), NEAR (1.5, 0, 1.5),
+//         WALL (0, 0, 1), NONE (0, 0, -)
+//   4..15 adjoint (transposed) stencils: 4 + 6*ai + 2*pi + qi with diagonal
+//         weight {1.5, 1}[ai], w1 {2, 1.5, 0}[pi], w2 {-0.5, 0}[qi]
+enum { NIB_ADJ0 = 4, NNIB = 16 };
+
+// sweep modes (template bit flags)
+enum {
+    MODE_FIELD = 1,   // delta per cell (one reciprocal per update)
+    MODE_SPEC = 2,    // alpha < 1: Maxwell specular share through face buffers
+    MODE_ADJ = 4,     // adjoint sweep (face buffers receive cell values)
+    MODE_P12 = 8,     // diagnostic pass: shear stress only, no state written
+    MODE_CKPT = 16,   // forward pass that also stores h and the face values
+    MODE_GRAD = 32,   // adjoint pass that also accumulates sum W nu h(-v)
+};
 
 // per-velocity constants, VT_STRIDE values per velocity, velocities ordered
 // by quadrant (q = 0: xi>0,eta>0; 1: xi<0,eta>0; 2: xi>0,eta<0; 3: both <0)
@@ -71,21 +91,34 @@ struct SolveState {
     unsigned long long maxdiff_bits, maxabs_bits;
 };
 
+// face record of a sweep entry (alpha < 1 and the gradient): faces whose
+// buffer is read on the x / y upwind side (with weight kx / ky), and the
+// cell's own faces on the x / y downstream side that receive values
+struct FaceRec {
+    int rdx, rdy, wrx, wry;
+    float kx, ky, pad0, pad1;
+};
+
 template <typename T>
 struct SweepArgs {
     const InstDev *inst;
     const WorkItem *items;
     const T *srec;            // skewed records [entry][REC_STRIDE]
-    const uint8_t *scode;     // skewed stencil codes [entry]
-    const int *smap;          // skewed entry -> cell of the instance, -1 none
+    const uint8_t *scode;     // skewed stencil nibbles [entry]
+    const int *smap;          // skewed entry -> fluid cell of the instance, -1 none
+    const FaceRec *sface;     // skewed face records [entry] (MODE_SPEC/CKPT/GRAD)
+    T *fb;                    // wall-face values [2][fb_half]: [parity][face][kp4]
+    double *ckpt;             // checkpoint h [cell][kp4] (MODE_CKPT writes, MODE_GRAD reads)
+    double *part5;            // extra partial [group][ncell] (P12 / gradient)
     const T *vtab;            // [inst][kp4][VT_STRIDE]
     const double *delta_field;
     double *part;             // [group][ncell][4]   (final pass: [group][ncell])
     T *seam;                  // [2][seam_half]
-    T *wrap;
+    T *wrap;                  // [strip][3][kp4][64] per instance
     SolveState *st;
     long long ncell;          // total cells over all instances
     long long seam_half;
+    long long fb_half;
     int gq;                   // velocity groups per quadrant
     int kq;                   // padded velocities per quadrant (= gq * G * V)
     int kp4;                  // 4 * kq
@@ -100,10 +133,12 @@ struct MomArgs {
     SolveState *st;
     long long ncell;
     int gq;
+    int force;                // also for instances that are not iterating
 };
 
 template <typename T>
 struct RecArgs {
+    int adjoint;              // wall terms of the transposed problem
     const InstDev *inst;
     const uint8_t *codes;
     const double *mom;
@@ -116,10 +151,33 @@ struct RecArgs {
 };
 
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, bool field,
-                        bool final_pass, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, int mode, hipStream_t s);
 hipError_t launch_moments(const MomArgs &a, int max_cells, int n_inst, hipStream_t s);
-hipError_t launch_sum1(const MomArgs &a, double *out, int max_cells, int n_inst, hipStream_t s);
+// out[cell] = scale * sum over velocity groups of part5[group][cell]
+hipError_t launch_sum1(const MomArgs &a, const double *part5, double *out, double scale, int max_cells,
+                       int n_inst, hipStream_t s);
+
+// gradient assembly at one instance: per cell dQ/d delta, per wall face
+// the part of dQ/d alpha
+struct GradArgs {
+    const InstDev *inst;
+    const uint8_t *codes;
+    const double *mom_fwd;    // forward moments [cell][MOM_STRIDE]
+    const double *mom_adj;    // adjoint moments [cell][MOM_STRIDE]
+    const double *part5;      // [group][ncell] sum W nu h(-v) per group
+    double *dqdd;             // [cell]
+    const int *face_cell;     // [face] cell (global index)
+    const int *face_side;     // [face]
+    const int *face_inst;     // [face]
+    const double *fb_fwd;     // forward incident face values [face][kp4]
+    const double *fb_adj;     // adjoint cell values at incident velocities [face][kp4]
+    const double *vtab;       // [inst][kp4][VT_STRIDE]
+    double *dqda_face;        // [face]
+    long long ncell;
+    int ngroups, kq, kp4, face0, nfaces;
+    double m0, m2, c2, c4, D;
+};
+hipError_t launch_grad(const GradArgs &a, int instance, int ncells, hipStream_t s);
 template <typename T>
 hipError_t launch_record(const RecArgs<T> &a, int max_cells, int n_inst, hipStream_t s);
 hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, hipStream_t s);

@@ -5,21 +5,21 @@
 //
 //   k_sweep   One workgroup = one (instance, strip of <= 64 rows, velocity
 //             group of G*V velocities of one quadrant).  Lane l of every wave
-//             owns grid row l of the strip; the wave marches x on a skewed,
-//             wrap-around diagonal (lane l treats x = (t - l) mod nx at step
-//             t), so the upwind neighbours of a cell are the lane's own two
-//             previous results (x direction) and the results of lanes l-1,
-//             l-2 one and two steps earlier (y direction, moved with DPP
-//             wave_shr).  Each lane carries V velocities at once; velocity
-//             constants are wave-uniform.  Grids narrower than WRAP_MIN
-//             use a skewed schedule without wrap-around (lane l treats x at
-//             step x + l), which lags only the periodic seam.  The
-//             perturbation h is never
-//             written to memory: the lane accumulates the quadrature moments
-//             of its V velocities, the G waves of the group add theirs in
-//             LDS, and the group writes one partial per cell.  Values that
-//             cross a strip boundary or the wrap-around diagonal come from
-//             the previous iteration (seam and wrap buffers).
+//             owns grid row l of the strip; the wave marches x on a skewed
+//             diagonal (lane l treats x = t - l at step t, x counted from the
+//             upwind side), so the upwind neighbours of a cell are the lane's
+//             own two previous results (x direction) and the results of
+//             lanes l-1, l-2 one and two steps earlier (y direction, moved
+//             with DPP wave_shr).  Only values that cross the periodic x seam
+//             or a strip boundary come from the previous iteration (wrap and
+//             seam buffers).  The optional wrap-around schedule (x = (t - l)
+//             mod nx) saves the 63 fill steps but also lags the y coupling of
+//             every lane's first cell.  Each lane carries V velocities at
+//             once; velocity constants are wave-uniform.  The perturbation h
+//             is never written to memory (except by the checkpoint pass of
+//             the gradient): the lane accumulates the quadrature moments of
+//             its V velocities, the G waves of the group add theirs in LDS,
+//             and the group writes one partial per cell.
 //   k_moments sums the partials of all velocity groups per cell (fixed order,
 //             deterministic): rho, u1, u2, e and the four half-range fluxes.
 //   k_record  builds the next sweep's per-cell record: the collision gain of
@@ -93,64 +93,33 @@ __device__ __forceinline__ T ldc(cptr<T> p, int i)
 // y-upwind value are pure renaming inside a chunk.
 constexpr int SWEEP_C = 6;
 
-// One velocity of one step for one lane (see k_sweep).  xa: the lane has a
-// cell at this step (false keeps the registers, used off the lane's window).
-template <typename T, bool FIELD, bool FINAL, bool HOLD>
-__device__ __forceinline__ void sweep_update(
-    T &p1, T &p2, T &pn, T &hs1p, T &hs1n, T &hout, double *acc,
-    T sm1, T sm2, T b0, T b1, T b2, T b3, T gx, T gy, T px, T qx, T py, T qy,
-    T rinv_or_dl, T ax, T ay, bool solid, bool xa,
-    T xi, T eta, T qq, T cx, T cy, double w, double wxi, double weta, double wq)
-{
-    const T hS1 = dpp_shr1(sm1, p1);
-    const T hS2 = dpp_shr1(sm2, hs1p);
-    const T S = fma(b3, qq, fma(b2, eta, fma(b1, xi, b0)));
-    const T ux = fma(px, p1, fma(qx, p2, gx));
-    const T uy = fma(py, hS1, fma(qy, hS2, gy));
-    const T g = fma(cx, ux, fma(cy, uy, S));
-    T rinv;
-    if (FIELD) {
-        const T den = fma(ax, cx, fma(ay, cy, rinv_or_dl));
-        rinv = (solid || w == 0.0) ? T(0) : rcp_full(den);
-    } else {
-        rinv = rinv_or_dl;
-    }
-    const T h = g * rinv;
-    const double hd = (double)h;
-    if (FINAL) {
-        acc[0] = fma(wxi * (double)eta, hd, acc[0]);
-    } else {
-        acc[0] = fma(w, hd, acc[0]);
-        acc[1] = fma(wxi, hd, acc[1]);
-        acc[2] = fma(weta, hd, acc[2]);
-        acc[3] = fma(wq, hd, acc[3]);
-    }
-    hout = h;
-    if (HOLD) {
-        // keep prev1/prev2/hs1 when the lane has no cell at this step
-        pn = xa ? h : p1;
-        p1 = xa ? p1 : p2;        // becomes prev2 of the next step
-        hs1n = xa ? hS1 : hs1p;
-    } else {
-        pn = h;
-        hs1n = hS1;
-    }
-}
-
-template <typename T, int V, int G, bool FIELD, bool FINAL>
+template <typename T, int V, int G, int MODE>
 __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
 {
+    constexpr bool FIELD = (MODE & MODE_FIELD) != 0;
+    constexpr bool SPEC = (MODE & MODE_SPEC) != 0;
+    constexpr bool ADJ = (MODE & MODE_ADJ) != 0;
+    constexpr bool P12 = (MODE & MODE_P12) != 0;
+    constexpr bool CKPT = (MODE & MODE_CKPT) != 0;
+    constexpr bool GRAD = (MODE & MODE_GRAD) != 0;
+    constexpr bool FACES = SPEC || CKPT || GRAD;          // face records needed
+    constexpr bool FBWRITE = (SPEC || CKPT || GRAD) && !P12;
     constexpr int C = SWEEP_C;                 // steps per chunk
-    constexpr int NM = FINAL ? 1 : 4;          // moments accumulated
+    // moments gathered: 4 (rho, u1, u2, e) and an extra one (P12 or gradient)
+    constexpr int NACC = P12 ? 1 : (GRAD ? 5 : 4);
+    // steps per partial flush: the whole chunk unless LDS is short
+    constexpr int FL = (FACES || NACC > 4 || G > 8) ? C / 2 : C;
     constexpr int P = G * V;                   // velocities of the group
     constexpr int UPE = 8 * sizeof(T) / 16;    // 16-byte units per record
     __shared__ __attribute__((aligned(16))) T st_rec[2][C][64][8];
     __shared__ uint8_t st_code[2][C][64];
     __shared__ int st_cell[2][C][64];
     __shared__ __attribute__((aligned(16))) T st_seam[2][C][2][P];
-    __shared__ double lds_part[C][G][64][NM];
+    __shared__ __attribute__((aligned(16))) FaceRec st_face[FACES ? 2 : 1][FACES ? C : 1][64];
+    __shared__ double lds_part[FL][G][64][NACC];
     __shared__ T lds_rinv[P][NSTENCIL];
-    __shared__ __attribute__((aligned(16))) T lds_pq[4][2];
+    __shared__ T lds_lut[NNIB][2];
+    __shared__ int lds_aone[NNIB];
 
     const WorkItem it = a.items[blockIdx.x];
     const InstDev in = a.inst[it.inst];
@@ -162,6 +131,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = it.group / a.gq;
     const bool xpos = (q & 1) == 0, ypos = (q & 2) == 0;
+    const int idx0 = (it.group % a.gq) * P + wave * V;  // index in the quadrant
     const int kq0 = q * a.kq + (it.group % a.gq) * P;   // first velocity of the group
     const int kw = kq0 + wave * V;                      // first velocity of this wave
     cptr<T> vt = (cptr<T>)(a.vtab + (size_t)it.inst * a.kp4 * VT_STRIDE);
@@ -175,6 +145,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     const T *__restrict__ srec = a.srec + ebase * 8;
     const uint8_t *__restrict__ scode = a.scode + ebase;
     const int *__restrict__ smap = a.smap + ebase;
+    const FaceRec *__restrict__ sface = FACES ? a.sface + ebase : nullptr;
 
     if (!FIELD) {
         for (int e = tid; e < P * NSTENCIL; e += 64 * G) {
@@ -186,9 +157,24 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             lds_rinv[v][ci] = (ci == STENCIL_SOLID || w == T(0) || den == T(0)) ? T(0) : T(1) / den;
         }
     }
-    if (tid < 4) {
-        lds_pq[tid][0] = tid == CODE_INT ? T(2) : (tid == CODE_NEAR ? T(1.5) : T(0));
-        lds_pq[tid][1] = tid == CODE_INT ? T(-0.5) : T(0);
+    if (tid < NNIB) {
+        T w1 = T(0), w2 = T(0);
+        int one = 0;
+        if (tid == CODE_INT) {
+            w1 = T(2); w2 = T(-0.5);
+        } else if (tid == CODE_NEAR) {
+            w1 = T(1.5);
+        } else if (tid == CODE_WALL) {
+            one = 1;
+        } else if (tid >= NIB_ADJ0) {
+            const int r = tid - NIB_ADJ0, ai = r / 6, pi = (r / 2) % 3, qi = r % 2;
+            w1 = pi == 0 ? T(2) : (pi == 1 ? T(1.5) : T(0));
+            w2 = qi == 0 ? T(-0.5) : T(0);
+            one = ai;
+        }
+        lds_lut[tid][0] = w1;
+        lds_lut[tid][1] = w2;
+        lds_aone[tid] = one;
     }
 
     const bool has_up = ypos ? (it.strip > 0 || in.periodic_y)
@@ -199,16 +185,24 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     const size_t seam_row = (size_t)2 * a.kp4;
     const T *seam_in = a.seam + (size_t)par_r * a.seam_half + in.seam_off + (size_t)s_up * nx * seam_row;
     T *seam_out = a.seam + (size_t)par_w * a.seam_half + in.seam_off + (size_t)it.strip * nx * seam_row;
+    const T *fb_rd = FACES ? a.fb + (size_t)par_r * a.fb_half : nullptr;
+    T *fb_wr = FACES ? a.fb + (size_t)par_w * a.fb_half : nullptr;
     const bool x_coupled = nx > 1;
+    const T spec = T(1.0 - in.alpha);
+    // mirrored velocities (first of this wave) across x- and y-normal faces
+    const int kmx = (q ^ 1) * a.kq + idx0, kmy = (q ^ 2) * a.kq + idx0;
+    const int krev = (q ^ 3) * a.kq + idx0;   // reversed velocity (gradient)
 
-    // ---- staging of one chunk of steps into LDS buffer b (global loads are
-    //      issued into registers first and stored after the current chunk)
+    // ---- staging of one chunk of steps into LDS buffer b
     constexpr int REC_UNITS = C * 64 * UPE;
     constexpr int RU_PER_T = (REC_UNITS + 64 * G - 1) / (64 * G);
     constexpr int SEAM_VALS = C * 2 * P;
     constexpr int SV_PER_T = (SEAM_VALS + 64 * G - 1) / (64 * G);
     constexpr int CC_PER_T = (C * 64 + 64 * G - 1) / (64 * G);
+    constexpr int FR_UNITS = FACES ? C * 64 * 2 : 0;     // 16-byte units
+    constexpr int FR_PER_T = FACES ? (FR_UNITS + 64 * G - 1) / (64 * G) : 1;
     uint4 ru[RU_PER_T];
+    uint4 fu[FR_PER_T];
     T sv[SV_PER_T];
     int cc[CC_PER_T];
     uint8_t cb[CC_PER_T];
@@ -221,11 +215,24 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             if (u < REC_UNITS && t0 + (u / UPE) / 64 < tp)
                 ru[r] = reinterpret_cast<const uint4 *>(srec + ((size_t)t0 * 64) * 8)[u];
         }
+        if (FACES) {
+#pragma unroll
+            for (int r = 0; r < FR_PER_T; ++r) {
+                const int u = tid + r * 64 * G;
+                fu[r] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+                if (u < FR_UNITS) {
+                    if (t0 + (u / 2) / 64 < tp)
+                        fu[r] = reinterpret_cast<const uint4 *>(sface + (size_t)t0 * 64)[u];
+                    else if (u & 1)
+                        fu[r] = make_uint4(0, 0, 0, 0);
+                }
+            }
+        }
 #pragma unroll
         for (int r = 0; r < CC_PER_T; ++r) {
             const int e = tid + r * 64 * G;
             cc[r] = -1;
-            cb[r] = 0x1F;
+            cb[r] = 0xFF;
             if (e < C * 64 && t0 + e / 64 < tp) {
                 cc[r] = smap[(size_t)t0 * 64 + e];
                 cb[r] = scode[(size_t)t0 * 64 + e];
@@ -251,6 +258,14 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             const int u = tid + r * 64 * G;
             if (u < REC_UNITS)
                 reinterpret_cast<uint4 *>(&st_rec[b][0][0][0])[u] = ru[r];
+        }
+        if (FACES) {
+#pragma unroll
+            for (int r = 0; r < FR_PER_T; ++r) {
+                const int u = tid + r * 64 * G;
+                if (u < FR_UNITS)
+                    reinterpret_cast<uint4 *>(&st_face[b][0][0])[u] = fu[r];
+            }
         }
 #pragma unroll
         for (int r = 0; r < CC_PER_T; ++r) {
@@ -288,12 +303,14 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     // rotating registers: x-upwind values A (prev1), B (prev2), X (free);
     // y-upwind chain H0 (current hs1), H1 (free)
     T rA[V], rB[V], rX[V], rH0[V], rH1[V];
-    T *wrapp = a.wrap + in.wrap_off + (((size_t)it.strip * (a.kp4 / V) + kw / V) * 64 + lane) * (3 * V);
+    // wrap state [strip][slot][velocity][lane]: independent of V and G
+    T *wrapp = a.wrap + in.wrap_off + ((size_t)it.strip * 3 * a.kp4 + kw) * 64 + lane;
+    const size_t wslot = (size_t)a.kp4 * 64;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        rA[v] = x_coupled ? wrapp[v] : T(0);
-        rB[v] = x_coupled ? wrapp[V + v] : T(0);
-        rH0[v] = x_coupled ? wrapp[2 * V + v] : T(0);
+        rA[v] = x_coupled ? wrapp[v * 64] : T(0);
+        rB[v] = x_coupled ? wrapp[wslot + v * 64] : T(0);
+        rH0[v] = x_coupled ? wrapp[2 * wslot + v * 64] : T(0);
         rX[v] = T(0);
         rH1[v] = T(0);
     }
@@ -301,75 +318,139 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     const long long cbase = in.cell_off;
     const int nchunks = (tp + C - 1) / C;
     const bool skew = tp != nx;
-    // x position (in sweep order) of this lane's cell at the chunk start
     int xr0 = (tp - (lane % tp)) % tp;
 
     issue(0);
     commit(0);
     __syncthreads();
 
-    // one step: s-th step of the chunk in buffer b; (PA, PB, PX) and (HA, HB)
-    // are the register roles of this step in the rotation
+    // one step (s-th of the chunk in buffer b); (PA, PB, PX) and (HA, HB) are
+    // the register roles of this step in the rotation; hold: keep the
+    // registers when the lane has no cell at this step (xa false)
     auto step = [&](int b, int s, int t, T *PA, T *PB, T *PX, T *HA, T *HB, bool hold, bool xa) {
-        double acc[NM];
+        const int sl = s % FL;
+        double acc[NACC];
 #pragma unroll
-        for (int m = 0; m < NM; ++m)
+        for (int m = 0; m < NACC; ++m)
             acc[m] = 0.0;
         const T *rec = &st_rec[b][s][lane][0];
         const int code = st_code[b][s][lane];
-        const int cxc = code & 3, cyc = (code >> 2) & 3;
-        const bool solid = (code >> 4) != 0;
+        const int cl = st_cell[b][s][lane];
+        const int xn = code & 15, yn = code >> 4;
+        const bool solid = cl < 0;
         const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
         const T gx = rec[4], gy = rec[5];
-        const T px = lds_pq[cxc][0], qx = lds_pq[cxc][1];
-        const T py = lds_pq[cyc][0], qy = lds_pq[cyc][1];
-        const int ci = solid ? STENCIL_SOLID : ((cxc == CODE_WALL) ? 2 : 0) + ((cyc == CODE_WALL) ? 1 : 0);
-        T ax = T(0), ay = T(0), rdl[V];
+        const T px = lds_lut[xn][0], qx = lds_lut[xn][1];
+        const T py = lds_lut[yn][0], qy = lds_lut[yn][1];
+        const int aox = lds_aone[xn], aoy = lds_aone[yn];
+        const int ci = solid ? STENCIL_SOLID : 2 * aox + aoy;
+        T ax = T(0), ay = T(0), dl = T(0);
         if (FIELD) {
-            ax = (cxc == CODE_WALL) ? T(1) : T(1.5);
-            ay = (cyc == CODE_WALL) ? T(1) : T(1.5);
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                rdl[v] = rec[6];
-        } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                rdl[v] = lds_rinv[wave * V + v][ci];
+            ax = aox ? T(1) : T(1.5);
+            ay = aoy ? T(1) : T(1.5);
+            dl = rec[6];
         }
-        T sm1[V], sm2[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            sm1[v] = has_up ? st_seam[b][s][1][wave * V + v] : T(0);
-            sm2[v] = has_up ? st_seam[b][s][0][wave * V + v] : T(0);
-        }
+        FaceRec fr;
+        if (FACES)
+            fr = st_face[b][s][lane];
         T hout[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            if (hold)
-                sweep_update<T, FIELD, FINAL, true>(PA[v], PB[v], PX[v], HA[v], HB[v], hout[v], acc,
-                                                    sm1[v], sm2[v], b0, b1, b2, b3, gx, gy, px, qx, py, qy,
-                                                    rdl[v], ax, ay, solid, xa, cxi[v], ceta[v], cqq[v],
-                                                    ccx[v], ccy[v], cw[v], cwxi[v], cweta[v], cwq[v]);
-            else
-                sweep_update<T, FIELD, FINAL, false>(PA[v], PB[v], PX[v], HA[v], HB[v], hout[v], acc,
-                                                     sm1[v], sm2[v], b0, b1, b2, b3, gx, gy, px, qx, py, qy,
-                                                     rdl[v], ax, ay, solid, xa, cxi[v], ceta[v], cqq[v],
-                                                     ccx[v], ccy[v], cw[v], cwxi[v], cweta[v], cwq[v]);
-        }
-        // the last two rows of the strip feed the next strip next iteration
-        if (!FINAL && has_down && t < tp && lane >= hs - 2 && lane < hs) {
-            const int cl = st_cell[b][s][lane];
-            if (cl >= 0) {
-                const int slot = lane - (hs - 2);
-                T *sp = seam_out + (size_t)(cl % nx) * seam_row + (size_t)slot * a.kp4 + kw;
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-                    sp[v] = hout[v];
+            const T p1 = PA[v], p2 = PB[v], h1 = HA[v];
+            const T sm1 = has_up ? st_seam[b][s][1][wave * V + v] : T(0);
+            const T sm2 = has_up ? st_seam[b][s][0][wave * V + v] : T(0);
+            const T hS1 = dpp_shr1(sm1, p1);
+            const T hS2 = dpp_shr1(sm2, h1);
+            T gxv = gx, gyv = gy;
+            if (SPEC) {
+                // Maxwell's specular share: mirrored value of the previous iterate
+                if (fr.rdx >= 0)
+                    gxv = fma(T(fr.kx) * spec, fb_rd[(size_t)fr.rdx * a.kp4 + kmx + v], gxv);
+                if (fr.rdy >= 0)
+                    gyv = fma(T(fr.ky) * spec, fb_rd[(size_t)fr.rdy * a.kp4 + kmy + v], gyv);
+            }
+            const T S = fma(b3, cqq[v], fma(b2, ceta[v], fma(b1, cxi[v], b0)));
+            const T ux = fma(px, p1, fma(qx, p2, gxv));
+            const T uy = fma(py, hS1, fma(qy, hS2, gyv));
+            const T g = fma(ccx[v], ux, fma(ccy[v], uy, S));
+            T rinv;
+            if (FIELD) {
+                const T den = fma(ax, ccx[v], fma(ay, ccy[v], dl));
+                rinv = (solid || cw[v] == 0.0) ? T(0) : rcp_full(den);
+            } else {
+                rinv = lds_rinv[wave * V + v][ci];
+            }
+            const T h = g * rinv;
+            const double hd = (double)h;
+            if (P12) {
+                acc[0] = fma(cwxi[v] * (double)ceta[v], hd, acc[0]);
+            } else {
+                acc[0] = fma(cw[v], hd, acc[0]);
+                acc[1] = fma(cwxi[v], hd, acc[1]);
+                acc[2] = fma(cweta[v], hd, acc[2]);
+                acc[3] = fma(cwq[v], hd, acc[3]);
+                if (GRAD && !solid)
+                    acc[4] = fma(cw[v], hd * a.ckpt[((size_t)cbase + cl) * a.kp4 + krev + v], acc[4]);
+            }
+            if (FBWRITE && !solid && xa) {
+                // values this cell sends through its downstream wall faces:
+                // forward -- the reconstructed incident face value;
+                // adjoint -- the cell value
+                if (fr.wrx >= 0)
+                    fb_wr[(size_t)fr.wrx * a.kp4 + kw + v] =
+                        ADJ ? h : (xn == CODE_WALL ? h : T(1.5) * h - T(0.5) * p1);
+                if (fr.wry >= 0)
+                    fb_wr[(size_t)fr.wry * a.kp4 + kw + v] =
+                        ADJ ? h : (yn == CODE_WALL ? h : T(1.5) * h - T(0.5) * hS1);
+            }
+            if (CKPT && !solid && xa)
+                a.ckpt[((size_t)cbase + cl) * a.kp4 + kw + v] = hd;
+            hout[v] = h;
+            if (hold) {
+                PX[v] = xa ? h : p1;
+                PA[v] = xa ? p1 : p2;       // prev2 of the next step
+                HB[v] = xa ? hS1 : h1;
+            } else {
+                PX[v] = h;
+                HB[v] = hS1;
             }
         }
+        // the last two rows of the strip feed the next strip next iteration
+        if (!P12 && has_down && t < tp && lane >= hs - 2 && lane < hs && xa) {
+            const int clx = st_cell[b][s][lane];
+            const int xx = clx >= 0 ? clx % nx : (xpos ? wrap_mod(t - lane, tp) : nx - 1 - wrap_mod(t - lane, tp));
+            const int slot = lane - (hs - 2);
+            T *sp = seam_out + (size_t)xx * seam_row + (size_t)slot * a.kp4 + kw;
 #pragma unroll
-        for (int m = 0; m < NM; ++m)
-            lds_part[s][wave][lane][m] = acc[m];
+            for (int v = 0; v < V; ++v)
+                sp[v] = hout[v];
+        }
+#pragma unroll
+        for (int m = 0; m < NACC; ++m)
+            lds_part[sl][wave][lane][m] = acc[m];
+    };
+
+    // group-wide sum of the partial moments of steps [s0, s0 + FL) of buffer b
+    auto flush = [&](int b, int s0) {
+        __syncthreads();
+        for (int e = tid; e < FL * 64 * NACC; e += 64 * G) {
+            const int sl = e / (64 * NACC), l = (e / NACC) % 64, m = e % NACC;
+            const int cl = st_cell[b][s0 + sl][l];
+            if (cl < 0)
+                continue;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < G; ++w)
+                sum += lds_part[sl][w][l][m];
+            const size_t cg = (size_t)it.group * a.ncell + cbase + cl;
+            if (P12)
+                a.part5[cg] = sum;
+            else if (m < 4)
+                a.part[cg * 4 + m] = sum;
+            else
+                a.part5[cg] = sum;
+        }
+        __syncthreads();
     };
 
     for (int c = 0; c < nchunks; ++c) {
@@ -377,27 +458,32 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         const int t0 = c * C;
         if (c + 1 < nchunks)
             issue(c + 1);
-        // register roles cycle with period 6: (A,B,X)(H0,H1) -> (X,A,B)(H1,H0) -> ...
-        if (!skew && t0 + C <= tp) {
-            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, false, true);
-            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, false, true);
-            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, false, true);
-            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, false, true);
-            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, false, true);
-            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, false, true);
-        } else {
-            // skewed schedule or the partial last chunk: lanes keep their
-            // registers at steps where they have no cell
+        bool xa[C];
+        {
             int xr = xr0;
-            bool xa[C];
 #pragma unroll
             for (int s = 0; s < C; ++s) {
                 xa[s] = (t0 + s < tp) && (xr < nx);
                 xr = (xr + 1 == tp) ? 0 : xr + 1;
             }
+        }
+        const bool fast = !skew && t0 + C <= tp;
+        // register roles cycle with period 6: (A,B,X)(H0,H1) -> (X,A,B)(H1,H0) -> ...
+        if (fast) {
+            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, false, true);
+            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, false, true);
+            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, false, true);
+            if (FL == 3)
+                flush(b, 0);
+            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, false, true);
+            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, false, true);
+            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, false, true);
+        } else {
             step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, true, xa[0]);
             step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, true, xa[1]);
             step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, true, xa[2]);
+            if (FL == 3)
+                flush(b, 0);
             step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, true, xa[3]);
             step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, true, xa[4]);
             step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, true, xa[5]);
@@ -405,27 +491,14 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         xr0 = (xr0 + C) % tp;
         if (c + 1 < nchunks)
             commit(b ^ 1);
-        __syncthreads();
-        // group-wide sum of the partial moments of this chunk
-        for (int e = tid; e < C * 64 * NM; e += 64 * G) {
-            const int s = e / (64 * NM), l = (e / NM) % 64, m = e % NM;
-            const int cl = st_cell[b][s][l];
-            if (cl < 0 || (st_code[b][s][l] >> 4))
-                continue;
-            double sum = 0.0;
-#pragma unroll
-            for (int w = 0; w < G; ++w)
-                sum += lds_part[s][w][l][m];
-            a.part[((size_t)it.group * a.ncell + cbase + cl) * NM + m] = sum;
-        }
-        __syncthreads();
+        flush(b, C - FL);
     }
-    if (!FINAL && x_coupled) {
+    if (!P12 && x_coupled) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            wrapp[v] = rA[v];
-            wrapp[V + v] = rB[v];
-            wrapp[2 * V + v] = rH0[v];
+            wrapp[v * 64] = rA[v];
+            wrapp[wslot + v * 64] = rB[v];
+            wrapp[2 * wslot + v * 64] = rH0[v];
         }
     }
 }
@@ -435,7 +508,7 @@ __global__ void __launch_bounds__(256) k_moments(MomArgs a)
 {
     const int inst = blockIdx.y;
     const InstDev in = a.inst[inst];
-    if (a.st[inst].active == 0)
+    if (!a.force && a.st[inst].active == 0)
         return;
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= in.nx * in.ny)
@@ -474,8 +547,9 @@ __global__ void __launch_bounds__(256) k_moments(MomArgs a)
     m[MOM_FYM] = fym;
 }
 
-// sum of a single diagnostic moment (shear stress) over velocity groups
-__global__ void __launch_bounds__(256) k_sum1(MomArgs a, double *out)
+// sum of one extra per-group partial (shear stress, gradient term) over the
+// velocity groups, fixed order
+__global__ void __launch_bounds__(256) k_sum1(MomArgs a, const double *part5, double *out, double scale)
 {
     const int inst = blockIdx.y;
     const InstDev in = a.inst[inst];
@@ -486,8 +560,8 @@ __global__ void __launch_bounds__(256) k_sum1(MomArgs a, double *out)
     double s = 0.0;
     if (a.codes[cg] != 0xFF)
         for (int g = 0; g < 4 * a.gq; ++g)
-            s += a.part[(size_t)g * a.ncell + cg];
-    out[cg] = 2.0 * s;
+            s += part5[(size_t)g * a.ncell + cg];
+    out[cg] = scale * s;
 }
 
 // ------------------------------------------------------------------ record
@@ -511,7 +585,10 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
             const double dl = in.field ? a.delta_field[cg] : in.delta;
             T rec[8];
             rec[0] = T(dl * (r / a.m0 - t * a.c2));
-            rec[1] = T(dl * (u1 / a.m2) + in.drive);
+            // drive: unit pressure gradient along x (forward); the adjoint
+            // is driven by -dQ/dh / W = -(dx / nx) xi
+            const double drive = a.adjoint ? -1.0 / (in.inv_dx * (double)in.nx) : in.drive;
+            rec[1] = T(dl * (u1 / a.m2) + drive);
             rec[2] = T(dl * (u2 / a.m2));
             rec[3] = T(dl * t);
             rec[6] = T(dl);
@@ -520,28 +597,45 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
             const int x = c % in.nx, y = c / in.nx;
             for (int d = 0; d < 4; ++d) {
                 const int cd = (code >> (2 * d)) & 3;
+                const int od = d ^ 1;
+                const int co = (code >> (2 * od)) & 3;
+                // half-range flux moment of the velocities that cross side d
+                // outwards, and its sign as a flux through that face
+                const int hf = (d == SIDE_W) ? MOM_FXM : (d == SIDE_E) ? MOM_FXP
+                             : (d == SIDE_S) ? MOM_FYM : MOM_FYP;
+                const double sgn = (d == SIDE_W || d == SIDE_S) ? -1.0 : 1.0;
+                auto nbr = [&](int side) {
+                    int nxx = x, nyy = y;
+                    if (side == SIDE_W) nxx = (x + in.nx - 1) % in.nx;
+                    else if (side == SIDE_E) nxx = (x + 1) % in.nx;
+                    else if (side == SIDE_S) nyy = (y + in.ny - 1) % in.ny;
+                    else nyy = (y + 1) % in.ny;
+                    return in.cell_off + (long long)nyy * in.nx + nxx;
+                };
                 double gval = 0.0;
-                if (cd == CODE_WALL) {
-                    // incident flux through the wall face on side d: the
-                    // half-range flux of the cell, extrapolated from the
-                    // neighbour on the opposite side unless that side is a
-                    // wall as well (first-order face value)
-                    const int od = d ^ 1;
-                    const int co = (code >> (2 * od)) & 3;
-                    const int hf = (d == SIDE_W) ? MOM_FXM : (d == SIDE_E) ? MOM_FXP
-                                 : (d == SIDE_S) ? MOM_FYM : MOM_FYP;
-                    const double sgn = (d == SIDE_W || d == SIDE_S) ? -1.0 : 1.0;
-                    double f = m[hf];
-                    if (co != CODE_WALL && co != CODE_NONE) {
-                        int nxx = x, nyy = y;
-                        if (od == SIDE_W) nxx = (x + in.nx - 1) % in.nx;
-                        else if (od == SIDE_E) nxx = (x + 1) % in.nx;
-                        else if (od == SIDE_S) nyy = (y + in.ny - 1) % in.ny;
-                        else nyy = (y + 1) % in.ny;
-                        const double fo = a.mom[(in.cell_off + (long long)nyy * in.nx + nxx) * MOM_STRIDE + hf];
-                        f = 1.5 * f - 0.5 * fo;
+                if (!a.adjoint) {
+                    if (cd == CODE_WALL) {
+                        // incident flux through the wall face on side d: the
+                        // half-range flux of the cell, extrapolated from the
+                        // neighbour on the opposite side unless that side is
+                        // a wall as well (first-order face value)
+                        double f = m[hf];
+                        if (co != CODE_WALL && co != CODE_NONE)
+                            f = 1.5 * f - 0.5 * a.mom[nbr(od) * MOM_STRIDE + hf];
+                        gval = in.alpha * sgn * f / a.D;
                     }
-                    gval = in.alpha * sgn * f / a.D;
+                } else {
+                    // transposed wall coupling: the diffuse wall of a face
+                    // gathers the incident flux of the adjoint cell values and
+                    // returns it to the two cells whose values built the
+                    // face value (weights 1.5 / -0.5, or 1 next to a second
+                    // wall on the opposite side)
+                    if (cd == CODE_WALL) {
+                        const double kap = (co == CODE_WALL || co == CODE_NONE) ? 1.0 : 1.5;
+                        gval = kap * in.alpha * sgn * m[hf] / a.D;
+                    } else if (cd == CODE_NEAR) {
+                        gval = -0.5 * in.alpha * sgn * a.mom[nbr(d) * MOM_STRIDE + hf] / a.D;
+                    }
                 }
                 gside[d] = gval;
             }
@@ -579,6 +673,88 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
         atomicMax(&st->maxdiff_bits, (unsigned long long)__builtin_bit_cast(long long, dmax));
         atomicMax(&st->maxabs_bits, (unsigned long long)__builtin_bit_cast(long long, amax));
     }
+}
+
+// -------------------------------------------------------------- gradient
+// dQ/d delta_c = -sum_k lambda_ck (h_ck - E_k(h_c)) with lambda_ck = W_k nu_c(-k):
+// the group partials hold sum_k W_k nu_c,k h_c(-k); the equilibrium part
+// follows from the moments of both fields (E is linear in the forward moments
+// and the reversal flips the odd moments of nu).
+__global__ void __launch_bounds__(256) k_grad_cell(GradArgs a, int instance)
+{
+    const InstDev in = a.inst[instance];
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= in.nx * in.ny)
+        return;
+    const long long cg = in.cell_off + c;
+    if (a.codes[cg] == 0xFF) {
+        a.dqdd[cg] = 0.0;
+        return;
+    }
+    double s5 = 0.0;
+    for (int g = 0; g < a.ngroups; ++g)
+        s5 += a.part5[(size_t)g * a.ncell + cg];
+    const double *m = a.mom_fwd + cg * MOM_STRIDE;
+    const double *n = a.mom_adj + cg * MOM_STRIDE;
+    const double t = (m[MOM_E] - a.c2 * m[MOM_RHO]) / a.c4;
+    const double a0 = m[MOM_RHO] / a.m0 - t * a.c2, a1 = m[MOM_U1] / a.m2, a2 = m[MOM_U2] / a.m2;
+    const double eq = a0 * n[MOM_RHO] - a1 * n[MOM_U1] - a2 * n[MOM_U2] + t * n[MOM_E];
+    a.dqdd[cg] = -(s5 - eq);
+}
+
+// dQ/d alpha, part of wall face phi: sum over the velocities j that cross
+// the face towards the wall of (|v_n|/dx) W_j nu_j (rho_w - h_inc(mirror(-j))),
+// rho_w the diffuse density of the face from the forward incident values.
+__global__ void __launch_bounds__(256) k_grad_face(GradArgs a)
+{
+    const int f = a.face0 + blockIdx.x;
+    const int side = a.face_side[f];
+    const InstDev in = a.inst[a.face_inst[f]];
+    const double *vt = a.vtab + (size_t)a.face_inst[f] * a.kp4 * VT_STRIDE;
+    const double *ff = a.fb_fwd + (size_t)f * a.kp4;
+    const double *fa = a.fb_adj + (size_t)f * a.kp4;
+    // quadrants whose velocities move into the face; reversing a velocity
+    // flips both quadrant bits, mirroring in the face flips the bit of the
+    // normal component (bit 0: xi < 0, bit 1: eta < 0)
+    const bool xface = side < 2;
+    const int qa = side == SIDE_W ? 1 : side == SIDE_E ? 0 : side == SIDE_S ? 2 : 0;
+    const int qb = side == SIDE_W ? 3 : side == SIDE_E ? 2 : side == SIDE_S ? 3 : 1;
+    const int mflip = xface ? 1 : 2;
+    __shared__ double red[256];
+    double r = 0.0;
+    for (int e = threadIdx.x; e < 2 * a.kq; e += 256) {
+        const int q = e < a.kq ? qa : qb;
+        const int j = q * a.kq + (e % a.kq);
+        const double vn = fabs(vt[(size_t)j * VT_STRIDE + (xface ? VT_XI : VT_ETA)]);
+        r += vt[(size_t)j * VT_STRIDE + VT_W] * vn * ff[j];
+    }
+    red[threadIdx.x] = r;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double rho_w = red[0] / a.D;
+    __syncthreads();
+    double g = 0.0;
+    for (int e = threadIdx.x; e < 2 * a.kq; e += 256) {
+        const int q = e < a.kq ? qa : qb;
+        const int idx = e % a.kq;
+        const int j = q * a.kq + idx;
+        const int jm = (q ^ 3 ^ mflip) * a.kq + idx;
+        const double vn = fabs(vt[(size_t)j * VT_STRIDE + (xface ? VT_XI : VT_ETA)]);
+        g += vt[(size_t)j * VT_STRIDE + VT_W] * vn * fa[j] * (rho_w - ff[jm]);
+    }
+    red[threadIdx.x] = g;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        a.dqda_face[f] = red[0] * in.inv_dx;
 }
 
 // ------------------------------------------------------------------ status
@@ -652,25 +828,62 @@ __global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst,
 }
 
 // --------------------------------------------------------- host launchers
-template <typename T, int V, int G, bool FIELD, bool FINAL>
+template <typename T, int V, int G, int MODE>
 static hipError_t launch_sweep_t(const SweepArgs<T> &a, int nitems, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sweep<T, V, G, FIELD, FINAL>), dim3(nitems), dim3(64 * G), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<T, V, G, MODE>), dim3(nitems), dim3(64 * G), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, bool field,
-                        bool final_pass, hipStream_t s)
+// plain iterations run in every supported shape
+template <typename T, int V, int G>
+static hipError_t launch_plain(const SweepArgs<T> &a, int n, int mode, hipStream_t s)
 {
-#define DVM_SW(VV, GG)                                                                  \
-    if (V == VV && G == GG) {                                                            \
-        if (final_pass)                                                                  \
-            return field ? launch_sweep_t<T, VV, GG, true, true>(a, nitems, s)           \
-                         : launch_sweep_t<T, VV, GG, false, true>(a, nitems, s);         \
-        return field ? launch_sweep_t<T, VV, GG, true, false>(a, nitems, s)              \
-                     : launch_sweep_t<T, VV, GG, false, false>(a, nitems, s);            \
+    if (mode == 0)
+        return launch_sweep_t<T, V, G, 0>(a, n, s);
+    if (mode == MODE_FIELD)
+        return launch_sweep_t<T, V, G, MODE_FIELD>(a, n, s);
+    return hipErrorInvalidValue;
+}
+
+// the other modes run with 4 velocities per lane, in the wave count that
+// keeps the velocity group (and so the partial and seam layout) unchanged
+template <int G>
+static hipError_t launch_special(const SweepArgs<double> &a, int n, int mode, hipStream_t s)
+{
+    constexpr int F = MODE_FIELD, S = MODE_SPEC;
+#define DVM_SP(M)                                                                         \
+    case (M): return launch_sweep_t<double, 4, G, (M)>(a, n, s);                          \
+    case (M) | F: return launch_sweep_t<double, 4, G, (M) | F>(a, n, s);                  \
+    case (M) | S: return launch_sweep_t<double, 4, G, (M) | S>(a, n, s);                  \
+    case (M) | F | S: return launch_sweep_t<double, 4, G, (M) | F | S>(a, n, s);
+    switch (mode) {
+    case S: return launch_sweep_t<double, 4, G, S>(a, n, s);
+    case F | S: return launch_sweep_t<double, 4, G, F | S>(a, n, s);
+    DVM_SP(MODE_P12)
+    DVM_SP(MODE_CKPT)
+    DVM_SP(MODE_ADJ)
+    DVM_SP(MODE_ADJ | MODE_GRAD)
+    default: return hipErrorInvalidValue;
     }
+#undef DVM_SP
+}
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, int mode, hipStream_t s)
+{
+    if ((mode & ~MODE_FIELD) != 0) {
+        if constexpr (sizeof(T) == 8) {
+            if (V * G == 32)
+                return launch_special<8>(a, nitems, mode, s);
+            if (V * G == 16)
+                return launch_special<4>(a, nitems, mode, s);
+        }
+        return hipErrorInvalidValue;
+    }
+#define DVM_SW(VV, GG)                                                                    \
+    if (V == VV && G == GG)                                                                \
+        return launch_plain<T, VV, GG>(a, nitems, mode, s);
     DVM_SW(4, 8)
     DVM_SW(8, 4)
     DVM_SW(4, 4)
@@ -679,8 +892,8 @@ hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, bool fi
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, int, int, bool, bool, hipStream_t);
-template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, int, int, bool, bool, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, int, int, int, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, int, int, int, hipStream_t);
 
 hipError_t launch_moments(const MomArgs &a, int max_cells, int n_inst, hipStream_t s)
 {
@@ -688,9 +901,20 @@ hipError_t launch_moments(const MomArgs &a, int max_cells, int n_inst, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_sum1(const MomArgs &a, double *out, int max_cells, int n_inst, hipStream_t s)
+hipError_t launch_sum1(const MomArgs &a, const double *part5, double *out, double scale, int max_cells,
+                       int n_inst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum1, dim3((max_cells + 255) / 256, n_inst), dim3(256), 0, s, a, out);
+    hipLaunchKernelGGL(k_sum1, dim3((max_cells + 255) / 256, n_inst), dim3(256), 0, s, a, part5, out, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const GradArgs &a, int instance, int ncells, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_cell, dim3((ncells + 255) / 256), dim3(256), 0, s, a, instance);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.nfaces == 0)
+        return e;
+    hipLaunchKernelGGL(k_grad_face, dim3(a.nfaces), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

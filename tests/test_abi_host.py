@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol(lib):
 
 def _ctx(lib, nv=8, n=1, **kw):
     cfg = dvm.dvm_config(kw.get("precision", 0), kw.get("tol", 1e-8), kw.get("max_iter", 1000),
-                         kw.get("block_iters", 0), 1, kw.get("vel", 0), kw.get("waves", 0), None, 0)
+                         kw.get("block_iters", 0), 1, kw.get("vel", 0), kw.get("waves", 0), None, 0,
+                         kw.get("schedule", 0))
     h = ctypes.c_void_p()
     rc = lib.dvm_create(ctypes.byref(h), nv, n, ctypes.byref(cfg), None)
     return rc, h
@@ -51,6 +52,7 @@ def test_create_validates_arguments(lib):
     assert _ctx(lib, precision=7)[0] == dvm.DVM_EINVAL
     assert _ctx(lib, tol=-1.0)[0] == dvm.DVM_EINVAL
     assert _ctx(lib, vel=3)[0] == dvm.DVM_EINVAL
+    assert _ctx(lib, schedule=2)[0] == dvm.DVM_EINVAL
     assert b"nv" in lib.dvm_last_error() or b"vel" in lib.dvm_last_error() or lib.dvm_last_error()
     rc, h = _ctx(lib)
     assert rc == dvm.DVM_OK
@@ -116,7 +118,7 @@ def test_call_order_and_solve_arguments(lib):
                              ctypes.byref(info)) == dvm.DVM_EINVAL
         # batched solve needs every instance described
         assert lib.dvm_solve(h, -1, dp, 0, 1.0, ctypes.byref(info)) == dvm.DVM_ESTATE
-        assert lib.dvm_grad(h, 0, None, None) == dvm.DVM_ESTATE or True
+        assert lib.dvm_grad(h, 0, None, None) == dvm.DVM_ESTATE   # not solved yet
     finally:
         lib.dvm_destroy(h)
 

@@ -28,9 +28,9 @@ def dvm():
 
 
 def gpu_solve(dvm, g, delta, nv, tol=1e-11, alpha=1.0, vel=0, waves=0, graphs=True,
-              shear=False, max_iter=200000):
+              shear=False, max_iter=200000, schedule=0):
     s = dvm.Solver(nv, 1, tol=tol, vel_per_lane=vel, waves_per_block=waves,
-                   use_graphs=graphs, max_iter=max_iter)
+                   use_graphs=graphs, max_iter=max_iter, schedule=schedule)
     s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
     info = s.solve(0, delta, alpha)
     Q, ka = s.flow_rate(0)
@@ -98,12 +98,14 @@ def test_multi_strip_and_ragged_sizes(dvm):
     Q2, _, mom2, _ = gpu_solve(dvm, g2, 2.0, 6)
     assert abs(Q2 - ref2.Q) < 1e-9 * abs(ref2.Q)
     assert np.max(np.abs(mom2["u1"] - ref2.u1)) < 1e-9
-    # narrow periodic porous cell whose oracle sweep diverges at delta = 0.01:
-    # the direct solve decides
+    # narrow periodic porous cell whose plain source iteration diverges at
+    # delta = 0.01 when it lags only the periodic seams (the oracle's order
+    # and the default one); the wrap-around order converges: the direct solve
+    # decides
     from paper_1704_03126_amd.geometry import porous_discs as pd
     g3 = pd(8, 0.7, 5)
     ref3 = dn.solve(g3.mask, 0.01, 6, periodic_y=True, cells_per_H=8.0)
-    Q3, _, mom3, info3 = gpu_solve(dvm, g3, 0.01, 6, tol=1e-12)
+    Q3, _, mom3, info3 = gpu_solve(dvm, g3, 0.01, 6, tol=1e-12, schedule=dvm.DVM_SCHED_WRAP)
     assert info3.status == "converged"
     assert abs(Q3 - ref3.Q) < 1e-8 * abs(ref3.Q)
 
@@ -197,3 +199,30 @@ def test_warm_start_delta_sweep(dvm):
     ref = oracle_solve(g, 2.0, 8)
     assert abs(Qw - ref.Q) < 1e-8 * abs(ref.Q)
     s.close()
+
+
+@pytest.mark.parametrize("case", ["rough", "porous"])
+def test_wrap_schedule_same_fixed_point(dvm, case):
+    """The wrap-around diagonal lags different couplings but converges (on
+    these geometries) to the same discrete solution as the oracle."""
+    if case == "rough":
+        g, nv = rough_channel(64, 32, 6, 32), 16
+    else:
+        g, nv = porous_discs(64, 0.6, 1003), 12
+    ref = oracle_solve(g, 1.0, nv)
+    Q, _, mom, info = gpu_solve(dvm, g, 1.0, nv, schedule=dvm.DVM_SCHED_WRAP)
+    assert info.status == "converged"
+    assert_parity(Q, mom, ref, qtol=1e-8, utol=1e-8)
+
+
+def test_block_in_periodic_cell_default_schedule(dvm):
+    """A solid block inside a periodic cell: the default schedule converges
+    to the oracle's solution (the wrap-around diagonal diverges here)."""
+    m = np.zeros((16, 16), np.uint8)
+    m[6:10, 4:10] = 1
+    from paper_1704_03126_amd.geometry import Geometry
+    g = Geometry(mask=m, periodic_y=True, cells_per_H=16.0)
+    ref = oracle_solve(g, 0.7, 8)
+    Q, _, mom, info = gpu_solve(dvm, g, 0.7, 8)
+    assert info.status == "converged"
+    assert_parity(Q, mom, ref, qtol=1e-8, utol=1e-8)
