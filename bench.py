@@ -51,6 +51,9 @@ def parse():
     p.add_argument("--schedule", choices=["skew", "wrap"], default="skew",
                    help="sweep order: skew (lags periodic/strip seams only) or the "
                         "wrap-around diagonal (fewer steps, not unconditionally stable)")
+    p.add_argument("--accel", choices=["auto", "none", "gmres"], default="auto",
+                   help="auto: source iteration, GMRES for an instance that stops contracting; "
+                        "none: plain source iteration; gmres: GMRES on its fixed-point map")
     p.add_argument("--vel", type=int, default=0)
     p.add_argument("--waves", type=int, default=0)
     p.add_argument("--no-roofline", action="store_true",
@@ -89,8 +92,9 @@ def main():
     nf = g.n_fluid
     K = NV * NV
     sched = dvm.DVM_SCHED_WRAP if args.schedule == "wrap" else dvm.DVM_SCHED_SKEW
+    accel = {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE, "gmres": dvm.DVM_ACCEL_GMRES}[args.accel]
     solver = dvm.Solver(NV, 1, tol=TOL, vel_per_lane=args.vel, waves_per_block=args.waves,
-                        schedule=sched)
+                        schedule=sched, accel=accel)
     solver.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
 
     def step():
@@ -173,7 +177,7 @@ def main():
         "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
                    "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
                    "deltas": list(DELTAS), "tol": TOL, "precision": "fp64",
-                   "schedule": args.schedule, "parallelism": "single_gpu"},
+                   "schedule": args.schedule, "accel": args.accel, "parallelism": "single_gpu"},
         "iterations_per_delta": all_its[-1],
         "time_to_solution_s": dict(zip([str(d) for d in DELTAS],
                                        np.mean(np.array(all_tts), axis=0).tolist())),

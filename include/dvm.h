@@ -53,6 +53,12 @@ extern "C" {
 #define DVM_SCHED_SKEW 0    /* sweep order with lags at periodic/strip seams only */
 #define DVM_SCHED_WRAP 1    /* wrap-around diagonal: fewer steps on wide grids  */
 
+#define DVM_ACCEL_AUTO 0    /* plain source iteration; GMRES takes over an
+                               instance whose iteration stops contracting     */
+#define DVM_ACCEL_NONE 1    /* plain source iteration only (the paper's)      */
+#define DVM_ACCEL_GMRES 2   /* restarted GMRES on the fixed-point map of the
+                               iteration from the start                       */
+
 #define DVM_STATUS_RUNNING 0
 #define DVM_STATUS_CONVERGED 1
 #define DVM_STATUS_MAXITER 2
@@ -87,6 +93,19 @@ typedef struct {
                                diagonal per strip, saving 63 steps per pass,
                                but the iteration can then diverge (seen with
                                a solid block inside a periodic cell)         */
+    int accel;              /* DVM_ACCEL_AUTO (default), DVM_ACCEL_NONE or
+                               DVM_ACCEL_GMRES.  GMRES drives the iteration's
+                               state (moments, lagged seam, wrap and wall
+                               values) with the same sweeps and reaches the
+                               same fixed point; it converges where the lagged
+                               iteration diverges.  AUTO hands an instance to
+                               GMRES when its relative change of u1 has not
+                               dropped by 5% over 64 iterations.  GMRES stop
+                               rule: one iteration from the result changes u1
+                               by eps (relative) with eps / sigma <= tol,
+                               sigma the smallest singular value of the last
+                               Krylov projection clamped to [1e-3, 1]         */
+    int krylov_dim;         /* GMRES restart length; 0 -> 30 (max 64)         */
 } dvm_config;
 
 /* Per-instance result of dvm_solve. */

@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdvm.so")
-SOURCES = ["dvm_kernels.hip", "dvm_api.hip"]
+SOURCES = ["dvm_kernels.hip", "dvm_vec.hip", "dvm_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -75,6 +75,19 @@ struct DevBuf {
     }
 };
 
+// device workspace of the GMRES driver (grown on demand)
+struct KrylovWork {
+    DevBuf<double> V, x, w, part, c1, c2, y;
+    DevBuf<VSeg> gseg, sseg;
+    DevBuf<VChunk> ch;
+    DevBuf<int> c0, nc;
+    void release()
+    {
+        V.release(); x.release(); w.release(); part.release(); c1.release(); c2.release(); y.release();
+        gseg.release(); sseg.release(); ch.release(); c0.release(); nc.release();
+    }
+};
+
 } // namespace
 
 struct dvm_ctx {
@@ -115,6 +128,9 @@ struct dvm_ctx {
     DevBuf<double> d_ckpt, d_part5, d_momg, d_dqda;
     DevBuf<SolveState> d_st_adj;
 
+    KrylovWork kw;
+    std::vector<long long> sweeps_done;   // per instance, last solve (GMRES)
+
     // captured iteration blocks: [0] forward, [1] adjoint
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_iters[2] = {0, 0};
@@ -143,6 +159,7 @@ struct dvm_ctx {
         d_face_inst.release(); d_srec_adj.release(); d_mom_adj.release(); d_u1prev_adj.release();
         d_seam_adj.release(); d_wrap_adj.release(); d_fb_adj.release(); d_ckpt.release();
         d_part5.release(); d_momg.release(); d_dqda.release(); d_st_adj.release();
+        kw.release();
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
     }
@@ -614,6 +631,8 @@ static RecArgs<double> rec_args(dvm_ctx *c, bool adj = false)
 {
     RecArgs<double> a{};
     a.adjoint = adj ? 1 : 0;
+    a.homog = 0;
+    a.monitor = 1;
     a.inst = c->d_inst.p;
     a.codes = c->d_codes.p;
     a.mom = adj ? c->d_mom_adj.p : c->d_mom.p;
@@ -740,13 +759,21 @@ static int enqueue_block(dvm_ctx *c, int iters, bool adj)
     return DVM_OK;
 }
 
+static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
+                     const std::vector<long long> &prior);
+
 // Replay blocks of iterations until no instance of [i0, i1) is active.
+// With stall detection (DVM_ACCEL_AUTO) an instance whose relative change of
+// u1 has not dropped by 5% over the last 64 iterations is stopped and flagged
+// in stalled[] (its state is that of a completed iteration).
 static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, bool adj,
-                      std::vector<SolveState> &st)
+                      std::vector<SolveState> &st, std::vector<char> *stalled = nullptr)
 {
     const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
     const long long cap = c->cfg.max_iter;
+    const long long W = 64;
     SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
+    std::vector<std::vector<std::pair<long long, double>>> hist(c->n_inst);
     for (;;) {
         int rc = enqueue_block(c, B, adj);
         if (rc)
@@ -759,13 +786,453 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
             if (prc)
                 return prc;
         }
-        bool running = false;
-        for (int i = i0; i < i1; ++i)
-            if (st[i].active && st[i].iter - iter0[i] < cap)
-                running = true;
+        bool running = false, stop = false;
+        for (int i = i0; i < i1; ++i) {
+            if (!(st[i].active && st[i].iter - iter0[i] < cap))
+                continue;
+            if (stalled) {
+                auto &hv = hist[i];
+                const long long it = st[i].iter - iter0[i];
+                hv.emplace_back(it, st[i].eps);
+                double old = -1.0;
+                for (const auto &e : hv)
+                    if (e.first <= it - W)
+                        old = e.second;
+                if (old > 0.0 && st[i].eps > c->cfg.tol && !(st[i].eps < 0.95 * old)) {
+                    st[i].active = 0;
+                    (*stalled)[i] = 1;
+                    stop = true;
+                    continue;
+                }
+            }
+            running = true;
+        }
+        if (stop) {
+            HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
         if (!running)
             return DVM_OK;
     }
+}
+
+// The iteration of [i0, i1) as configured: plain, GMRES, or plain with GMRES
+// taking over stalled instances.  Leaves per-instance sweep counts in
+// c->sweeps_done.
+static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, bool adj,
+                   std::vector<SolveState> &st)
+{
+    if (c->cfg.accel == DVM_ACCEL_GMRES) {
+        std::vector<long long> prior;
+        return gmres_run(c, i0, i1, adj, st, prior);
+    }
+    std::vector<char> stalled(c->n_inst, 0);
+    int rc = run_blocks(c, i0, i1, iter0, adj, st, c->cfg.accel == DVM_ACCEL_AUTO ? &stalled : nullptr);
+    if (rc)
+        return rc;
+    std::vector<long long> prior(c->n_inst, 0);
+    bool any = false;
+    for (int i = i0; i < i1; ++i) {
+        prior[i] = st[i].iter - iter0[i];
+        c->sweeps_done[i] = prior[i];
+        if (stalled[i]) {
+            st[i].active = 1;
+            st[i].status = STATUS_RUNNING;
+            any = true;
+        }
+    }
+    if (!any)
+        return DVM_OK;
+    SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
+    HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return gmres_run(c, i0, i1, adj, st, prior);
+}
+
+// --------------------------------------------------------------- GMRES
+// The source iteration is an affine map x -> F(x) = L x + b of its state x:
+// the cell moments (they define the next collision gain and wall values),
+// the values lagged across strip seams and the periodic x seam, and (for
+// alpha < 1) the incident wall-face values.  Restarted GMRES solves
+// (I - L) x = b with the same sweeps: L v is one sweep without the drive.
+// Each cycle starts with one full iteration from the current x, which gives
+// the residual x - F(x) and the relative change eps of u1; an instance is
+// accepted when eps / sigma <= tol, sigma the smallest singular value of the
+// last Krylov projection (clamped to [1e-3, 1]), or eps is at round-off.  The
+// accepted state is F(x).
+
+struct Slot {
+    int inst;
+    long long off, len;
+    int pw;           // parity written by the sweeps while GMRES runs
+};
+
+static void add_seg(std::vector<VSeg> &v, int buf, long long boff, long long voff, long long len)
+{
+    while (len > 0) {
+        const int l = (int)std::min<long long>(len, VCHUNK);
+        v.push_back(VSeg{boff, voff, l, buf});
+        boff += l;
+        voff += l;
+        len -= l;
+    }
+}
+
+// Segments of one instance's state: outputs of a sweep (parity pw) for
+// gather, inputs of the next sweep (parity pw ^ 1) for scatter.  Returns the
+// state length.
+static long long state_segments(const dvm_ctx *c, int i, int pw, long long voff, std::vector<VSeg> *g,
+                                std::vector<VSeg> *sc)
+{
+    const HostInst &h = c->inst[i];
+    const InstDev &d = c->idev[i];
+    const int pr = pw ^ 1;
+    long long v = voff;
+    auto both = [&](int buf, long long off_w, long long off_r, long long len) {
+        if (g)
+            add_seg(*g, buf, off_w, v, len);
+        if (sc)
+            add_seg(*sc, buf, off_r, v, len);
+        v += len;
+    };
+    const long long nmom = (long long)d.nx * d.ny * MOM_STRIDE;
+    both(0, d.cell_off * MOM_STRIDE, d.cell_off * MOM_STRIDE, nmom);
+    const long long kq = c->kq, kp4 = c->kp4;
+    for (int st = 0; st < d.nstrips; ++st) {
+        const bool up = st < d.nstrips - 1 || d.periodic_y;   // eta > 0 quadrants feed the strip above
+        const bool dn = st > 0 || d.periodic_y;               // eta < 0 quadrants feed the strip below
+        if (!up && !dn)
+            continue;
+        const long long k0 = up ? 0 : 2 * kq, k1 = dn ? 4 * kq : 2 * kq;
+        for (int x = 0; x < d.nx; ++x)
+            for (int sl = 0; sl < 2; ++sl) {
+                const long long rel = d.seam_off + (((long long)st * d.nx + x) * 2 + sl) * kp4 + k0;
+                both(1, pw * c->seam_half + rel, pr * c->seam_half + rel, k1 - k0);
+            }
+    }
+    if (d.nx > 1)
+        for (int st = 0; st < d.nstrips; ++st)
+            for (int sl = 0; sl < 3; ++sl) {
+                const long long off = d.wrap_off + ((long long)st * 3 + sl) * kp4 * 64;
+                both(2, off, off, kp4 * 64);
+            }
+    if (h.alpha < 1.0 && h.nfaces > 0) {
+        const long long fh = std::max<long long>(c->nfaces, 1) * kp4;
+        const long long rel = h.face_base * kp4;
+        both(3, pw * fh + rel, pr * fh + rel, (long long)h.nfaces * kp4);
+    }
+    return v - voff;
+}
+
+struct GmresSlotHost {
+    std::vector<double> H, cs, sn, g;   // H: (m+1) x m column-major
+    double beta = 0.0, sig = -1.0;
+    bool live = true;
+    long long sweeps = 0;
+};
+
+// smallest singular value of the k x k upper triangular R (column-major,
+// leading dimension ld) by inverse iteration on R^T R
+static double sigma_min_tri(const std::vector<double> &R, int ld, int k)
+{
+    if (k == 0)
+        return 1.0;
+    std::vector<double> z(k, 1.0 / std::sqrt((double)k)), t(k), u(k);
+    double lam = 0.0;
+    for (int it = 0; it < 40; ++it) {
+        for (int i = 0; i < k; ++i) {           // R^T t = z
+            double a = z[i];
+            for (int j = 0; j < i; ++j)
+                a -= R[(size_t)i * ld + j] * t[j];
+            const double dg = R[(size_t)i * ld + i];
+            if (dg == 0.0)
+                return 0.0;
+            t[i] = a / dg;
+        }
+        for (int i = k - 1; i >= 0; --i) {      // R u = t
+            double a = t[i];
+            for (int j = i + 1; j < k; ++j)
+                a -= R[(size_t)j * ld + i] * u[j];
+            u[i] = a / R[(size_t)i * ld + i];
+        }
+        double nrm = 0.0;
+        for (double q : u)
+            nrm += q * q;
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm))
+            return 0.0;
+        lam = nrm;
+        for (int i = 0; i < k; ++i)
+            z[i] = u[i] / nrm;
+    }
+    return 1.0 / std::sqrt(lam);
+}
+
+static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
+                     const std::vector<long long> &prior)
+{
+    const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 30;
+    const int mode = solve_mode(c) | (adj ? MODE_ADJ : 0);
+    SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
+    StateBufs sb;
+    sb.b[0] = adj ? c->d_mom_adj.p : c->d_mom.p;
+    sb.b[1] = adj ? c->d_seam_adj.p : c->d_seam.p;
+    sb.b[2] = adj ? c->d_wrap_adj.p : c->d_wrap.p;
+    sb.b[3] = adj ? c->d_fb_adj.p : c->d_fb.p;
+
+    std::vector<Slot> slots;
+    long long n = 0;
+    for (int i = i0; i < i1; ++i) {
+        if (!st[i].active)
+            continue;
+        Slot sl{i, n, 0, (int)(st[i].iter & 1)};
+        sl.len = state_segments(c, i, sl.pw, n, nullptr, nullptr);
+        n += sl.len;
+        slots.push_back(sl);
+    }
+    const int ns = (int)slots.size();
+    if (ns == 0)
+        return DVM_OK;
+    KrylovWork &kw = c->kw;
+    auto grow = [&](DevBuf<double> &b, size_t cnt) -> hipError_t {
+        return b.n >= cnt ? hipSuccess : b.alloc(cnt);
+    };
+    const long long nchmax = n / VCHUNK + ns + 1;
+    HIPCHK(grow(kw.V, (size_t)(m + 1) * n));
+    HIPCHK(grow(kw.x, n));
+    HIPCHK(grow(kw.w, n));
+    HIPCHK(grow(kw.part, (size_t)(m + 2) * nchmax));
+    HIPCHK(grow(kw.c1, (size_t)ns * (m + 2)));
+    HIPCHK(grow(kw.c2, (size_t)ns * (m + 2)));
+    HIPCHK(grow(kw.y, (size_t)ns * (m + 2)));
+    const int cst = m + 2;
+
+    std::vector<GmresSlotHost> hs(ns);
+    for (int q = 0; q < ns; ++q)
+        hs[q].sweeps = prior.empty() ? 0 : prior[slots[q].inst];
+    for (auto &h : hs) {
+        h.H.assign((size_t)(m + 1) * m, 0.0);
+        h.cs.assign(m, 0.0);
+        h.sn.assign(m, 0.0);
+        h.g.assign(m + 1, 0.0);
+    }
+    // tables of the live slots (rebuilt when a slot finishes)
+    std::vector<VSeg> gseg, sseg;
+    std::vector<VChunk> chunks;
+    std::vector<int> c0(ns), ncs(ns);
+    auto rebuild = [&]() -> int {
+        gseg.clear();
+        sseg.clear();
+        chunks.clear();
+        for (int q = 0; q < ns; ++q) {
+            c0[q] = (int)chunks.size();
+            if (hs[q].live) {
+                state_segments(c, slots[q].inst, slots[q].pw, slots[q].off, &gseg, &sseg);
+                for (long long o = 0; o < slots[q].len; o += VCHUNK)
+                    chunks.push_back(VChunk{slots[q].off + o, (int)std::min<long long>(VCHUNK, slots[q].len - o), q});
+            }
+            ncs[q] = (int)chunks.size() - c0[q];
+        }
+        HIPCHK(kw.gseg.alloc(std::max<size_t>(gseg.size(), 1)));
+        HIPCHK(kw.sseg.alloc(std::max<size_t>(sseg.size(), 1)));
+        HIPCHK(kw.ch.alloc(std::max<size_t>(chunks.size(), 1)));
+        HIPCHK(kw.c0.alloc(ns));
+        HIPCHK(kw.nc.alloc(ns));
+        HIPCHK(hipMemcpyAsync(kw.gseg.p, gseg.data(), gseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(kw.sseg.p, sseg.data(), sseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(kw.ch.p, chunks.data(), chunks.size() * sizeof(VChunk), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipMemcpyAsync(kw.c0.p, c0.data(), ns * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(kw.nc.p, ncs.data(), ns * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return DVM_OK;
+    };
+    int rc = rebuild();
+    if (rc)
+        return rc;
+    const int nch = (int)chunks.size();
+    (void)nch;
+    auto sweep_once = [&](bool homog, bool monitor) -> int {
+        RecArgs<double> ra = rec_args(c, adj);
+        ra.homog = homog ? 1 : 0;
+        ra.monitor = monitor ? 1 : 0;
+        HIPCHK(launch_record<double>(ra, c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_sweep<double>(sweep_args(c, 0, adj), (int)c->items.size(), c->V, c->G, mode, c->stream));
+        HIPCHK(launch_moments(mom_args(c, adj), c->max_cells, c->n_inst, c->stream));
+        return DVM_OK;
+    };
+    // dots of w against V_0..V_{nv-1} (and |w|^2) summed per slot into out[slot][.]
+    auto dots = [&](const double *w, int nv, bool norm, double *out) -> int {
+        const int nchl = (int)chunks.size();
+        HIPCHK(launch_vdots(kw.ch.p, nchl, w, kw.V.p, n, nv, norm ? 1 : 0, kw.part.p, c->stream));
+        HIPCHK(launch_vsum(kw.c0.p, kw.nc.p, ns, kw.part.p, nchl, nv + (norm ? 1 : 0), out, cst, c->stream));
+        return DVM_OK;
+    };
+    // synchronous: the host vector is modified again right after
+    auto upload_st = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return DVM_OK;
+    };
+    const double tol = c->cfg.tol;
+    const long long cap = c->cfg.max_iter;
+    HIPCHK(launch_gather(kw.sseg.p, (int)sseg.size(), sb, kw.x.p, nullptr, c->stream));
+
+    std::vector<double> hc1((size_t)ns * cst), hc2((size_t)ns * cst), hy((size_t)ns * cst);
+    for (;;) {
+        // ---- one full iteration from x: residual w = x - F(x) and eps
+        for (int q = 0; q < ns; ++q)
+            if (hs[q].live)
+                st[slots[q].inst].maxdiff_bits = st[slots[q].inst].maxabs_bits = 0ull;
+        if ((rc = upload_st()))
+            return rc;
+        HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, kw.x.p, c->stream));
+        if ((rc = sweep_once(false, true)))
+            return rc;
+        HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, kw.x.p, c->stream));
+        {
+            // statistics of u1(F(x)) - u1(x): the monitor of this record
+            for (int q = 0; q < ns; ++q)
+                if (hs[q].live)
+                    st[slots[q].inst].maxdiff_bits = st[slots[q].inst].maxabs_bits = 0ull;
+            if ((rc = upload_st()))
+                return rc;
+            RecArgs<double> ra = rec_args(c, adj);
+            HIPCHK(launch_record<double>(ra, c->max_cells, c->n_inst, c->stream));
+        }
+        if ((rc = dots(kw.w.p, 0, true, kw.c1.p)))
+            return rc;
+        std::vector<SolveState> dev(c->n_inst);
+        HIPCHK(hipMemcpyAsync(dev.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(hc1.data(), kw.c1.p, hc1.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        bool changed = false, any = false;
+        for (int q = 0; q < ns; ++q) {
+            GmresSlotHost &h = hs[q];
+            if (!h.live)
+                continue;
+            SolveState &s = st[slots[q].inst];
+            h.sweeps += 1;
+            const double dmax = __builtin_bit_cast(double, (long long)dev[slots[q].inst].maxdiff_bits);
+            const double amax = __builtin_bit_cast(double, (long long)dev[slots[q].inst].maxabs_bits);
+            const double eps = amax > 0.0 ? dmax / amax : (dmax == 0.0 ? 0.0 : INFINITY);
+            const double sig = h.sig < 0.0 ? -1.0 : std::min(1.0, std::max(h.sig, 1e-3));
+            const double est = sig > 0.0 ? eps / sig : INFINITY;
+            s.eps = eps;
+            s.est = est;
+            h.beta = std::sqrt(std::max(hc1[(size_t)q * cst], 0.0));
+            int fin = 0;
+            if (!(amax < 1e30) || eps != eps || !std::isfinite(h.beta))
+                fin = STATUS_DIVERGED;
+            else if (eps <= 16.0 * 2.220446049250313e-16 || est <= tol || h.beta == 0.0)
+                fin = STATUS_CONVERGED;
+            else if (h.sweeps >= cap)
+                fin = STATUS_MAXITER;
+            if (fin) {
+                // the state now holds F(x): advance the parity like an iteration
+                s.iter += 1;
+                s.status = fin;
+                s.active = 0;
+                s.maxdiff_bits = s.maxabs_bits = 0ull;
+                h.live = false;
+                changed = true;
+                c->sweeps_done[slots[q].inst] = h.sweeps;
+            } else {
+                any = true;
+            }
+        }
+        if ((rc = upload_st()))
+            return rc;
+        if (!any)
+            break;
+        if (changed && (rc = rebuild()))
+            return rc;
+        // ---- GMRES cycle
+        for (int q = 0; q < ns; ++q) {
+            std::fill(hs[q].H.begin(), hs[q].H.end(), 0.0);
+            std::fill(hs[q].g.begin(), hs[q].g.end(), 0.0);
+            hs[q].g[0] = hs[q].beta;
+        }
+        // V_0 = w / beta (coefficient row holds |w|^2 with no vectors)
+        HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, 0, kw.c1.p, cst, kw.V.p,
+                              c->stream));
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *Vj = kw.V.p + (size_t)j * n;
+            HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, Vj, c->stream));
+            if ((rc = sweep_once(true, false)))
+                return rc;
+            HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, Vj, c->stream));
+            if ((rc = dots(kw.w.p, j + 1, false, kw.c1.p)))
+                return rc;
+            HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c1.p, cst, nullptr,
+                                  c->stream));
+            if ((rc = dots(kw.w.p, j + 1, true, kw.c2.p)))
+                return rc;
+            HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c2.p, cst,
+                                  kw.V.p + (size_t)(j + 1) * n, c->stream));
+            HIPCHK(hipMemcpyAsync(hc1.data(), kw.c1.p, hc1.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+            HIPCHK(hipMemcpyAsync(hc2.data(), kw.c2.p, hc2.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            k = j + 1;
+            bool all_done = true;
+            for (int q = 0; q < ns; ++q) {
+                GmresSlotHost &h = hs[q];
+                if (!h.live)
+                    continue;
+                h.sweeps += 1;
+                double *col = &h.H[(size_t)j * (m + 1)];
+                double n2 = hc2[(size_t)q * cst + j + 1];
+                for (int i = 0; i <= j; ++i) {
+                    col[i] = hc1[(size_t)q * cst + i] + hc2[(size_t)q * cst + i];
+                    n2 -= hc2[(size_t)q * cst + i] * hc2[(size_t)q * cst + i];
+                }
+                col[j + 1] = std::sqrt(std::max(n2, 0.0));
+                for (int i = 0; i < j; ++i) {
+                    const double a = h.cs[i] * col[i] + h.sn[i] * col[i + 1];
+                    col[i + 1] = -h.sn[i] * col[i] + h.cs[i] * col[i + 1];
+                    col[i] = a;
+                }
+                const double r = std::hypot(col[j], col[j + 1]);
+                h.cs[j] = r > 0.0 ? col[j] / r : 1.0;
+                h.sn[j] = r > 0.0 ? col[j + 1] / r : 0.0;
+                col[j] = r;
+                col[j + 1] = 0.0;
+                h.g[j + 1] = -h.sn[j] * h.g[j];
+                h.g[j] = h.cs[j] * h.g[j];
+                const double res = std::fabs(h.g[j + 1]);
+                if (!(res <= 1e-3 * h.beta) && h.sweeps < cap)
+                    all_done = false;
+            }
+            if (all_done)
+                break;
+        }
+        // x -= V y per slot, y from the triangular system of the cycle
+        std::fill(hy.begin(), hy.end(), 0.0);
+        for (int q = 0; q < ns; ++q) {
+            GmresSlotHost &h = hs[q];
+            if (!h.live)
+                continue;
+            std::vector<double> y(k, 0.0);
+            for (int i = k - 1; i >= 0; --i) {
+                double a = h.g[i];
+                for (int jj = i + 1; jj < k; ++jj)
+                    a -= h.H[(size_t)jj * (m + 1) + i] * y[jj];
+                const double dg = h.H[(size_t)i * (m + 1) + i];
+                y[i] = dg != 0.0 ? a / dg : 0.0;
+            }
+            for (int i = 0; i < k; ++i)
+                hy[(size_t)q * cst + i] = y[i];
+            h.sig = sigma_min_tri(h.H, m + 1, k);
+        }
+        HIPCHK(hipMemcpyAsync(kw.y.p, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, k, kw.y.p, cst, nullptr, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DVM_OK;
 }
 
 static int check_instance(const dvm_ctx *c, int instance)
@@ -891,17 +1358,19 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
     // the record of the first sweep (from zero or the warm moments); the stop
     // statistics it gathers are discarded
     HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     for (int i = i0; i < i1; ++i) {
         st[i].maxdiff_bits = st[i].maxabs_bits = 0ull;
     }
     // u1prev was refreshed by the record kernel; reset the max slots only
     HIPCHK(hipMemcpyAsync(c->d_st.p, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
                           c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     for (int i = i0; i < i1; ++i)
         c->inst[i].has_state = true;
 
     {
-        int rc = run_blocks(c, i0, i1, iter0, false, st);
+        int rc = iterate(c, i0, i1, iter0, false, st);
         if (rc)
             return rc;
     }
@@ -910,7 +1379,7 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
         const SolveState &s = st[i];
         if (info) {
             dvm_info &o = info[instance < 0 ? i : 0];
-            o.iters = s.iter - iter0[i];
+            o.iters = c->sweeps_done[i];
             o.sweeps_fp64 = o.iters;
             o.rel_change = s.eps;
             o.est_error = s.est;
@@ -1028,9 +1497,10 @@ static int grad_instance(dvm_ctx *c, int instance, double *dqdd_out, double *dqd
     HIPCHK(launch_record<double>(rec_args(c, true), c->max_cells, c->n_inst, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_st_adj.p, sa.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
                           c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     {
         std::vector<long long> iter0(c->n_inst, 0);
-        rc = run_blocks(c, instance, instance + 1, iter0, true, sa);
+        rc = iterate(c, instance, instance + 1, iter0, true, sa);
         if (rc)
             return rc;
     }
@@ -1125,6 +1595,10 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
         return fail(DVM_EINVAL, "block_iters must be in [0, 4096]");
     if (c.schedule != DVM_SCHED_SKEW && c.schedule != DVM_SCHED_WRAP)
         return fail(DVM_EINVAL, "unknown schedule");
+    if (c.accel != DVM_ACCEL_AUTO && c.accel != DVM_ACCEL_NONE && c.accel != DVM_ACCEL_GMRES)
+        return fail(DVM_EINVAL, "unknown acceleration");
+    if (c.krylov_dim < 0 || c.krylov_dim > 64)
+        return fail(DVM_EINVAL, "krylov_dim must be in [0, 64]");
     int V = c.vel_per_lane ? c.vel_per_lane : 4;
     int G = c.waves_per_block ? c.waves_per_block : 8;
     bool okvg = (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) || (V == 2 && G == 8);
@@ -1140,6 +1614,7 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->V = V;
     ctx->G = G;
     ctx->inst.assign(n_instances, HostInst{});
+    ctx->sweeps_done.assign(n_instances, 0);
     ctx->stream = (hipStream_t)hip_stream;   // NULL: a stream is made on first use
     build_quadrature(ctx);
     *out = ctx;

@@ -139,6 +139,8 @@ struct MomArgs {
 template <typename T>
 struct RecArgs {
     int adjoint;              // wall terms of the transposed problem
+    int homog;                // leave the drive out (linear part of the iteration map)
+    int monitor;              // fold |du1|, |u1| into the stop statistics
     const InstDev *inst;
     const uint8_t *codes;
     const double *mom;
@@ -184,5 +186,40 @@ hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, 
 hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_zero_f(float *p, size_t n, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+
+// ---- state vectors of the iteration (Krylov acceleration, refinement)
+// A run of consecutive elements of one solver buffer and its place in a
+// compact state vector.
+struct VSeg {
+    long long buf_off;   // element offset in the solver buffer
+    long long vec_off;   // element offset in the state vector
+    int len;
+    int buf;             // 0 moments, 1 seams, 2 wrap state, 3 wall faces
+};
+// A chunk of a state vector that belongs to one instance slot.
+struct VChunk {
+    long long start;
+    int len;
+    int slot;
+};
+struct StateBufs {
+    double *b[4];
+};
+enum { VCHUNK = 4096 };
+// vec[vec_off..] = buf[buf_off..]        (sub == nullptr)
+// vec[vec_off..] = sub[..] - buf[..]     (sub != nullptr)
+hipError_t launch_gather(const VSeg *seg, int nseg, StateBufs b, double *vec, const double *sub, hipStream_t s);
+// buf[buf_off..] = vec[vec_off..]
+hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const double *vec, hipStream_t s);
+// part[j][chunk] = <w, V_j> over the chunk, j < nvec; row nvec: <w, w> if with_norm
+hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const double *V, long long ldv, int nvec,
+                        int with_norm, double *part, hipStream_t s);
+// out[slot][j] = sum of part[j][chunk] over the slot's chunks (fixed order)
+hipError_t launch_vsum(const int *slot_chunk0, const int *slot_nchunk, int nslots, const double *part, int nch,
+                       int nrows, double *out, int ostride, hipStream_t s);
+// w -= sum_j coef[slot][j] V_j; if vout: vout = w / hn, hn from coef[slot]
+// (Pythagoras with the norm in coef[slot][nvec]); zero when hn == 0
+hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const double *V, long long ldv, int nvec,
+                          const double *coef, int cstride, double *vout, hipStream_t s);
 
 } // namespace dvm

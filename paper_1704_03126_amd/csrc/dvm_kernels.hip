@@ -587,7 +587,7 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
             rec[0] = T(dl * (r / a.m0 - t * a.c2));
             // drive: unit pressure gradient along x (forward); the adjoint
             // is driven by -dQ/dh / W = -(dx / nx) xi
-            const double drive = a.adjoint ? -1.0 / (in.inv_dx * (double)in.nx) : in.drive;
+            const double drive = a.homog ? 0.0 : a.adjoint ? -1.0 / (in.inv_dx * (double)in.nx) : in.drive;
             rec[1] = T(dl * (u1 / a.m2) + drive);
             rec[2] = T(dl * (u2 / a.m2));
             rec[3] = T(dl * t);
@@ -648,10 +648,12 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
                 for (int i = 0; i < 8; ++i)
                     dst[i] = rec[i];
             }
-            const double up = a.u1prev[cg];
-            diff = fabs(u1 - up);
-            absu = fabs(u1);
-            a.u1prev[cg] = u1;
+            if (a.monitor) {
+                const double up = a.u1prev[cg];
+                diff = fabs(u1 - up);
+                absu = fabs(u1);
+                a.u1prev[cg] = u1;
+            }
         }
     }
     // block max, then one atomic per block (max is order independent)
@@ -666,7 +668,7 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && a.monitor) {
         // a NaN anywhere must reach the status kernel: encode it as +inf
         double dmax = sd[0] != sd[0] ? __builtin_inf() : sd[0];
         double amax = sa[0] != sa[0] ? __builtin_inf() : sa[0];

@@ -27,6 +27,9 @@ DVM_FP64 = 0
 DVM_FP32_REFINE = 1
 DVM_SCHED_SKEW = 0
 DVM_SCHED_WRAP = 1
+DVM_ACCEL_AUTO = 0
+DVM_ACCEL_NONE = 1
+DVM_ACCEL_GMRES = 2
 STATUS_NAMES = {0: "running", 1: "converged", 2: "max_iter", 3: "diverged"}
 
 EXPORTED = ("dvm_create", "dvm_set_geometry", "dvm_solve", "dvm_solve_warm",
@@ -45,7 +48,8 @@ class dvm_config(ctypes.Structure):
                 ("max_iter", ctypes.c_long), ("block_iters", ctypes.c_int),
                 ("use_graphs", ctypes.c_int), ("vel_per_lane", ctypes.c_int),
                 ("waves_per_block", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
-                ("profile", ctypes.c_int), ("schedule", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("schedule", ctypes.c_int),
+                ("accel", ctypes.c_int), ("krylov_dim", ctypes.c_int)]
 
 
 class dvm_info(ctypes.Structure):
@@ -124,10 +128,11 @@ class Solver:
                  tol: float = 1e-8, max_iter: int = 200000, block_iters: int = 32,
                  use_graphs: bool = True, vel_per_lane: int = 0,
                  waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_SKEW,
-                 stream=None):
+                 accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, stream=None):
         lib = load_library()
         cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
-                         vel_per_lane, waves_per_block, None, int(profile), int(schedule))
+                         vel_per_lane, waves_per_block, None, int(profile), int(schedule),
+                         int(accel), int(krylov_dim))
         h = ctypes.c_void_p()
         s = stream if stream is not None else _current_stream()
         _check(lib.dvm_create(ctypes.byref(h), nv, n_instances, ctypes.byref(cfg), s))

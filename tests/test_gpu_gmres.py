@@ -1,0 +1,146 @@
+"""GMRES-accelerated iteration on the GPU, through the C ABI.
+
+Same sweeps, same discrete fixed point: the results are compared with the
+FP64 oracle (its source iteration, or its direct solve where the lagged
+iteration itself diverges) and with the plain iteration on the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.dense as dn
+from paper_1704_03126_amd.geometry import (Geometry, delta_field, plane_channel,
+                                           porous_discs, rough_channel)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dvm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1704_03126_amd.dvm as d
+    d.load_library()
+    return d
+
+
+def solve(dvm, g, delta, nv, alpha=1.0, tol=1e-10, **kw):
+    s = dvm.Solver(nv, 1, tol=tol, accel=dvm.DVM_ACCEL_GMRES, **kw)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    info = s.solve(0, delta, alpha)
+    Q, _ = s.flow_rate(0)
+    mom = s.moments(0)
+    return s, info, Q, mom
+
+
+@pytest.mark.parametrize("case,delta,alpha", [
+    ("rough", 0.1, 1.0), ("rough", 10.0, 1.0), ("rough", 1.0, 0.8),
+    ("porous", 1.0, 1.0), ("plane", 1.0, 1.0)])
+def test_gmres_matches_oracle(dvm, case, delta, alpha):
+    if case == "rough":
+        g, nv = rough_channel(64, 32, 6, 32), 12
+    elif case == "porous":
+        g, nv = porous_discs(64, 0.6, 1003), 8
+    else:
+        g, nv = plane_channel(64), 16
+    ref = oracle.si_solve(g.mask, delta, nv, periodic_y=g.periodic_y,
+                          cells_per_H=g.cells_per_H, alpha=alpha, tol=1e-12)
+    s, info, Q, mom = solve(dvm, g, delta, nv, alpha)
+    s.close()
+    assert info.status == "converged", info
+    assert abs(Q - ref.Q) <= 1e-8 * abs(ref.Q), (Q, ref.Q)
+    assert np.max(np.abs(mom["u1"] - ref.u1)) <= 1e-8
+
+
+def test_gmres_where_the_lagged_iteration_diverges(dvm):
+    """Both sweep orders have a geometry on which the plain iteration
+    diverges; GMRES on the same sweeps converges to the direct solution."""
+    m = np.zeros((16, 16), np.uint8)
+    m[6:10, 4:10] = 1
+    g = Geometry(mask=m, periodic_y=True, cells_per_H=16.0)
+    ref = oracle.si_solve(m, 0.7, 8, periodic_y=True, cells_per_H=16.0, tol=1e-12)
+    s, info, Q, mom = solve(dvm, g, 0.7, 8, schedule=dvm.DVM_SCHED_WRAP)
+    s.close()
+    assert info.status == "converged"
+    assert abs(Q - ref.Q) <= 1e-8 * abs(ref.Q)
+    g3 = porous_discs(8, 0.7, 5)
+    ref3 = dn.solve(g3.mask, 0.01, 6, periodic_y=True, cells_per_H=8.0)
+    s, info, Q3, mom3 = solve(dvm, g3, 0.01, 6, tol=1e-12)
+    s.close()
+    assert info.status == "converged"
+    assert abs(Q3 - ref3.Q) <= 1e-8 * abs(ref3.Q), (Q3, ref3.Q)
+    assert np.max(np.abs(mom3["u1"] - ref3.u1)) <= 1e-8
+
+
+def test_gmres_adjoint_multi_strip(dvm):
+    """Adjoint of a three-strip periodic porous cell in the default order
+    (the plain adjoint iteration diverges there): sum of dQ/d delta_c equals
+    the derivative of the uniform problem."""
+    g = porous_discs(130, 0.65, 1005)
+    nv = 8
+    s = dvm.Solver(nv, 1, tol=1e-12, accel=dvm.DVM_ACCEL_GMRES)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    s.solve(0, 1.0, 0.9)
+    gd, ga = s.grad(0)
+    eps = 1e-4
+    s.solve(0, 1.0 + eps, 0.9)
+    qp = s.flow_rate(0)[0]
+    s.solve(0, 1.0 - eps, 0.9)
+    qm = s.flow_rate(0)[0]
+    ea = 1e-4
+    s.solve(0, 1.0, 0.9 + ea)
+    qap = s.flow_rate(0)[0]
+    s.solve(0, 1.0, 0.9 - ea)
+    qam = s.flow_rate(0)[0]
+    s.close()
+    fd = (qp - qm) / (2 * eps)
+    assert abs(gd.sum() - fd) <= 1e-6 * abs(fd), (gd.sum(), fd)
+    fda = (qap - qam) / (2 * ea)
+    assert abs(ga - fda) <= 1e-6 * abs(fda), (ga, fda)
+
+
+def test_gmres_batched_equals_single(dvm):
+    gs = [rough_channel(48, 24, 4, 24), porous_discs(40, 0.6, 1010), plane_channel(16)]
+    deltas = [0.5, 2.0, 1.0]
+    nv = 8
+    b = dvm.Solver(nv, len(gs), tol=1e-10, accel=dvm.DVM_ACCEL_GMRES)
+    for i, g in enumerate(gs):
+        b.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
+    infos = b.solve(-1, deltas)
+    Qb = [b.flow_rate(i)[0] for i in range(len(gs))]
+    b.close()
+    for i, g in enumerate(gs):
+        assert infos[i].status == "converged"
+        ref = oracle.si_solve(g.mask, deltas[i], nv, periodic_y=g.periodic_y,
+                              cells_per_H=g.cells_per_H, tol=1e-12)
+        assert abs(Qb[i] - ref.Q) <= 1e-8 * abs(ref.Q), (i, Qb[i], ref.Q)
+
+
+def test_auto_hands_diverging_instances_to_gmres(dvm):
+    """Default mode: the plain iteration runs, stops contracting on the two
+    geometries above, and GMRES finishes them; a well-behaved instance in the
+    same batch stays on the plain iteration."""
+    m = np.zeros((16, 16), np.uint8)
+    m[6:10, 4:10] = 1
+    gs = [Geometry(mask=m, periodic_y=True, cells_per_H=16.0), rough_channel(32, 16, 3, 16)]
+    s = dvm.Solver(8, 2, tol=1e-10, schedule=dvm.DVM_SCHED_WRAP)
+    for i, g in enumerate(gs):
+        s.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
+    infos = s.solve(-1, [0.7, 1.0])
+    Qs = [s.flow_rate(i)[0] for i in range(2)]
+    s.close()
+    for i, g in enumerate(gs):
+        assert infos[i].status == "converged", infos[i]
+        ref = oracle.si_solve(g.mask, [0.7, 1.0][i], 8, periodic_y=g.periodic_y,
+                              cells_per_H=g.cells_per_H, tol=1e-12)
+        assert abs(Qs[i] - ref.Q) <= 1e-8 * abs(ref.Q), (i, Qs[i], ref.Q)
+    g3 = porous_discs(8, 0.7, 5)
+    ref3 = dn.solve(g3.mask, 0.01, 6, periodic_y=True, cells_per_H=8.0)
+    s = dvm.Solver(6, 1, tol=1e-12)
+    s.set_geometry(0, g3.mask, True, 8.0)
+    info = s.solve(0, 0.01)
+    Q3 = s.flow_rate(0)[0]
+    s.close()
+    assert info.status == "converged"
+    assert abs(Q3 - ref3.Q) <= 1e-8 * abs(ref3.Q)
