@@ -44,7 +44,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--precision", choices=["fp64"], default="fp64")
+    p.add_argument("--precision", choices=["fp64", "fp32_refine"], default="fp64",
+                   help="fp64 sweeps, or FP32 sweeps with FP64 defect correction")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
@@ -93,8 +94,9 @@ def main():
     K = NV * NV
     sched = dvm.DVM_SCHED_WRAP if args.schedule == "wrap" else dvm.DVM_SCHED_SKEW
     accel = {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE, "gmres": dvm.DVM_ACCEL_GMRES}[args.accel]
+    prec = dvm.DVM_FP32_REFINE if args.precision == "fp32_refine" else dvm.DVM_FP64
     solver = dvm.Solver(NV, 1, tol=TOL, vel_per_lane=args.vel, waves_per_block=args.waves,
-                        schedule=sched, accel=accel)
+                        schedule=sched, accel=accel, precision=prec)
     solver.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
 
     def step():
@@ -176,7 +178,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
                    "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
-                   "deltas": list(DELTAS), "tol": TOL, "precision": "fp64",
+                   "deltas": list(DELTAS), "tol": TOL, "precision": args.precision,
                    "schedule": args.schedule, "accel": args.accel, "parallelism": "single_gpu"},
         "iterations_per_delta": all_its[-1],
         "time_to_solution_s": dict(zip([str(d) for d in DELTAS],

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <string>
@@ -129,12 +130,22 @@ struct dvm_ctx {
     DevBuf<SolveState> d_st_adj;
 
     KrylovWork kw;
-    std::vector<long long> sweeps_done;   // per instance, last solve (GMRES)
+    std::vector<long long> sweeps_done;   // per instance, last solve
+    std::vector<long long> sweeps64_done; // of which FP64 sweeps
 
-    // captured iteration blocks: [0] forward, [1] adjoint
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    int graph_iters[2] = {0, 0};
-    int graph_mode[2] = {-1, -1};
+    // FP32 correction state of the refinement (allocated by the first
+    // DVM_FP32_REFINE solve)
+    bool fp32_ready = false;
+    DevBuf<float> d_srec32, d_seam32, d_wrap32, d_fb32, d_vt32;
+    DevBuf<double> d_mom_d, d_u1prev_d, d_xr, d_rr, d_er;
+    DevBuf<SolveState> d_st32;
+    DevBuf<VSeg2> d_seg32;
+    int nseg32 = 0;
+
+    // captured iteration blocks: [0] forward, [1] adjoint, [2] FP32 correction
+    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+    int graph_iters[3] = {0, 0, 0};
+    int graph_mode[3] = {-1, -1, -1};
 
     // profiling (cfg.profile): event pairs around sweep launches
     std::vector<hipEvent_t> ev_pool;
@@ -160,6 +171,9 @@ struct dvm_ctx {
         d_seam_adj.release(); d_wrap_adj.release(); d_fb_adj.release(); d_ckpt.release();
         d_part5.release(); d_momg.release(); d_dqda.release(); d_st_adj.release();
         kw.release();
+        d_srec32.release(); d_seam32.release(); d_wrap32.release(); d_fb32.release(); d_vt32.release();
+        d_mom_d.release(); d_u1prev_d.release(); d_xr.release(); d_rr.release(); d_er.release();
+        d_st32.release(); d_seg32.release();
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
     }
@@ -373,7 +387,7 @@ static int ensure_device(dvm_ctx *c)
 // -------------------------------------------------------------- layout
 static void drop_graphs(dvm_ctx *c)
 {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 3; ++i) {
         if (c->graph[i])
             (void)hipGraphExecDestroy(c->graph[i]);
         c->graph[i] = nullptr;
@@ -385,6 +399,7 @@ static int build_layout(dvm_ctx *c)
 {
     drop_graphs(c);
     c->adj_ready = false;
+    c->fp32_ready = false;
     const int V = c->V, G = c->G, P = V * G;
     c->gq = (c->K / 4 + P - 1) / P;
     c->kq = c->gq * P;
@@ -693,11 +708,78 @@ static int collect_profile(dvm_ctx *c)
     return DVM_OK;
 }
 
-// One source iteration for every active instance of the forward or the
-// adjoint problem.
-static int enqueue_iteration(dvm_ctx *c, bool adj)
+// Arguments of the FP32 correction iteration (refinement).
+static SweepArgs<float> sweep_args32(dvm_ctx *c)
 {
-    const bool prof = c->cfg.profile != 0 && !adj;
+    SweepArgs<float> a{};
+    a.inst = c->d_inst.p;
+    a.items = c->d_items.p;
+    a.srec = c->d_srec32.p;
+    a.scode = c->d_scode.p;
+    a.smap = c->d_smap.p;
+    a.sface = c->d_sface.p;
+    a.fb = c->d_fb32.p;
+    a.vtab = c->d_vt32.p;
+    a.delta_field = c->d_dfield.p;
+    a.part = c->d_part.p;
+    a.part5 = c->d_part5.p;
+    a.seam = c->d_seam32.p;
+    a.wrap = c->d_wrap32.p;
+    a.st = c->d_st32.p;
+    a.ncell = c->ncell;
+    a.seam_half = c->seam_half;
+    a.fb_half = std::max<long long>(c->nfaces, 1) * c->kp4;
+    a.gq = c->gq;
+    a.kq = c->kq;
+    a.kp4 = c->kp4;
+    a.force = 0;
+    return a;
+}
+
+static RecArgs<float> rec_args32(dvm_ctx *c)
+{
+    RecArgs<float> a{};
+    a.adjoint = 0;
+    a.homog = 1;
+    a.monitor = 1;
+    a.inst = c->d_inst.p;
+    a.codes = c->d_codes.p;
+    a.mom = c->d_mom_d.p;
+    a.delta_field = c->d_dfield.p;
+    a.u1prev = c->d_u1prev_d.p;
+    a.srec = c->d_srec32.p;
+    a.spos = c->d_spos.p;
+    a.st = c->d_st32.p;
+    a.m0 = c->m0;
+    a.m2 = c->m2;
+    a.c2 = c->c2;
+    a.c4 = c->c4;
+    a.D = c->D;
+    return a;
+}
+
+static StateBufs32 state32(dvm_ctx *c)
+{
+    StateBufs32 b;
+    b.mom = c->d_mom_d.p;
+    b.b[0] = c->d_seam32.p;
+    b.b[1] = c->d_wrap32.p;
+    b.b[2] = c->d_fb32.p;
+    return b;
+}
+
+static double refine_inner_tol(const dvm_ctx *c)
+{
+    return std::max(c->cfg.tol, 1e-4);
+}
+
+// One source iteration for every active instance: kind 0 forward, 1 adjoint,
+// 2 FP32 correction iteration of the refinement (homogeneous sweep, then the
+// FP64 residual added to the new state).
+static int enqueue_iteration(dvm_ctx *c, int kind)
+{
+    const bool adj = kind == 1;
+    const bool prof = c->cfg.profile != 0 && kind == 0;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     if (prof) {
         int rc = next_event(c, &e0);
@@ -706,6 +788,17 @@ static int enqueue_iteration(dvm_ctx *c, bool adj)
         if (rc)
             return rc;
         HIPCHK(hipEventRecord(e0, c->stream));
+    }
+    if (kind == 2) {
+        HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V, c->G, solve_mode(c), c->stream));
+        MomArgs m = mom_args(c);
+        m.mom = c->d_mom_d.p;
+        m.st = c->d_st32.p;
+        HIPCHK(launch_moments(m, c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
+        HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_status(c->d_st32.p, c->n_inst, refine_inner_tol(c), c->cfg.max_iter, c->stream));
+        return DVM_OK;
     }
     const int mode = solve_mode(c) | (adj ? MODE_ADJ : 0);
     HIPCHK(launch_sweep<double>(sweep_args(c, 0, adj), (int)c->items.size(), c->V, c->G, mode, c->stream));
@@ -723,17 +816,17 @@ static int enqueue_iteration(dvm_ctx *c, bool adj)
     return DVM_OK;
 }
 
-static int enqueue_block(dvm_ctx *c, int iters, bool adj)
+static int enqueue_block(dvm_ctx *c, int iters, int kind)
 {
     if (!c->cfg.use_graphs || c->cfg.profile) {
         for (int i = 0; i < iters; ++i) {
-            int rc = enqueue_iteration(c, adj);
+            int rc = enqueue_iteration(c, kind);
             if (rc)
                 return rc;
         }
         return DVM_OK;
     }
-    const int slot = adj ? 1 : 0;
+    const int slot = kind;
     const int mode = solve_mode(c);
     if (!c->graph[slot] || c->graph_iters[slot] != iters || c->graph_mode[slot] != mode) {
         if (c->graph[slot]) {
@@ -744,7 +837,7 @@ static int enqueue_block(dvm_ctx *c, int iters, bool adj)
         HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         int rc = DVM_OK;
         for (int i = 0; i < iters && rc == DVM_OK; ++i)
-            rc = enqueue_iteration(c, adj);
+            rc = enqueue_iteration(c, kind);
         hipError_t e = hipStreamEndCapture(c->stream, &g);
         if (rc)
             return rc;
@@ -766,16 +859,17 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
 // With stall detection (DVM_ACCEL_AUTO) an instance whose relative change of
 // u1 has not dropped by 5% over the last 64 iterations is stopped and flagged
 // in stalled[] (its state is that of a completed iteration).
-static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, bool adj,
+static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, int kind,
                       std::vector<SolveState> &st, std::vector<char> *stalled = nullptr)
 {
     const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
     const long long cap = c->cfg.max_iter;
     const long long W = 64;
-    SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
+    const double tol = kind == 2 ? refine_inner_tol(c) : c->cfg.tol;
+    SolveState *dst = kind == 1 ? c->d_st_adj.p : kind == 2 ? c->d_st32.p : c->d_st.p;
     std::vector<std::vector<std::pair<long long, double>>> hist(c->n_inst);
     for (;;) {
-        int rc = enqueue_block(c, B, adj);
+        int rc = enqueue_block(c, B, kind);
         if (rc)
             return rc;
         HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
@@ -798,7 +892,7 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                 for (const auto &e : hv)
                     if (e.first <= it - W)
                         old = e.second;
-                if (old > 0.0 && st[i].eps > c->cfg.tol && !(st[i].eps < 0.95 * old)) {
+                if (old > 0.0 && st[i].eps > tol && !(st[i].eps < 0.95 * old)) {
                     st[i].active = 0;
                     (*stalled)[i] = 1;
                     stop = true;
@@ -828,7 +922,7 @@ static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &ite
         return gmres_run(c, i0, i1, adj, st, prior);
     }
     std::vector<char> stalled(c->n_inst, 0);
-    int rc = run_blocks(c, i0, i1, iter0, adj, st, c->cfg.accel == DVM_ACCEL_AUTO ? &stalled : nullptr);
+    int rc = run_blocks(c, i0, i1, iter0, adj ? 1 : 0, st, c->cfg.accel == DVM_ACCEL_AUTO ? &stalled : nullptr);
     if (rc)
         return rc;
     std::vector<long long> prior(c->n_inst, 0);
@@ -1235,6 +1329,344 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
     return DVM_OK;
 }
 
+// ---------------------------------------------------------- refinement
+// DVM_FP32_REFINE: outer defect correction in FP64 around FP32 sweeps.
+//   r = x - F64(x)   (one FP64 iteration from the FP64 state x; eps64 is its
+//                     relative change of u1)
+//   solve (I - L) e = r with the FP32 source iteration e <- L32 e + r
+//                    (FP32 records, seams, wrap and wall values; moments
+//                     accumulated in FP64), to relative change 1e-4
+//   x <- x - e
+// An instance is accepted when eps64 * q / (1 - q) <= tol, q the contraction
+// observed in the last FP32 solve (the a-posteriori bound of the stop rule);
+// the accepted state is F64(x).  An instance whose FP32 iteration stalls or
+// diverges continues with the FP64 iteration.
+
+static int ensure_fp32(dvm_ctx *c)
+{
+    if (c->fp32_ready)
+        return DVM_OK;
+    const long long sk = c->sk_total, fh = std::max<long long>(c->nfaces, 1) * c->kp4;
+    HIPCHK(c->d_srec32.alloc(sk * REC_STRIDE));
+    HIPCHK(c->d_seam32.alloc(2 * c->seam_half));
+    HIPCHK(c->d_wrap32.alloc(c->wrap_total));
+    HIPCHK(c->d_fb32.alloc(2 * fh));
+    HIPCHK(c->d_vt32.alloc((size_t)c->n_inst * c->kp4 * VT_STRIDE));
+    HIPCHK(c->d_mom_d.alloc(c->ncell * MOM_STRIDE));
+    HIPCHK(c->d_u1prev_d.alloc(c->ncell));
+    HIPCHK(c->d_st32.alloc(c->n_inst));
+    HIPCHK(launch_zero_f(c->d_srec32.p, c->d_srec32.n, c->stream));
+    HIPCHK(launch_zero_f(c->d_seam32.p, c->d_seam32.n, c->stream));
+    HIPCHK(launch_zero_f(c->d_wrap32.p, c->d_wrap32.n, c->stream));
+    HIPCHK(launch_zero_f(c->d_fb32.p, c->d_fb32.n, c->stream));
+    HIPCHK(launch_zero(c->d_mom_d.p, c->d_mom_d.n, c->stream));
+    HIPCHK(launch_zero(c->d_u1prev_d.p, c->d_u1prev_d.n, c->stream));
+    std::vector<double> vt(c->d_vt.n);
+    HIPCHK(hipMemcpyAsync(vt.data(), c->d_vt.p, vt.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<float> vt32(vt.begin(), vt.end());
+    std::vector<SolveState> st(c->n_inst);
+    HIPCHK(hipMemcpyAsync(c->d_vt32.p, vt32.data(), vt32.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_st32.p, st.data(), st.size() * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->fp32_ready = true;
+    return DVM_OK;
+}
+
+static bool debug_on()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *e = std::getenv("DVM_DEBUG");
+        on = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st)
+{
+    int rc = ensure_fp32(c);
+    if (rc)
+        return rc;
+    const int mode = solve_mode(c);
+    const double tol = c->cfg.tol;
+    const long long cap = c->cfg.max_iter;
+    StateBufs sb;
+    sb.b[0] = c->d_mom.p;
+    sb.b[1] = c->d_seam.p;
+    sb.b[2] = c->d_wrap.p;
+    sb.b[3] = c->d_fb.p;
+
+    struct DSlot {
+        int inst;
+        long long off, len;
+        int pw;
+        bool live;
+        double q;
+        long long s32, s64;
+        bool fallback;
+    };
+    std::vector<DSlot> slots;
+    long long n = 0;
+    for (int i = i0; i < i1; ++i) {
+        if (!st[i].active)
+            continue;
+        DSlot d{i, n, 0, (int)(st[i].iter & 1), true, -1.0, 0, 0, false};
+        d.len = state_segments(c, i, d.pw, n, nullptr, nullptr);
+        n += d.len;
+        slots.push_back(d);
+    }
+    if (slots.empty())
+        return DVM_OK;
+    HIPCHK(c->d_xr.alloc(n));
+    HIPCHK(c->d_rr.alloc(n));
+    HIPCHK(c->d_er.alloc(n));
+    KrylovWork &kw = c->kw;
+    std::vector<VSeg> gseg, sseg;
+    auto rebuild = [&]() -> int {
+        gseg.clear();
+        sseg.clear();
+        std::vector<VSeg2> s2;
+        for (const auto &d : slots) {
+            if (!d.live)
+                continue;
+            state_segments(c, d.inst, d.pw, d.off, &gseg, &sseg);
+            std::vector<VSeg> g0, g1;
+            state_segments(c, d.inst, 0, d.off, &g0, nullptr);
+            state_segments(c, d.inst, 1, d.off, &g1, nullptr);
+            for (size_t k = 0; k < g0.size(); ++k)
+                s2.push_back(VSeg2{{g0[k].buf_off, g1[k].buf_off}, g0[k].vec_off, g0[k].len, g0[k].buf, d.inst});
+        }
+        HIPCHK(kw.gseg.alloc(std::max<size_t>(gseg.size(), 1)));
+        HIPCHK(kw.sseg.alloc(std::max<size_t>(sseg.size(), 1)));
+        HIPCHK(c->d_seg32.alloc(std::max<size_t>(s2.size(), 1)));
+        HIPCHK(hipMemcpyAsync(kw.gseg.p, gseg.data(), gseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(kw.sseg.p, sseg.data(), sseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->d_seg32.p, s2.data(), s2.size() * sizeof(VSeg2), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->nseg32 = (int)s2.size();
+        if (c->graph[2]) {                 // the captured block holds the old table
+            (void)hipGraphExecDestroy(c->graph[2]);
+            c->graph[2] = nullptr;
+        }
+        return DVM_OK;
+    };
+    if ((rc = rebuild()))
+        return rc;
+    auto upload = [&](SolveState *dst, std::vector<SolveState> &v) -> int {
+        HIPCHK(hipMemcpyAsync(dst, v.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return DVM_OK;
+    };
+    std::vector<SolveState> st32(c->n_inst);
+    HIPCHK(hipMemcpyAsync(st32.data(), c->d_st32.p, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(launch_gather(kw.sseg.p, (int)sseg.size(), sb, c->d_xr.p, nullptr, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+
+    for (;;) {
+        // ---- FP64 residual r = x - F64(x) and eps64
+        for (auto &d : slots)
+            if (d.live)
+                st[d.inst].maxdiff_bits = st[d.inst].maxabs_bits = 0ull;
+        if ((rc = upload(c->d_st.p, st)))
+            return rc;
+        HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, c->d_xr.p, c->stream));
+        HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_sweep<double>(sweep_args(c, 0, false), (int)c->items.size(), c->V, c->G, mode, c->stream));
+        HIPCHK(launch_moments(mom_args(c), c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, c->d_rr.p, c->d_xr.p, c->stream));
+        if ((rc = upload(c->d_st.p, st)))
+            return rc;
+        HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+        std::vector<SolveState> dev(c->n_inst);
+        HIPCHK(hipMemcpyAsync(dev.data(), c->d_st.p, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        bool changed = false, any = false;
+        for (auto &d : slots) {
+            if (!d.live)
+                continue;
+            SolveState &s = st[d.inst];
+            d.s64 += 1;
+            const double dmax = __builtin_bit_cast(double, (long long)dev[d.inst].maxdiff_bits);
+            const double amax = __builtin_bit_cast(double, (long long)dev[d.inst].maxabs_bits);
+            const double eps = amax > 0.0 ? dmax / amax : (dmax == 0.0 ? 0.0 : INFINITY);
+            const double est = d.q >= 0.0 ? eps * d.q / (1.0 - d.q) : INFINITY;
+            s.eps = eps;
+            s.est = est;
+            if (debug_on())
+                std::fprintf(stderr, "[dvm refine] inst %d fp64 step %lld: eps64 %.3e amax %.3e q %.4f est %.3e\n",
+                             d.inst, d.s64, eps, amax, d.q, est);
+            int fin = 0;
+            if (!(amax < 1e30) || eps != eps)
+                fin = STATUS_DIVERGED;
+            else if (eps <= 16.0 * 2.220446049250313e-16 || est <= tol)
+                fin = STATUS_CONVERGED;
+            else if (d.s32 + d.s64 >= cap)
+                fin = STATUS_MAXITER;
+            if (fin) {
+                s.iter += 1;              // the state holds F64(x)
+                s.status = fin;
+                s.active = 0;
+                s.maxdiff_bits = s.maxabs_bits = 0ull;
+                d.live = false;
+                changed = true;
+            } else {
+                any = true;
+            }
+        }
+        if ((rc = upload(c->d_st.p, st)))
+            return rc;
+        if (!any)
+            break;
+        if (changed && (rc = rebuild()))
+            return rc;
+        if (debug_on() && std::getenv("DVM_DEBUG_CMP")) {
+            // one homogeneous map of the residual vector in both precisions
+            std::vector<double> a64(n), a32(n);
+            HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, c->d_rr.p, c->stream));
+            RecArgs<double> ra = rec_args(c);
+            ra.homog = 1;
+            ra.monitor = 0;
+            HIPCHK(launch_record<double>(ra, c->max_cells, c->n_inst, c->stream));
+            HIPCHK(launch_sweep<double>(sweep_args(c, 0, false), (int)c->items.size(), c->V, c->G, mode, c->stream));
+            HIPCHK(launch_moments(mom_args(c), c->max_cells, c->n_inst, c->stream));
+            HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, c->d_er.p, nullptr, c->stream));
+            HIPCHK(hipMemcpyAsync(a64.data(), c->d_er.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            for (auto &d : slots)
+                st32[d.inst].active = d.live ? 1 : 0;
+            if ((rc = upload(c->d_st32.p, st32)))
+                return rc;
+            HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 1, c->stream));
+            RecArgs<float> r32 = rec_args32(c);
+            r32.monitor = 0;
+            HIPCHK(launch_record<float>(r32, c->max_cells, c->n_inst, c->stream));
+            HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V, c->G, mode, c->stream));
+            MomArgs m = mom_args(c);
+            m.mom = c->d_mom_d.p;
+            m.st = c->d_st32.p;
+            HIPCHK(launch_moments(m, c->max_cells, c->n_inst, c->stream));
+            HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_er.p, 3, c->stream));
+            HIPCHK(hipMemcpyAsync(a32.data(), c->d_er.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            double dmax = 0, amax64 = 0, amax32 = 0;
+            long long imax = 0;
+            for (long long k = 0; k < n; ++k) {
+                if (std::fabs(a64[k] - a32[k]) > dmax) {
+                    dmax = std::fabs(a64[k] - a32[k]);
+                    imax = k;
+                }
+                amax64 = std::max(amax64, std::fabs(a64[k]));
+                amax32 = std::max(amax32, std::fabs(a32[k]));
+            }
+            std::fprintf(stderr, "[dvm refine] L64 r vs L32 r: max|diff| %.3e at %lld (%.6e vs %.6e), max %.3e / %.3e\n",
+                         dmax, imax, a64[imax], a32[imax], amax64, amax32);
+            for (long long k = 0; k < std::min<long long>(n, 16); ++k)
+                std::fprintf(stderr, "   %lld: %.6e %.6e\n", k, a64[k], a32[k]);
+        }
+        // ---- FP32 correction: (I - L) e = r
+        std::vector<long long> iter0(c->n_inst, 0);
+        for (int i = 0; i < c->n_inst; ++i) {
+            SolveState &s = st32[i];
+            s.active = 0;
+            iter0[i] = s.iter;
+        }
+        for (auto &d : slots) {
+            if (!d.live)
+                continue;
+            SolveState &s = st32[d.inst];
+            s.active = 1;
+            s.status = STATUS_RUNNING;
+            s.npass = 0;
+            s.eps_prev = 0.0;
+            s.iter0 = s.iter;
+            s.maxdiff_bits = s.maxabs_bits = 0ull;
+        }
+        if ((rc = upload(c->d_st32.p, st32)))
+            return rc;
+        HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 1, c->stream));
+        HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
+        for (auto &d : slots)
+            if (d.live)
+                st32[d.inst].maxdiff_bits = st32[d.inst].maxabs_bits = 0ull;
+        if ((rc = upload(c->d_st32.p, st32)))
+            return rc;
+        std::vector<char> stalled(c->n_inst, 0);
+        if ((rc = run_blocks(c, i0, i1, iter0, 2, st32, &stalled)))
+            return rc;
+        bool fb = false;
+        for (auto &d : slots) {
+            if (!d.live)
+                continue;
+            const SolveState &s = st32[d.inst];
+            d.s32 += s.iter - iter0[d.inst];
+            if (debug_on())
+                std::fprintf(stderr, "[dvm refine] inst %d fp32 solve: %lld iterations status %d eps %.3e "
+                             "eps_prev %.3e stalled %d\n", d.inst, s.iter - iter0[d.inst], s.status, s.eps,
+                             s.eps_prev, (int)stalled[d.inst]);
+            // contraction of the last FP32 iterations: the stop rule's bound
+            // est = eps q / (1 - q) (the status kernel has already replaced
+            // eps_prev by eps)
+            if (s.status == STATUS_CONVERGED && s.eps > 0.0 && std::isfinite(s.est) && s.est > 0.0)
+                d.q = std::min(s.est / (s.eps + s.est), 0.9999);
+            else
+                d.q = 0.9999;
+            if (stalled[d.inst] || s.status == STATUS_DIVERGED) {
+                d.fallback = true;
+                d.live = false;
+                fb = true;
+            }
+        }
+        // ---- x <- x - e
+        HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_er.p, 2, c->stream));
+        HIPCHK(launch_axpy(c->d_xr.p, c->d_er.p, -1.0, n, c->stream));
+        if (fb) {
+            // back to the FP64 state x for the instances that leave
+            HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, c->d_xr.p, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if ((rc = rebuild()))
+                return rc;
+        }
+    }
+    for (const auto &d : slots) {
+        c->sweeps_done[d.inst] = d.s32 + d.s64;
+        c->sweeps64_done[d.inst] = d.s64;
+    }
+    // instances whose FP32 iteration did not contract: FP64 from x
+    bool any_fb = false;
+    std::vector<long long> iter0(c->n_inst, 0);
+    for (int i = 0; i < c->n_inst; ++i)
+        iter0[i] = st[i].iter;
+    for (const auto &d : slots)
+        if (d.fallback) {
+            SolveState &s = st[d.inst];
+            s.active = 1;
+            s.status = STATUS_RUNNING;
+            s.npass = 0;
+            s.eps_prev = 0.0;
+            any_fb = true;
+        }
+    if (!any_fb)
+        return DVM_OK;
+    HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+    for (const auto &d : slots)
+        if (d.fallback)
+            st[d.inst].maxdiff_bits = st[d.inst].maxabs_bits = 0ull;
+    if ((rc = upload(c->d_st.p, st)))
+        return rc;
+    std::vector<long long> before(c->n_inst);
+    for (const auto &d : slots)
+        before[d.inst] = c->sweeps_done[d.inst];
+    rc = iterate(c, i0, i1, iter0, false, st);
+    for (const auto &d : slots)
+        if (d.fallback) {
+            c->sweeps64_done[d.inst] += c->sweeps_done[d.inst];
+            c->sweeps_done[d.inst] += before[d.inst];
+        }
+    return rc;
+}
+
 static int check_instance(const dvm_ctx *c, int instance)
 {
     if (!c)
@@ -1370,7 +1802,8 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
         c->inst[i].has_state = true;
 
     {
-        int rc = iterate(c, i0, i1, iter0, false, st);
+        int rc = c->cfg.precision == DVM_FP32_REFINE ? dc_run(c, i0, i1, st)
+                                                     : iterate(c, i0, i1, iter0, false, st);
         if (rc)
             return rc;
     }
@@ -1380,7 +1813,7 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
         if (info) {
             dvm_info &o = info[instance < 0 ? i : 0];
             o.iters = c->sweeps_done[i];
-            o.sweeps_fp64 = o.iters;
+            o.sweeps_fp64 = c->cfg.precision == DVM_FP32_REFINE ? c->sweeps64_done[i] : o.iters;
             o.rel_change = s.eps;
             o.est_error = s.est;
             o.status = s.status;
@@ -1615,6 +2048,7 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->G = G;
     ctx->inst.assign(n_instances, HostInst{});
     ctx->sweeps_done.assign(n_instances, 0);
+    ctx->sweeps64_done.assign(n_instances, 0);
     ctx->stream = (hipStream_t)hip_stream;   // NULL: a stream is made on first use
     build_quadrature(ctx);
     *out = ctx;

@@ -217,6 +217,28 @@ hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const double
 // out[slot][j] = sum of part[j][chunk] over the slot's chunks (fixed order)
 hipError_t launch_vsum(const int *slot_chunk0, const int *slot_nchunk, int nslots, const double *part, int nch,
                        int nrows, double *out, int ostride, hipStream_t s);
+// A run of the FP32 correction state (refinement): element offsets for
+// sweeps that write parity 0 and parity 1 (moments: equal).
+struct VSeg2 {
+    long long off[2];
+    long long vec_off;
+    int len;
+    int buf;             // 0 moments (FP64), 1 seams, 2 wrap state, 3 wall faces (FP32)
+    int inst;
+};
+struct StateBufs32 {
+    double *mom;
+    float *b[3];         // seams, wrap state, wall faces
+};
+// what: 0 -- state outputs of the sweep just run (parity st.iter & 1) += vec
+//            (instances that are not iterating are left alone)
+//       1 -- state inputs of the next sweep (parity (st.iter & 1) ^ 1) = vec
+//       2 -- vec = state inputs of the next sweep
+//       3 -- vec = state outputs of the sweep just run
+hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b, double *vec, int what,
+                          hipStream_t s);
+// y += a * x (n elements)
+hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream_t s);
 // w -= sum_j coef[slot][j] V_j; if vout: vout = w / hn, hn from coef[slot]
 // (Pythagoras with the norm in coef[slot][nvec]); zero when hn == 0
 hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const double *V, long long ldv, int nvec,

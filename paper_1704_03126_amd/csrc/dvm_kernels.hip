@@ -871,6 +871,17 @@ static hipError_t launch_special(const SweepArgs<double> &a, int n, int mode, hi
 #undef DVM_SP
 }
 
+// FP32 sweeps (refinement): specular walls only
+template <int G>
+static hipError_t launch_special_f(const SweepArgs<float> &a, int n, int mode, hipStream_t s)
+{
+    if (mode == MODE_SPEC)
+        return launch_sweep_t<float, 4, G, MODE_SPEC>(a, n, s);
+    if (mode == (MODE_SPEC | MODE_FIELD))
+        return launch_sweep_t<float, 4, G, MODE_SPEC | MODE_FIELD>(a, n, s);
+    return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, int mode, hipStream_t s)
 {
@@ -880,6 +891,11 @@ hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, int mod
                 return launch_special<8>(a, nitems, mode, s);
             if (V * G == 16)
                 return launch_special<4>(a, nitems, mode, s);
+        } else {
+            if (V * G == 32)
+                return launch_special_f<8>(a, nitems, mode, s);
+            if (V * G == 16)
+                return launch_special_f<4>(a, nitems, mode, s);
         }
         return hipErrorInvalidValue;
     }

@@ -97,6 +97,63 @@ __global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, co
     }
 }
 
+__global__ void __launch_bounds__(256) k_state32(const VSeg2 *seg, const SolveState *st, StateBufs32 b,
+                                                 double *vec, int what)
+{
+    const VSeg2 sg = seg[blockIdx.x];
+    // the add runs inside captured blocks of iterations: an instance that
+    // has stopped iterating keeps its state
+    if (what == 0 && st[sg.inst].active == 0)
+        return;
+    const int par = (int)(st[sg.inst].iter & 1);
+    const long long off = sg.off[(what == 0 || what == 3) ? par : par ^ 1];
+    double *v = vec + sg.vec_off;
+    if (sg.buf == 0) {
+        double *m = b.mom + off;
+        for (int i = threadIdx.x; i < sg.len; i += 256) {
+            if (what == 0)
+                m[i] += v[i];
+            else if (what == 1)
+                m[i] = v[i];
+            else
+                v[i] = m[i];
+        }
+    } else {
+        float *f = b.b[sg.buf - 1] + off;
+        for (int i = threadIdx.x; i < sg.len; i += 256) {
+            if (what == 0)
+                f[i] = (float)((double)f[i] + v[i]);
+            else if (what == 1)
+                f[i] = (float)v[i];
+            else
+                v[i] = (double)f[i];
+        }
+    }
+}
+
+hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b, double *vec, int what,
+                          hipStream_t s)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_state32, dim3(nseg), dim3(256), 0, s, seg, st, b, vec, what);
+    return hipGetLastError();
+}
+
+__global__ void k_axpy(double *y, const double *x, double a, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = fma(a, x[i], y[i]);
+}
+
+hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3(1024), dim3(256), 0, s, y, x, a, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(const VSeg *seg, int nseg, StateBufs b, double *vec, const double *sub, hipStream_t s)
 {
     if (nseg == 0)

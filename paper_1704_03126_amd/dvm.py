@@ -138,6 +138,7 @@ class Solver:
         _check(lib.dvm_create(ctypes.byref(h), nv, n_instances, ctypes.byref(cfg), s))
         self._h = h
         self._lib = lib
+        self.epoch = 0              # bumped by every solve (autograd checks it)
         self.nv = nv
         self.n_instances = n_instances
         self.shapes = [None] * n_instances
@@ -178,6 +179,7 @@ class Solver:
         n = self.n_instances if instance < 0 else 1
         infos = (dvm_info * n)()
         fn = self._lib.dvm_solve_warm if warm else self._lib.dvm_solve
+        self.epoch += 1
         rc = fn(self._h, instance, _ptr(d), field, float(alpha), infos)
         if rc != DVM_OK and not (rc == DVM_ENOCONV and not raise_on_noconv):
             _check(rc)

@@ -150,3 +150,36 @@ def test_grad_requires_converged_solve(dvm):
         s.grad(0)
     assert e.value.code == dvm.DVM_ESTATE
     s.close()
+
+
+def test_autograd_function(dvm):
+    """torch.autograd: gradients of a loss through Q match the C ABI's
+    gradient and central differences of the loss."""
+    import torch
+    from paper_1704_03126_amd.autograd import flow_rate
+    g = rough_channel(32, 16, 3, 16)
+    nv = 8
+    s = _solver(dvm, g.mask, g.periodic_y, g.cells_per_H, nv, tol=1e-13)
+    base = np.where(g.mask == 0, delta_field(g.mask.shape, 21, mean=1.0, amp=0.2), 0.0)
+    delta = torch.tensor(base, dtype=torch.float64, requires_grad=True)
+    alpha = torch.tensor(0.85, dtype=torch.float64, requires_grad=True)
+    Q = flow_rate(s, delta, alpha)
+    loss = Q * Q
+    loss.backward()
+    s.solve(0, base, 0.85)
+    gd, ga = s.grad(0)
+    Qv = float(Q)
+    assert np.allclose(delta.grad.numpy(), 2 * Qv * gd, rtol=1e-12, atol=0)
+    assert abs(float(alpha.grad) - 2 * Qv * ga) <= 1e-12 * abs(2 * Qv * ga)
+    # uniform delta as a 0-d tensor: the gradient is the sum over cells
+    d0 = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    Q0 = flow_rate(s, d0, 1.0)
+    Q0.backward()
+    eps = 1e-5
+    s.solve(0, 1.0 + eps)
+    qp = s.flow_rate(0)[0]
+    s.solve(0, 1.0 - eps)
+    qm = s.flow_rate(0)[0]
+    s.close()
+    fd = (qp - qm) / (2 * eps)
+    assert abs(float(d0.grad) - fd) <= 1e-6 * abs(fd)
