@@ -75,11 +75,14 @@ typedef struct {
     long max_iter;          /* iteration cap per solve; default 200000        */
     int block_iters;        /* iterations per captured launch block; 0 -> 32  */
     int use_graphs;         /* 1: replay blocks as HIP graphs; 0: plain launches */
-    int vel_per_lane;       /* velocities per lane: 0 = default, 2, 4 or 8    */
-    int waves_per_block;    /* waves per workgroup: 0 = default, 4 or 8;
-                               supported pairs (V, G): (4,8) (8,4) (4,4)
-                               (2,8)                                          */
-    const char *tune_cache; /* autotune cache file or NULL (in-memory only)   */
+    int vel_per_lane;       /* velocities per lane: 2, 4 or 8                 */
+    int waves_per_block;    /* waves per workgroup: 4 or 8; supported pairs
+                               (V, G): (4,8) (8,4) (4,4) (2,8).  Both 0: the
+                               pair is chosen by timing a few sweeps of the
+                               geometries at the first solve (per precision;
+                               kept per process and in tune_cache)            */
+    const char *tune_cache; /* autotune cache file (appended to) or NULL;
+                               the string is copied                           */
     int profile;            /* 1: time every sweep launch with HIP events on
                                the context's stream (replaces graph replay);
                                read the totals with dvm_profile              */

@@ -12,6 +12,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -103,6 +106,10 @@ struct dvm_ctx {
     // layout of the device buffers
     bool layout_ok = false;
     int V = 8, G = 8, gq = 0, kq = 0, kp4 = 0, max_cells = 0;
+    int V32 = 4, G32 = 8;        // shape of the FP32 sweeps (same V * G)
+    bool autotune = false;       // choose (V, G) by timing at the first solve
+    bool tuned = false;
+    std::string tune_path;       // copy of cfg.tune_cache (the caller's string is not kept)
     long long ncell = 0, seam_half = 0, wrap_total = 0;
     std::vector<InstDev> idev;
     std::vector<WorkItem> items;
@@ -439,6 +446,10 @@ static int build_layout(dvm_ctx *c)
     std::stable_sort(c->items.begin(), c->items.end(), [&](const WorkItem &a, const WorkItem &b) {
         return c->idev[a.inst].tp > c->idev[b.inst].tp;
     });
+    for (int i = 0; i < c->n_inst; ++i)
+        if ((long long)c->inst[i].nx * 2 * c->kp4 >= (1ll << 31))
+            return fail(DVM_EINVAL, "instance " + std::to_string(i) +
+                                        ": nx too large for the velocity grid (nx * 2 * padded velocities >= 2^31)");
     c->ncell = cell;
     c->seam_half = seam;
     c->wrap_total = wrap;
@@ -790,7 +801,8 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         HIPCHK(hipEventRecord(e0, c->stream));
     }
     if (kind == 2) {
-        HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V, c->G, solve_mode(c), c->stream));
+        HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32, solve_mode(c),
+                                   c->stream));
         MomArgs m = mom_args(c);
         m.mom = c->d_mom_d.p;
         m.st = c->d_st32.p;
@@ -1542,7 +1554,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st)
             RecArgs<float> r32 = rec_args32(c);
             r32.monitor = 0;
             HIPCHK(launch_record<float>(r32, c->max_cells, c->n_inst, c->stream));
-            HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V, c->G, mode, c->stream));
+            HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32, mode, c->stream));
             MomArgs m = mom_args(c);
             m.mom = c->d_mom_d.p;
             m.st = c->d_st32.p;
@@ -1582,6 +1594,10 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st)
             s.eps_prev = 0.0;
             s.iter0 = s.iter;
             s.maxdiff_bits = s.maxabs_bits = 0ull;
+            // relative accuracy this correction needs: the error estimate of
+            // x must drop below tol (with a margin), within what FP32 resolves
+            const double need = std::isfinite(st[d.inst].est) ? 0.3 * tol / st[d.inst].est : 1e-4;
+            s.tol = std::min(1e-4, std::max(need, 1e-5));
         }
         if ((rc = upload(c->d_st32.p, st32)))
             return rc;
@@ -1667,6 +1683,182 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st)
     return rc;
 }
 
+// ------------------------------------------------------------ autotuner
+// The sweep shape (V velocities per lane, G waves per workgroup) is chosen
+// by timing a few sweeps of the actual geometries: the FP64 shape, and for
+// DVM_FP32_REFINE the FP32 shape among those with the same V * G (the
+// layout of partials and seams depends only on V * G).  Results are kept per
+// process and, with cfg.tune_cache, in a text file (one line per problem:
+// key, then V G V32 G32), so the choice is stable across contexts.
+
+struct TuneResult {
+    int V, G, V32, G32;
+};
+
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneResult> g_tune;
+
+static std::string tune_key(const dvm_ctx *c)
+{
+    std::string k = "nv" + std::to_string(c->nv) + " p" + std::to_string(c->cfg.precision) + " s" +
+                    std::to_string(c->cfg.schedule);
+    for (const auto &h : c->inst)
+        k += " " + std::to_string(h.nx) + "x" + std::to_string(h.ny) + (h.periodic_y ? "p" : "w");
+    return k;
+}
+
+static bool tune_file_read(const std::string &path, const std::string &key, TuneResult &r)
+{
+    if (path.empty())
+        return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t bar = line.rfind('|');
+        if (bar == std::string::npos || line.substr(0, bar) != key)
+            continue;
+        TuneResult t{};
+        if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d", &t.V, &t.G, &t.V32, &t.G32) == 4) {
+            r = t;
+            return true;
+        }
+    }
+    return false;
+}
+
+// file first (a cache written by another process wins), then this process
+static bool tune_lookup(dvm_ctx *c, const std::string &key, TuneResult &r)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (tune_file_read(c->tune_path, key, r)) {
+        g_tune[key] = r;
+        return true;
+    }
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+        r = it->second;
+        return true;
+    }
+    return false;
+}
+
+// remember the choice in this process and in the cache file (once per key)
+static void tune_store(dvm_ctx *c, const std::string &key, const TuneResult &r)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = r;
+    TuneResult old{};
+    if (!c->tune_path.empty() && !tune_file_read(c->tune_path, key, old)) {
+        std::ofstream f(c->tune_path, std::ios::app);
+        f << key << "|" << r.V << " " << r.G << " " << r.V32 << " " << r.G32 << "\n";
+    }
+}
+
+static int upload_inst(dvm_ctx *c)
+{
+    HIPCHK(hipMemcpyAsync(c->d_inst.p, c->idev.data(), c->n_inst * sizeof(InstDev), hipMemcpyHostToDevice,
+                          c->stream));
+    return DVM_OK;
+}
+
+// average milliseconds of one sweep launch of every instance in shape (V, G)
+template <typename T>
+static int time_sweep(dvm_ctx *c, int V, int G, double *ms)
+{
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    hipError_t err = hipSuccess;
+    for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+        if (rep == 1)
+            err = hipEventRecord(e0, c->stream);
+        if (err == hipSuccess) {
+            if constexpr (sizeof(T) == 8)
+                err = launch_sweep<double>(sweep_args(c, 1, false), (int)c->items.size(), V, G, 0, c->stream);
+            else {
+                SweepArgs<float> a = sweep_args32(c);
+                a.force = 1;
+                err = launch_sweep<float>(a, (int)c->items.size(), V, G, 0, c->stream);
+            }
+        }
+    }
+    if (err == hipSuccess)
+        err = hipEventRecord(e1, c->stream);
+    if (err == hipSuccess)
+        err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess)
+        err = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(err);
+    *ms = t / 3.0;
+    return DVM_OK;
+}
+
+static int autotune(dvm_ctx *c)
+{
+    c->tuned = true;
+    const std::string key = tune_key(c);
+    TuneResult best{c->V, c->G, c->V32, c->G32};
+    if (!tune_lookup(c, key, best)) {
+        static const int shapes[4][2] = {{4, 8}, {8, 4}, {4, 4}, {2, 8}};
+        const bool r32 = c->cfg.precision == DVM_FP32_REFINE;
+        double best_t = INFINITY;
+        for (int P : {32, 16}) {
+            int v0 = 0, g0 = 0;
+            for (auto &sh : shapes)
+                if (sh[0] * sh[1] == P && !v0) {
+                    v0 = sh[0];
+                    g0 = sh[1];
+                }
+            c->V = v0;
+            c->G = g0;
+            int rc = build_layout(c);
+            if (!rc) rc = upload_inst(c);
+            if (!rc && r32) rc = ensure_fp32(c);
+            if (rc)
+                return rc;
+            double t64 = INFINITY, t32 = INFINITY;
+            int bv = v0, bg = g0, bv32 = v0, bg32 = g0;
+            for (auto &sh : shapes) {
+                if (sh[0] * sh[1] != P)
+                    continue;
+                double t = 0.0;
+                if ((rc = time_sweep<double>(c, sh[0], sh[1], &t)))
+                    return rc;
+                if (t < t64) {
+                    t64 = t;
+                    bv = sh[0];
+                    bg = sh[1];
+                }
+                if (r32) {
+                    if ((rc = time_sweep<float>(c, sh[0], sh[1], &t)))
+                        return rc;
+                    if (t < t32) {
+                        t32 = t;
+                        bv32 = sh[0];
+                        bg32 = sh[1];
+                    }
+                }
+            }
+            // refinement: nearly all sweeps are FP32
+            const double score = r32 ? t32 : t64;
+            if (score < best_t) {
+                best_t = score;
+                best = TuneResult{bv, bg, bv32, bg32};
+            }
+        }
+    }
+    tune_store(c, key, best);
+    c->V = best.V;
+    c->G = best.G;
+    c->V32 = best.V32;
+    c->G32 = best.G32;
+    c->layout_ok = false;
+    return DVM_OK;
+}
+
 static int check_instance(const dvm_ctx *c, int instance)
 {
     if (!c)
@@ -1710,6 +1902,11 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
     }
     {
         int rc = ensure_device(c);
+        if (rc)
+            return rc;
+    }
+    if (c->autotune && !c->tuned) {
+        int rc = autotune(c);
         if (rc)
             return rc;
     }
@@ -2045,6 +2242,12 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->n_inst = n_instances;
     ctx->cfg = c;
     ctx->V = V;
+    ctx->V32 = V;
+    ctx->G32 = G;
+    ctx->autotune = c.vel_per_lane == 0 && c.waves_per_block == 0;
+    if (c.tune_cache)
+        ctx->tune_path = c.tune_cache;
+    ctx->cfg.tune_cache = nullptr;
     ctx->G = G;
     ctx->inst.assign(n_instances, HostInst{});
     ctx->sweeps_done.assign(n_instances, 0);
@@ -2087,6 +2290,7 @@ int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny, const uint8_t *
     h.has_geom = true;
     ctx->inst[instance] = std::move(h);
     ctx->layout_ok = false;
+    ctx->tuned = false;
     return DVM_OK;
 }
 

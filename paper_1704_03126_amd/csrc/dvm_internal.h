@@ -89,6 +89,8 @@ struct SolveState {
     int pad0;
     double eps, eps_prev, est;
     unsigned long long maxdiff_bits, maxabs_bits;
+    double tol;           // stop tolerance of this instance (0: the launch's)
+    double pad1;
 };
 
 // face record of a sweep entry (alpha < 1 and the gradient): faces whose

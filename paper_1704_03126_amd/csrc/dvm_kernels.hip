@@ -108,7 +108,8 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     // moments gathered: 4 (rho, u1, u2, e) and an extra one (P12 or gradient)
     constexpr int NACC = P12 ? 1 : (GRAD ? 5 : 4);
     // steps per partial flush: the whole chunk unless LDS is short
-    constexpr int FL = (FACES || NACC > 4 || G > 8) ? C / 2 : C;
+    // (FP32 sweeps: half the partial buffer, so two workgroups share a CU)
+    constexpr int FL = (FACES || NACC > 4 || G > 8 || sizeof(T) == 4) ? C / 2 : C;
     constexpr int P = G * V;                   // velocities of the group
     constexpr int UPE = 8 * sizeof(T) / 16;    // 16-byte units per record
     __shared__ __attribute__((aligned(16))) T st_rec[2][C][64][8];
@@ -327,7 +328,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     // one step (s-th of the chunk in buffer b); (PA, PB, PX) and (HA, HB) are
     // the register roles of this step in the rotation; hold: keep the
     // registers when the lane has no cell at this step (xa false)
-    auto step = [&](int b, int s, int t, T *PA, T *PB, T *PX, T *HA, T *HB, bool hold, bool xa) {
+    auto step = [&](int b, int s, int t, T *PA, T *PB, T *PX, T *HA, T *HB, bool hold, bool xa, int xr) {
         const int sl = s % FL;
         double acc[NACC];
 #pragma unroll
@@ -357,8 +358,9 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const T p1 = PA[v], p2 = PB[v], h1 = HA[v];
-            const T sm1 = has_up ? st_seam[b][s][1][wave * V + v] : T(0);
-            const T sm2 = has_up ? st_seam[b][s][0][wave * V + v] : T(0);
+            // staged as zero when the strip has no upstream neighbour
+            const T sm1 = st_seam[b][s][1][wave * V + v];
+            const T sm2 = st_seam[b][s][0][wave * V + v];
             const T hS1 = dpp_shr1(sm1, p1);
             const T hS2 = dpp_shr1(sm2, h1);
             T gxv = gx, gyv = gy;
@@ -417,10 +419,11 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         }
         // the last two rows of the strip feed the next strip next iteration
         if (!P12 && has_down && t < tp && lane >= hs - 2 && lane < hs && xa) {
-            const int clx = st_cell[b][s][lane];
-            const int xx = clx >= 0 ? clx % nx : (xpos ? wrap_mod(t - lane, tp) : nx - 1 - wrap_mod(t - lane, tp));
+            // x of this lane's cell from its running position on the diagonal
+            // (the seam of one strip holds < 2^31 values, checked on the host)
+            const int xx = xpos ? xr : nx - 1 - xr;
             const int slot = lane - (hs - 2);
-            T *sp = seam_out + (size_t)xx * seam_row + (size_t)slot * a.kp4 + kw;
+            T *sp = seam_out + (xx * (2 * a.kp4) + slot * a.kp4 + kw);
 #pragma unroll
             for (int v = 0; v < V; ++v)
                 sp[v] = hout[v];
@@ -459,34 +462,37 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         if (c + 1 < nchunks)
             issue(c + 1);
         bool xa[C];
+        int xrs[C];
         {
             int xr = xr0;
 #pragma unroll
             for (int s = 0; s < C; ++s) {
                 xa[s] = (t0 + s < tp) && (xr < nx);
+                xrs[s] = xr;
                 xr = (xr + 1 == tp) ? 0 : xr + 1;
             }
         }
-        const bool fast = !skew && t0 + C <= tp;
+        // every lane has a cell at every step of the chunk: no register holds
+        const bool fast = skew ? (t0 >= 63 && t0 + C <= nx) : (t0 + C <= tp);
         // register roles cycle with period 6: (A,B,X)(H0,H1) -> (X,A,B)(H1,H0) -> ...
         if (fast) {
-            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, false, true);
-            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, false, true);
-            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, false, true);
+            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, false, true, xrs[0]);
+            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, false, true, xrs[1]);
+            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, false, true, xrs[2]);
             if (FL == 3)
                 flush(b, 0);
-            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, false, true);
-            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, false, true);
-            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, false, true);
+            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, false, true, xrs[3]);
+            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, false, true, xrs[4]);
+            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, false, true, xrs[5]);
         } else {
-            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, true, xa[0]);
-            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, true, xa[1]);
-            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, true, xa[2]);
+            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, true, xa[0], xrs[0]);
+            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, true, xa[1], xrs[1]);
+            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, true, xa[2], xrs[2]);
             if (FL == 3)
                 flush(b, 0);
-            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, true, xa[3]);
-            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, true, xa[4]);
-            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, true, xa[5]);
+            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, true, xa[3], xrs[3]);
+            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, true, xa[4], xrs[4]);
+            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, true, xa[5], xrs[5]);
         }
         xr0 = (xr0 + C) % tp;
         if (c + 1 < nchunks)
@@ -785,14 +791,15 @@ __global__ void k_status(SolveState *st, int n, double tol, long long max_iter)
     // Sec. II.A stop rule on the relative change of u1, with the a-posteriori
     // bound from the observed contraction, on 3 consecutive iterations; a
     // change at the round-off floor passes without the bound.
+    const double tl = s.tol > 0.0 ? s.tol : tol;
     int pass = 0;
     double est = eps;
     if (eps <= 16.0 * 2.220446049250313e-16) {
         pass = 1;
-    } else if (eps <= tol && s.eps_prev > 0.0) {
+    } else if (eps <= tl && s.eps_prev > 0.0) {
         const double rh = eps / s.eps_prev;
         est = rh < 1.0 ? eps * rh / (1.0 - rh) : __builtin_inf();
-        pass = rh < 1.0 && est <= tol;
+        pass = rh < 1.0 && est <= tl;
     }
     s.npass = pass ? s.npass + 1 : 0;
     s.eps_prev = eps;

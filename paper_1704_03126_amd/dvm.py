@@ -128,10 +128,12 @@ class Solver:
                  tol: float = 1e-8, max_iter: int = 200000, block_iters: int = 32,
                  use_graphs: bool = True, vel_per_lane: int = 0,
                  waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_SKEW,
-                 accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, stream=None):
+                 accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, tune_cache: str | None = None,
+                 stream=None):
         lib = load_library()
+        tc = tune_cache.encode() if tune_cache else None
         cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
-                         vel_per_lane, waves_per_block, None, int(profile), int(schedule),
+                         vel_per_lane, waves_per_block, tc, int(profile), int(schedule),
                          int(accel), int(krylov_dim))
         h = ctypes.c_void_p()
         s = stream if stream is not None else _current_stream()

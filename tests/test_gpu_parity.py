@@ -226,3 +226,27 @@ def test_block_in_periodic_cell_default_schedule(dvm):
     Q, _, mom, info = gpu_solve(dvm, g, 0.7, 8)
     assert info.status == "converged"
     assert_parity(Q, mom, ref, qtol=1e-8, utol=1e-8)
+
+
+def test_autotuner_cache(dvm, tmp_path):
+    """Default shape selection: the tuned solve equals an explicit-shape
+    solve to round-off, writes its choice to the cache file, and a new
+    context reads it back."""
+    g = rough_channel(64, 32, 6, 32)
+    cache = str(tmp_path / "tune.txt")
+    s = dvm.Solver(12, 1, tol=1e-11, tune_cache=cache)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    s.solve(0, 1.0)
+    Q1 = s.flow_rate(0)[0]
+    s.close()
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and "|" in lines[0]
+    V, G, V32, G32 = map(int, lines[0].split("|")[1].split())
+    assert (V, G) in [(4, 8), (8, 4), (4, 4), (2, 8)] and V * G == V32 * G32
+    Q2, _, _, _ = gpu_solve(dvm, g, 1.0, 12, vel=V, waves=G)
+    assert abs(Q1 - Q2) <= 1e-12 * abs(Q2)
+    s = dvm.Solver(12, 1, tol=1e-11, tune_cache=cache)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    s.solve(0, 1.0)
+    s.close()
+    assert len(open(cache).read().strip().splitlines()) == 1
