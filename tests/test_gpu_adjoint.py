@@ -168,7 +168,7 @@ def test_autograd_function(dvm):
     loss.backward()
     s.solve(0, base, 0.85)
     gd, ga = s.grad(0)
-    Qv = float(Q)
+    Qv = float(Q.detach())
     assert np.allclose(delta.grad.numpy(), 2 * Qv * gd, rtol=1e-12, atol=0)
     assert abs(float(alpha.grad) - 2 * Qv * ga) <= 1e-12 * abs(2 * Qv * ga)
     # uniform delta as a 0-d tensor: the gradient is the sum over cells
@@ -183,3 +183,40 @@ def test_autograd_function(dvm):
     s.close()
     fd = (qp - qm) / (2 * eps)
     assert abs(float(d0.grad) - fd) <= 1e-6 * abs(fd)
+
+
+def test_adjoint_full_size_porous(dvm):
+    """The adjoint configuration at full size: 256 x 256 periodic porous cell
+    (porosity 0.55), log-normal delta(x) smoothed over 8 cells, alpha 0.9,
+    48 x 48 velocities, FP64.  dQ/d delta_c against central differences on
+    16 seeded fluid cells, dQ/d alpha against its central difference."""
+    g = porous_discs(256, 0.55, 3005)
+    nv, alpha = 48, 0.9
+    base = np.where(g.mask == 0, delta_field(g.mask.shape, 3006), 0.0)
+    s = _solver(dvm, g.mask, g.periodic_y, g.cells_per_H, nv, tol=1e-13)
+    s.solve(0, base, alpha)
+    Q0 = s.flow_rate(0)[0]
+    gd, ga = s.grad(0)
+    fl = np.argwhere(g.mask == 0)
+    cells = fl[np.random.default_rng(3007).choice(len(fl), 16, replace=False)]
+    scale = np.max(np.abs(gd))
+    for y, x in cells:
+        eps = 1e-3 * base[y, x]
+        d = base.copy()
+        d[y, x] += eps
+        s.solve(0, d, alpha, warm=True)
+        qp = s.flow_rate(0)[0]
+        d[y, x] -= 2 * eps
+        s.solve(0, d, alpha, warm=True)
+        qm = s.flow_rate(0)[0]
+        fd = (qp - qm) / (2 * eps)
+        assert abs(gd[y, x] - fd) <= 1e-4 * scale + 1e-4 * abs(fd), (y, x, gd[y, x], fd)
+    ea = 1e-4
+    s.solve(0, base, alpha + ea, warm=True)
+    qp = s.flow_rate(0)[0]
+    s.solve(0, base, alpha - ea, warm=True)
+    qm = s.flow_rate(0)[0]
+    s.close()
+    fda = (qp - qm) / (2 * ea)
+    assert abs(ga - fda) <= 1e-6 * abs(fda), (ga, fda)
+    assert np.isfinite(Q0) and Q0 > 0
