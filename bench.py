@@ -141,6 +141,7 @@ def main():
         flops_per_launch = float(nf) * K * FLOPS_PER_UPDATE
         achieved = flops_per_launch / avg_sweep_s
         traffic = None
+        traffic_detail = None
         tr = None
         if args.traffic_json:
             with open(args.traffic_json) as f:
@@ -148,13 +149,15 @@ def main():
         else:
             tr = measured_traffic()
         if tr is not None:
-            traffic = {"fetch_bytes_per_launch": tr["fetch_bytes"],
-                       "write_bytes_per_launch": tr["write_bytes"],
-                       "bytes_per_update": (tr["fetch_bytes"] + tr["write_bytes"]) / (nf * K),
-                       "hbm_GBps_at_avg_launch": (tr["fetch_bytes"] + tr["write_bytes"]) / avg_sweep_s / 1e9,
-                       "source": tr.get("source", "")}
+            traffic = tr["fetch_bytes"] + tr["write_bytes"]
+            traffic_detail = {"fetch_bytes_per_launch": tr["fetch_bytes"],
+                              "write_bytes_per_launch": tr["write_bytes"],
+                              "bytes_per_update": traffic / (nf * K),
+                              "hbm_GBps_at_avg_launch": traffic / avg_sweep_s / 1e9,
+                              "source": tr.get("source", "")}
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": traffic,
+                    "traffic_detail": traffic_detail,
                     "kernel": "k_sweep<double>", "avg_launch_ms": avg_sweep_s * 1e3,
                     "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": nf * K,
                     "sweep_share_of_iteration": sweep_ms / max(sweep_ms + other_ms, 1e-30)}
