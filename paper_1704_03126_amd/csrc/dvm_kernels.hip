@@ -510,38 +510,51 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
 }
 
 // ----------------------------------------------------------------- moments
+// 256 threads = 64 cells x 4 quadrants: each thread sums its quadrant's
+// groups in order, the four quadrant sums are combined in a fixed order
 __global__ void __launch_bounds__(256) k_moments(MomArgs a)
 {
+    __shared__ double qs[4][64][4];
     const int inst = blockIdx.y;
     const InstDev in = a.inst[inst];
     if (!a.force && a.st[inst].active == 0)
         return;
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= in.nx * in.ny)
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int c = blockIdx.x * 64 + l;
+    const bool valid = c < in.nx * in.ny;
+    const long long cg = in.cell_off + (valid ? c : 0);
+    const bool fluid = valid && a.codes[cg] != 0xFF;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    if (fluid) {
+        for (int g = q * a.gq; g < (q + 1) * a.gq; ++g) {
+            const double4 p = *reinterpret_cast<const double4 *>(a.part + ((size_t)g * a.ncell + cg) * 4);
+            s0 += p.x;
+            s1 += p.y;
+            s2 += p.z;
+            s3 += p.w;
+        }
+    }
+    qs[q][l][0] = s0;
+    qs[q][l][1] = s1;
+    qs[q][l][2] = s2;
+    qs[q][l][3] = s3;
+    __syncthreads();
+    if (q != 0 || !valid)
         return;
-    const long long cg = in.cell_off + c;
     double *m = a.mom + cg * MOM_STRIDE;
-    if (a.codes[cg] == 0xFF) {
+    if (!fluid) {
         for (int i = 0; i < MOM_STRIDE; ++i)
             m[i] = 0.0;
         return;
     }
     double r = 0, u1 = 0, u2 = 0, e = 0, fxp = 0, fxm = 0, fyp = 0, fym = 0;
-    for (int q = 0; q < 4; ++q) {
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int g = q * a.gq; g < (q + 1) * a.gq; ++g) {
-            const double *p = a.part + ((size_t)g * a.ncell + cg) * 4;
-            s0 += p[0];
-            s1 += p[1];
-            s2 += p[2];
-            s3 += p[3];
-        }
-        r += s0;
-        u1 += s1;
-        u2 += s2;
-        e += s3;
-        if ((q & 1) == 0) fxp += s1; else fxm += s1;
-        if ((q & 2) == 0) fyp += s2; else fym += s2;
+    for (int qq = 0; qq < 4; ++qq) {
+        r += qs[qq][l][0];
+        u1 += qs[qq][l][1];
+        u2 += qs[qq][l][2];
+        e += qs[qq][l][3];
+        if ((qq & 1) == 0) fxp += qs[qq][l][1]; else fxm += qs[qq][l][1];
+        if ((qq & 2) == 0) fyp += qs[qq][l][2]; else fym += qs[qq][l][2];
     }
     m[MOM_RHO] = r;
     m[MOM_U1] = u1;
@@ -922,7 +935,7 @@ template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, int, int,
 
 hipError_t launch_moments(const MomArgs &a, int max_cells, int n_inst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_moments, dim3((max_cells + 255) / 256, n_inst), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_moments, dim3((max_cells + 63) / 64, n_inst), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
