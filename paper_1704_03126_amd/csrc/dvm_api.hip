@@ -298,11 +298,22 @@ static long long neighbour(const HostInst &h, long long c, int d)
 static uint8_t adjoint_nibble(int up, int down)
 {
     if (up == CODE_NONE)
-        return CODE_NONE;
+        return NIB_ZERO;
     const int ai = down == CODE_WALL ? 1 : 0;
-    const int pi = up == CODE_WALL ? 2 : (down == CODE_WALL ? 1 : 0);
-    const int qi = up == CODE_INT ? 0 : 1;
-    return (uint8_t)(NIB_ADJ0 + 6 * ai + 2 * pi + qi);
+    const int pi = up == CODE_WALL ? 2 : (down == CODE_WALL ? 1 : 0);   // w1 = 2, 1.5, 0
+    const int qi = up == CODE_INT ? 0 : 1;                              // w2 = -0.5, 0
+    return (uint8_t)(NIB_ONE * ai + 2 * pi + qi);
+}
+
+// Stencil nibble of the forward transport for the code of the upwind side.
+static uint8_t forward_nibble(int up)
+{
+    switch (up) {
+    case CODE_INT: return NIB_INT;
+    case CODE_NEAR: return NIB_NEAR;
+    case CODE_WALL: return NIB_ONE + NIB_ZERO;
+    default: return NIB_ZERO;
+    }
 }
 
 // Every fluid component must wrap around the x period (carry a net flux);
@@ -504,7 +515,7 @@ static int build_layout(dvm_ctx *c)
     // nibbles of the forward and the adjoint problem, and the wall faces each
     // problem reads and writes.
     const FaceRec none{-1, -1, -1, -1, 0.f, 0.f, 0.f, 0.f};
-    std::vector<uint8_t> scode(sk, 0x33), scode_adj(sk, 0x33);
+    std::vector<uint8_t> scode(sk, NIB_ZERO * 17), scode_adj(sk, NIB_ZERO * 17);
     std::vector<int> smap(sk, -1);
     std::vector<long long> spos(cell * 4, -1);
     std::vector<FaceRec> sface(sk, none), sface_adj(sk, none);
@@ -550,7 +561,7 @@ static int build_layout(dvm_ctx *c)
                         spos[(d.cell_off + cl) * 4 + q] = e;
                         const int cxu = (code >> (2 * dxs)) & 3, cxd = (code >> (2 * dxd)) & 3;
                         const int cyu = (code >> (2 * dys)) & 3, cyd = (code >> (2 * dyd)) & 3;
-                        scode[e] = (uint8_t)(cxu | (cyu << 4));
+                        scode[e] = (uint8_t)(forward_nibble(cxu) | (forward_nibble(cyu) << 4));
                         scode_adj[e] = (uint8_t)(adjoint_nibble(cxu, cxd) | (adjoint_nibble(cyu, cyd) << 4));
                         // forward: the wall value on an upwind wall face has a
                         // specular share of that face's incident values; the

@@ -17,14 +17,14 @@ enum { CODE_INT = 0, CODE_NEAR = 1, CODE_WALL = 2, CODE_NONE = 3 };
 // bit 0 = same for y; 4 = no cell
 enum { NSTENCIL = 5, STENCIL_SOLID = 4 };
 
-// Per-axis stencil nibble of a sweep entry (low nibble x, high nibble y).
-// Each nibble indexes a table of (w1, w2, diagonal weight 1?) so that the
-// sweep evaluates  diag * h = ... + c (w1 h_1 + w2 h_2 + face term).
-//   0..3  forward codes: INT (2, -0.5, 1.5), NEAR (1.5, 0, 1.5),
-//         WALL (0, 0, 1), NONE (0, 0, -)
-//   4..15 adjoint (transposed) stencils: 4 + 6*ai + 2*pi + qi with diagonal
-//         weight {1.5, 1}[ai], w1 {2, 1.5, 0}[pi], w2 {-0.5, 0}[qi]
-enum { NIB_ADJ0 = 4, NNIB = 16 };
+// Per-axis stencil nibble of a sweep entry (low nibble x, high nibble y):
+// bit 3 = the diagonal weight is 1 (a wall face on the relevant side), else
+// 1.5; bits 0-2 select the neighbour weights (w1, w2) so that the sweep
+// evaluates  diag * h = ... + c (w1 h_1 + w2 h_2 + face term):
+//   0 (2, -0.5)   1 (2, 0)   2 (1.5, -0.5)   3 (1.5, 0)   4 (0, -0.5)   5 (0, 0)
+// Forward codes: INT -> 0, NEAR -> 3, WALL -> 8 + 5, NONE -> 5.  Adjoint
+// (transposed) stencils use every pair (see adjoint_nibble on the host).
+enum { NIB_ONE = 8, NIB_INT = 0, NIB_NEAR = 3, NIB_ZERO = 5, NWPAIR = 8 };
 
 // sweep modes (template bit flags)
 enum {

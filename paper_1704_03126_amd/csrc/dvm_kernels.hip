@@ -119,8 +119,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     __shared__ __attribute__((aligned(16))) FaceRec st_face[FACES ? 2 : 1][FACES ? C : 1][64];
     __shared__ double lds_part[FL][G][64][NACC];
     __shared__ T lds_rinv[P][NSTENCIL];
-    __shared__ T lds_lut[NNIB][2];
-    __shared__ int lds_aone[NNIB];
+    __shared__ T lds_lut[NWPAIR][2];
 
     const WorkItem it = a.items[blockIdx.x];
     const InstDev in = a.inst[it.inst];
@@ -158,24 +157,12 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             lds_rinv[v][ci] = (ci == STENCIL_SOLID || w == T(0) || den == T(0)) ? T(0) : T(1) / den;
         }
     }
-    if (tid < NNIB) {
-        T w1 = T(0), w2 = T(0);
-        int one = 0;
-        if (tid == CODE_INT) {
-            w1 = T(2); w2 = T(-0.5);
-        } else if (tid == CODE_NEAR) {
-            w1 = T(1.5);
-        } else if (tid == CODE_WALL) {
-            one = 1;
-        } else if (tid >= NIB_ADJ0) {
-            const int r = tid - NIB_ADJ0, ai = r / 6, pi = (r / 2) % 3, qi = r % 2;
-            w1 = pi == 0 ? T(2) : (pi == 1 ? T(1.5) : T(0));
-            w2 = qi == 0 ? T(-0.5) : T(0);
-            one = ai;
-        }
+    if (tid < NWPAIR) {
+        // neighbour weight pairs of the stencil nibbles (bits 0-2)
+        const T w1 = tid < 2 ? T(2) : tid < 4 ? T(1.5) : T(0);
+        const T w2 = (tid & 1) == 0 && tid < 6 ? T(-0.5) : T(0);
         lds_lut[tid][0] = w1;
         lds_lut[tid][1] = w2;
-        lds_aone[tid] = one;
     }
 
     const bool has_up = ypos ? (it.strip > 0 || in.periodic_y)
@@ -341,9 +328,9 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         const bool solid = cl < 0;
         const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
         const T gx = rec[4], gy = rec[5];
-        const T px = lds_lut[xn][0], qx = lds_lut[xn][1];
-        const T py = lds_lut[yn][0], qy = lds_lut[yn][1];
-        const int aox = lds_aone[xn], aoy = lds_aone[yn];
+        const T px = lds_lut[xn & 7][0], qx = lds_lut[xn & 7][1];
+        const T py = lds_lut[yn & 7][0], qy = lds_lut[yn & 7][1];
+        const int aox = xn >> 3, aoy = yn >> 3;
         const int ci = solid ? STENCIL_SOLID : 2 * aox + aoy;
         T ax = T(0), ay = T(0), dl = T(0);
         if (FIELD) {
@@ -400,10 +387,10 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                 // adjoint -- the cell value
                 if (fr.wrx >= 0)
                     fb_wr[(size_t)fr.wrx * a.kp4 + kw + v] =
-                        ADJ ? h : (xn == CODE_WALL ? h : T(1.5) * h - T(0.5) * p1);
+                        ADJ ? h : (aox ? h : T(1.5) * h - T(0.5) * p1);
                 if (fr.wry >= 0)
                     fb_wr[(size_t)fr.wry * a.kp4 + kw + v] =
-                        ADJ ? h : (yn == CODE_WALL ? h : T(1.5) * h - T(0.5) * hS1);
+                        ADJ ? h : (aoy ? h : T(1.5) * h - T(0.5) * hS1);
             }
             if (CKPT && !solid && xa)
                 a.ckpt[((size_t)cbase + cl) * a.kp4 + kw + v] = hd;
