@@ -686,6 +686,13 @@ static RecArgs<double> rec_args(dvm_ctx *c, bool adj = false)
     return a;
 }
 
+// MODE_XU when the V velocities of every wave share one xi node: velocities
+// are ordered (|xi| index, |eta| index) within a quadrant, nv/2 per |xi|
+static int xu_flag(const dvm_ctx *c, int V)
+{
+    return ((c->nv / 2) % V == 0) ? MODE_XU : 0;
+}
+
 // sweep mode of the instances being solved: per-cell delta, specular walls
 static int solve_mode(const dvm_ctx *c)
 {
@@ -812,8 +819,8 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         HIPCHK(hipEventRecord(e0, c->stream));
     }
     if (kind == 2) {
-        HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32, solve_mode(c),
-                                   c->stream));
+        HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32,
+                                   solve_mode(c) | xu_flag(c, c->V32), c->stream));
         MomArgs m = mom_args(c);
         m.mom = c->d_mom_d.p;
         m.st = c->d_st32.p;
@@ -823,7 +830,7 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         HIPCHK(launch_status(c->d_st32.p, c->n_inst, refine_inner_tol(c), c->cfg.max_iter, c->stream));
         return DVM_OK;
     }
-    const int mode = solve_mode(c) | (adj ? MODE_ADJ : 0);
+    const int mode = solve_mode(c) | (adj ? MODE_ADJ : xu_flag(c, c->V));
     HIPCHK(launch_sweep<double>(sweep_args(c, 0, adj), (int)c->items.size(), c->V, c->G, mode, c->stream));
     if (prof)
         HIPCHK(hipEventRecord(e1, c->stream));

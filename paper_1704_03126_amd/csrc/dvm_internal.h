@@ -34,6 +34,7 @@ enum {
     MODE_P12 = 8,     // diagnostic pass: shear stress only, no state written
     MODE_CKPT = 16,   // forward pass that also stores h and the face values
     MODE_GRAD = 32,   // adjoint pass that also accumulates sum W nu h(-v)
+    MODE_XU = 64,     // plain passes: the V velocities of a wave share one xi
 };
 
 // per-velocity constants, VT_STRIDE values per velocity, velocities ordered

@@ -102,6 +102,9 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     constexpr bool P12 = (MODE & MODE_P12) != 0;
     constexpr bool CKPT = (MODE & MODE_CKPT) != 0;
     constexpr bool GRAD = (MODE & MODE_GRAD) != 0;
+    // xi (and |xi|/dx) uniform over the wave's velocities: the collision gain's
+    // b0 + b1 xi and the u1 partial (xi times the density partial) once per step
+    constexpr bool XU = (MODE & MODE_XU) != 0;
     constexpr bool FACES = SPEC || CKPT || GRAD;          // face records needed
     constexpr bool FBWRITE = (SPEC || CKPT || GRAD) && !P12;
     constexpr int C = SWEEP_C;                 // steps per chunk
@@ -276,17 +279,19 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     double cw[V], cwxi[V], cweta[V], cwq[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const int k = (kw + v) * VT_STRIDE;
+        const int k = (kw + (XU ? 0 : v)) * VT_STRIDE;
+        const int kv = (kw + v) * VT_STRIDE;
         cxi[v] = ldc(vt, k + VT_XI);
-        ceta[v] = ldc(vt, k + VT_ETA);
-        cqq[v] = ldc(vt, k + VT_Q);
         ccx[v] = ldc(vt, k + VT_CX);
-        ccy[v] = ldc(vt, k + VT_CY);
-        cw[v] = (double)ldc(vt, k + VT_W);
+        ceta[v] = ldc(vt, kv + VT_ETA);
+        cqq[v] = ldc(vt, kv + VT_Q);
+        ccy[v] = ldc(vt, kv + VT_CY);
+        cw[v] = (double)ldc(vt, kv + VT_W);
         cwxi[v] = cw[v] * (double)cxi[v];
         cweta[v] = cw[v] * (double)ceta[v];
         cwq[v] = cw[v] * (double)cqq[v];
     }
+    const double xi0 = (double)cxi[0];
 
     // rotating registers: x-upwind values A (prev1), B (prev2), X (free);
     // y-upwind chain H0 (current hs1), H1 (free)
@@ -338,6 +343,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             ay = aoy ? T(1) : T(1.5);
             dl = rec[6];
         }
+        const T sbase = XU ? fma(b1, cxi[0], b0) : T(0);
         FaceRec fr;
         if (FACES)
             fr = st_face[b][s][lane];
@@ -358,7 +364,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                 if (fr.rdy >= 0)
                     gyv = fma(T(fr.ky) * spec, fb_rd[(size_t)fr.rdy * a.kp4 + kmy + v], gyv);
             }
-            const T S = fma(b3, cqq[v], fma(b2, ceta[v], fma(b1, cxi[v], b0)));
+            const T S = fma(b3, cqq[v], fma(b2, ceta[v], XU ? sbase : fma(b1, cxi[v], b0)));
             const T ux = fma(px, p1, fma(qx, p2, gxv));
             const T uy = fma(py, hS1, fma(qy, hS2, gyv));
             const T g = fma(ccx[v], ux, fma(ccy[v], uy, S));
@@ -375,7 +381,8 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                 acc[0] = fma(cwxi[v] * (double)ceta[v], hd, acc[0]);
             } else {
                 acc[0] = fma(cw[v], hd, acc[0]);
-                acc[1] = fma(cwxi[v], hd, acc[1]);
+                if (!XU)
+                    acc[1] = fma(cwxi[v], hd, acc[1]);
                 acc[2] = fma(cweta[v], hd, acc[2]);
                 acc[3] = fma(cwq[v], hd, acc[3]);
                 if (GRAD && !solid)
@@ -404,6 +411,8 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                 HB[v] = hS1;
             }
         }
+        if (XU && !P12)
+            acc[1] = xi0 * acc[0];
         // the last two rows of the strip feed the next strip next iteration
         if (!P12 && has_down && t < tp && lane >= hs - 2 && lane < hs && xa) {
             // x of this lane's cell from its running position on the diagonal
@@ -848,11 +857,13 @@ static hipError_t launch_sweep_t(const SweepArgs<T> &a, int nitems, hipStream_t 
 template <typename T, int V, int G>
 static hipError_t launch_plain(const SweepArgs<T> &a, int n, int mode, hipStream_t s)
 {
-    if (mode == 0)
-        return launch_sweep_t<T, V, G, 0>(a, n, s);
-    if (mode == MODE_FIELD)
-        return launch_sweep_t<T, V, G, MODE_FIELD>(a, n, s);
-    return hipErrorInvalidValue;
+    switch (mode) {
+    case 0: return launch_sweep_t<T, V, G, 0>(a, n, s);
+    case MODE_FIELD: return launch_sweep_t<T, V, G, MODE_FIELD>(a, n, s);
+    case MODE_XU: return launch_sweep_t<T, V, G, MODE_XU>(a, n, s);
+    case MODE_XU | MODE_FIELD: return launch_sweep_t<T, V, G, MODE_XU | MODE_FIELD>(a, n, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // the other modes run with 4 velocities per lane, in the wave count that
@@ -892,7 +903,8 @@ static hipError_t launch_special_f(const SweepArgs<float> &a, int n, int mode, h
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T> &a, int nitems, int V, int G, int mode, hipStream_t s)
 {
-    if ((mode & ~MODE_FIELD) != 0) {
+    if ((mode & ~(MODE_FIELD | MODE_XU)) != 0) {
+        mode &= ~MODE_XU;
         if constexpr (sizeof(T) == 8) {
             if (V * G == 32)
                 return launch_special<8>(a, nitems, mode, s);
