@@ -557,10 +557,13 @@ static int build_layout(dvm_ctx *c)
                         const uint8_t code = h.codes[cl];
                         if (code == 0xFF)
                             continue;
-                        smap[e] = (int)cl;
                         spos[(d.cell_off + cl) * 4 + q] = e;
                         const int cxu = (code >> (2 * dxs)) & 3, cxd = (code >> (2 * dxd)) & 3;
                         const int cyu = (code >> (2 * dys)) & 3, cyd = (code >> (2 * dyd)) & 3;
+                        // wall terms: forward on WALL sides, adjoint also on NEAR sides
+                        const bool wall = cxu == CODE_WALL || cxu == CODE_NEAR || cyu == CODE_WALL ||
+                                          cyu == CODE_NEAR;
+                        smap[e] = (int)cl | (wall ? SMAP_WALL : 0);
                         scode[e] = (uint8_t)(forward_nibble(cxu) | (forward_nibble(cyu) << 4));
                         scode_adj[e] = (uint8_t)(adjoint_nibble(cxu, cxd) | (adjoint_nibble(cyu, cyd) << 4));
                         // forward: the wall value on an upwind wall face has a

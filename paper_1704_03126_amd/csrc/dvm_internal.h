@@ -78,6 +78,11 @@ struct WorkItem {
     int inst, strip, group, pad;
 };
 
+// skewed cell map entries: fluid cell index, with this bit set when the
+// cell has a wall term on an upwind side (the record's wall values are read
+// only then); -1 for no cell
+enum { SMAP_WALL = 1 << 30, SMAP_CELL = (1 << 30) - 1 };
+
 // grids at least this wide use the wrap-around diagonal schedule
 enum { WRAP_MIN = 8 };
 

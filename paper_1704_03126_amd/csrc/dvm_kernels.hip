@@ -328,11 +328,17 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             acc[m] = 0.0;
         const T *rec = &st_rec[b][s][lane][0];
         const int code = st_code[b][s][lane];
-        const int cl = st_cell[b][s][lane];
+        const int craw = st_cell[b][s][lane];
         const int xn = code & 15, yn = code >> 4;
-        const bool solid = cl < 0;
+        const bool solid = craw < 0;
+        const int cl = craw & SMAP_CELL;
         const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
-        const T gx = rec[4], gy = rec[5];
+        // wall values only where the cell has a wall term (LDS bandwidth)
+        T gx = T(0), gy = T(0);
+        if (FIELD || (craw & SMAP_WALL) != 0) {
+            gx = rec[4];
+            gy = rec[5];
+        }
         const T px = lds_lut[xn & 7][0], qx = lds_lut[xn & 7][1];
         const T py = lds_lut[yn & 7][0], qy = lds_lut[yn & 7][1];
         const int aox = xn >> 3, aoy = yn >> 3;
@@ -434,9 +440,10 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         __syncthreads();
         for (int e = tid; e < FL * 64 * NACC; e += 64 * G) {
             const int sl = e / (64 * NACC), l = (e / NACC) % 64, m = e % NACC;
-            const int cl = st_cell[b][s0 + sl][l];
-            if (cl < 0)
+            const int craw = st_cell[b][s0 + sl][l];
+            if (craw < 0)
                 continue;
+            const int cl = craw & SMAP_CELL;
             double sum = 0.0;
 #pragma unroll
             for (int w = 0; w < G; ++w)
