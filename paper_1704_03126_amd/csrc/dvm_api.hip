@@ -1794,13 +1794,17 @@ static int time_sweep(dvm_ctx *c, int V, int G, double *ms)
         if (rep == 1)
             err = hipEventRecord(e0, c->stream);
         if (err == hipSuccess) {
+            // sweep + group sum: the velocity-group size sets both costs
             if constexpr (sizeof(T) == 8)
-                err = launch_sweep<double>(sweep_args(c, 1, false), (int)c->items.size(), V, G, 0, c->stream);
+                err = launch_sweep<double>(sweep_args(c, 1, false), (int)c->items.size(), V, G, xu_flag(c, V),
+                                           c->stream);
             else {
                 SweepArgs<float> a = sweep_args32(c);
                 a.force = 1;
-                err = launch_sweep<float>(a, (int)c->items.size(), V, G, 0, c->stream);
+                err = launch_sweep<float>(a, (int)c->items.size(), V, G, xu_flag(c, V), c->stream);
             }
+            if (err == hipSuccess)
+                err = launch_moments(mom_args(c, false, 1), c->max_cells, c->n_inst, c->stream);
         }
     }
     if (err == hipSuccess)

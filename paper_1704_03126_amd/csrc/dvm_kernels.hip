@@ -111,8 +111,9 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     // moments gathered: 4 (rho, u1, u2, e) and an extra one (P12 or gradient)
     constexpr int NACC = P12 ? 1 : (GRAD ? 5 : 4);
     // steps per partial flush: the whole chunk unless LDS is short
-    // (FP32 sweeps: half the partial buffer, so two workgroups share a CU)
-    constexpr int FL = (FACES || NACC > 4 || G > 8 || sizeof(T) == 4) ? C / 2 : C;
+    // (FP32 sweeps and 4-wave workgroups: half the partial buffer, so two
+    // workgroups share a CU)
+    constexpr int FL = (FACES || NACC > 4 || G > 8 || G <= 4 || sizeof(T) == 4) ? C / 2 : C;
     constexpr int P = G * V;                   // velocities of the group
     constexpr int UPE = 8 * sizeof(T) / 16;    // 16-byte units per record
     __shared__ __attribute__((aligned(16))) T st_rec[2][C][64][8];
