@@ -55,9 +55,10 @@ def parse():
                         "over a fixed number of iterations")
     p.add_argument("--batch-iters", type=int, default=24,
                    help="iterations per timed batched solve (batch64)")
-    p.add_argument("--schedule", choices=["skew", "wrap"], default="skew",
-                   help="sweep order: skew (lags periodic/strip seams only) or the "
-                        "wrap-around diagonal (fewer steps, not unconditionally stable)")
+    p.add_argument("--schedule", choices=["auto", "skew", "wrap"], default="auto",
+                   help="sweep order: auto (wrap-around diagonal, skewed order for instances "
+                        "that stop contracting), skew (lags periodic/strip seams only) or "
+                        "wrap (fewer steps, not unconditionally stable)")
     p.add_argument("--accel", choices=["auto", "none", "gmres"], default="auto",
                    help="auto: source iteration, GMRES for an instance that stops contracting; "
                         "none: plain source iteration; gmres: GMRES on its fixed-point map")
@@ -101,12 +102,14 @@ def main():
     g = cfg_rough_channel()
     nf = g.n_fluid
     K = NV * NV
-    sched = dvm.DVM_SCHED_WRAP if args.schedule == "wrap" else dvm.DVM_SCHED_SKEW
+    sched = {"auto": dvm.DVM_SCHED_AUTO, "skew": dvm.DVM_SCHED_SKEW, "wrap": dvm.DVM_SCHED_WRAP}[args.schedule]
     accel = {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE, "gmres": dvm.DVM_ACCEL_GMRES}[args.accel]
     prec = dvm.DVM_FP32_REFINE if args.precision == "fp32_refine" else dvm.DVM_FP64
     solver = dvm.Solver(NV, 1, tol=TOL, vel_per_lane=args.vel, waves_per_block=args.waves,
                         schedule=sched, accel=accel, precision=prec)
     solver.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+
+    scheds = {}
 
     def step():
         its, Qs, tts = [], [], []
@@ -117,6 +120,7 @@ def main():
             tts.append(time.perf_counter() - t0)
             its.append(info.iters)
             Qs.append(Q)
+            scheds[str(d)] = info.schedule
         return its, Qs, tts
 
     for _ in range(args.warmup):
@@ -142,10 +146,13 @@ def main():
         prof = dvm.Solver(NV, 1, tol=TOL, profile=True, vel_per_lane=args.vel,
                           waves_per_block=args.waves, schedule=sched)
         prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        prof_sched = set()
         for d in DELTAS:
-            prof.solve(0, d)
+            prof_sched.add(prof.solve(0, d).schedule)
         sweep_ms, n_sweeps, other_ms = prof.profile()
+        (pv, pg), _ = prof.launch_shape()
         prof.close()
+        kernel_sched = prof_sched.pop() if len(prof_sched) == 1 else "mixed" 
         avg_sweep_s = sweep_ms / max(n_sweeps, 1) / 1e3
         flops_per_launch = float(nf) * K * FLOPS_PER_UPDATE
         achieved = flops_per_launch / avg_sweep_s
@@ -156,7 +163,7 @@ def main():
             with open(args.traffic_json) as f:
                 tr = json.load(f)
         else:
-            tr = measured_traffic()
+            tr = measured_traffic(kernel_sched, pv, pg)
         if tr is not None:
             traffic = tr["fetch_bytes"] + tr["write_bytes"]
             traffic_detail = {"fetch_bytes_per_launch": tr["fetch_bytes"],
@@ -167,7 +174,8 @@ def main():
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": traffic,
                     "traffic_detail": traffic_detail,
-                    "kernel": "k_sweep<double>", "avg_launch_ms": avg_sweep_s * 1e3,
+                    "kernel": f"k_sweep<double,{pv},{pg}> ({kernel_sched} order)",
+                    "avg_launch_ms": avg_sweep_s * 1e3,
                     "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": nf * K,
                     "sweep_share_of_iteration": sweep_ms / max(sweep_ms + other_ms, 1e-30)}
 
@@ -193,6 +201,7 @@ def main():
                    "deltas": list(DELTAS), "tol": TOL, "precision": args.precision,
                    "schedule": args.schedule, "accel": args.accel, "parallelism": "single_gpu"},
         "iterations_per_delta": all_its[-1],
+        "schedule_per_delta": scheds,
         "time_to_solution_s": dict(zip([str(d) for d in DELTAS],
                                        np.mean(np.array(all_tts), axis=0).tolist())),
         "Q": dict(zip([str(d) for d in DELTAS], Qs)),
@@ -242,9 +251,10 @@ def bench_batch(args, torch, dvm):
     print(json.dumps(out))
 
 
-def measured_traffic():
+def measured_traffic(schedule, vel, waves):
     """Profiler-measured HBM bytes per sweep launch (profiles/), valid only
-    while the kernel source is the one that was profiled."""
+    while the kernel source, the sweep order and the launch shape are the
+    ones that were profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sweep_traffic.json")
     src = os.path.join(ROOT, "paper_1704_03126_amd", "csrc", "dvm_kernels.hip")
@@ -255,6 +265,8 @@ def measured_traffic():
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if not sha.startswith(tr.get("kernel_source_sha256_prefix", "-")):
+        return None
+    if tr.get("schedule") != schedule or tr.get("shape") != [vel, waves]:
         return None
     return tr
 

@@ -50,8 +50,10 @@ extern "C" {
 #define DVM_FP64 0          /* all sweeps in FP64                             */
 #define DVM_FP32_REFINE 1   /* FP32 sweeps, FP64 moments + defect correction  */
 
-#define DVM_SCHED_SKEW 0    /* sweep order with lags at periodic/strip seams only */
-#define DVM_SCHED_WRAP 1    /* wrap-around diagonal: fewer steps on wide grids  */
+#define DVM_SCHED_AUTO 0    /* wrap-around diagonal, skewed order for instances
+                               whose iteration stops contracting (default)   */
+#define DVM_SCHED_SKEW 1    /* sweep order with lags at periodic/strip seams only */
+#define DVM_SCHED_WRAP 2    /* wrap-around diagonal: fewer steps on wide grids  */
 
 #define DVM_ACCEL_AUTO 0    /* plain source iteration; GMRES takes over an
                                instance whose iteration stops contracting     */
@@ -88,14 +90,22 @@ typedef struct {
                                read the totals with dvm_profile              */
     int schedule;           /* order of the cells within a sweep (the fixed
                                point does not depend on it):
-                               DVM_SCHED_SKEW (default) lags only the values
-                               that cross periodic seams and 64-row strip
-                               boundaries, as the paper's iteration lags its
-                               periodic seam; DVM_SCHED_WRAP (grids with
-                               nx >= 8) also lags the y coupling along one
-                               diagonal per strip, saving 63 steps per pass,
-                               but the iteration can then diverge (seen with
-                               a solid block inside a periodic cell)         */
+                               DVM_SCHED_SKEW lags only the values that cross
+                               periodic seams and 64-row strip boundaries, as
+                               the paper's iteration lags its periodic seam,
+                               at the price of 63 fill steps per pass;
+                               DVM_SCHED_WRAP (grids with nx >= 8) sweeps a
+                               wrap-around diagonal without fill steps but
+                               also lags the y coupling along one diagonal
+                               per strip, and the iteration can then diverge
+                               (seen with a solid block inside a periodic
+                               cell); DVM_SCHED_AUTO (default) starts every
+                               instance on the wrap-around diagonal and moves
+                               an instance whose relative change of u1 has not
+                               dropped by 5% over 64 iterations to the skewed
+                               order for good: the layout is rebuilt and the
+                               solve restarts (other instances of the context
+                               lose their state, as after dvm_set_geometry)  */
     int accel;              /* DVM_ACCEL_AUTO (default), DVM_ACCEL_NONE or
                                DVM_ACCEL_GMRES.  GMRES drives the iteration's
                                state (moments, lagged seam, wrap and wall
@@ -118,6 +128,8 @@ typedef struct {
     double rel_change;      /* last relative change of u1                     */
     double est_error;       /* a-posteriori bound rel_change*r/(1-r)          */
     int status;             /* DVM_STATUS_*                                   */
+    int schedule;           /* sweep order the solve ended in: DVM_SCHED_SKEW
+                               or DVM_SCHED_WRAP                              */
 } dvm_info;
 
 /* Create a context for n_instances independent problems sharing one
@@ -185,6 +197,13 @@ int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha);
  * milliseconds of the other kernels of the iterations (moments, record,
  * stop rule).  Resets the totals.  Any output may be NULL. */
 int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms);
+
+/* Sweep launch shape in use: velocities per lane and waves per workgroup of
+ * the FP64 sweep and of the FP32 sweep (the latter used by
+ * DVM_FP32_REFINE).  With autotuning the shapes are known after the first
+ * dvm_solve; before it all four read 0.  Any output may be NULL. */
+int dvm_launch_shape(const dvm_ctx *ctx, int *vel_per_lane, int *waves_per_block,
+                     int *vel_per_lane32, int *waves_per_block32);
 
 /* Release every resource of the context (NULL is ignored). */
 void dvm_destroy(dvm_ctx *ctx);

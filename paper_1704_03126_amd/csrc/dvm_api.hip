@@ -55,6 +55,7 @@ struct HostInst {
     double delta = 1.0, alpha = 1.0;
     std::vector<double> dfield;
     bool has_state = false;   // a converged/partial solution is on the device
+    bool force_skew = false;  // DVM_SCHED_AUTO: this geometry needs the skewed order
     bool converged = false;   // the last solve met the stop rule
 };
 
@@ -139,6 +140,8 @@ struct dvm_ctx {
     KrylovWork kw;
     std::vector<long long> sweeps_done;   // per instance, last solve
     std::vector<long long> sweeps64_done; // of which FP64 sweeps
+    std::vector<long long> sweeps_wasted;   // before a restart in the skewed order
+    std::vector<long long> sweeps64_wasted; // of which FP64 sweeps
 
     // FP32 correction state of the refinement (allocated by the first
     // DVM_FP32_REFINE solve)
@@ -419,6 +422,9 @@ static int build_layout(dvm_ctx *c)
     c->adj_ready = false;
     c->fp32_ready = false;
     const int V = c->V, G = c->G, P = V * G;
+    const std::vector<InstDev> prev = c->idev;
+    const int prev_kp4 = c->kp4;
+    const long long prev_faces = c->nfaces;
     c->gq = (c->K / 4 + P - 1) / P;
     c->kq = c->gq * P;
     c->kp4 = 4 * c->kq;
@@ -433,7 +439,9 @@ static int build_layout(dvm_ctx *c)
         faces += h.nfaces;
         d.nx = h.nx;
         d.ny = h.ny;
-        d.tp = (c->cfg.schedule == DVM_SCHED_WRAP && h.nx >= WRAP_MIN) ? h.nx : h.nx + 63;
+        const bool on_wrap = c->cfg.schedule == DVM_SCHED_WRAP ||
+                             (c->cfg.schedule == DVM_SCHED_AUTO && !h.force_skew);
+        d.tp = (on_wrap && h.nx >= WRAP_MIN) ? h.nx : h.nx + 63;
         strip_layout(h.ny, d.nstrips, d.strip_h);
         d.periodic_y = h.periodic_y;
         d.cell_off = cell;
@@ -461,6 +469,26 @@ static int build_layout(dvm_ctx *c)
         if ((long long)c->inst[i].nx * 2 * c->kp4 >= (1ll << 31))
             return fail(DVM_EINVAL, "instance " + std::to_string(i) +
                                         ": nx too large for the velocity grid (nx * 2 * padded velocities >= 2^31)");
+    // The solution state (moments, seam, wrap and wall-face buffers, delta
+    // field) survives a new layout that keeps every instance's state where it
+    // was: same velocity padding, same offsets -- only the sweep order of
+    // some instance changed.
+    bool keep = prev.size() == c->idev.size() && prev_kp4 == c->kp4 && prev_faces == faces &&
+                c->d_mom.n == (size_t)cell * MOM_STRIDE && c->d_seam.n == (size_t)2 * seam &&
+                c->d_wrap.n == (size_t)wrap;
+    for (int i = 0; keep && i < c->n_inst; ++i) {
+        const InstDev &a = prev[i], &b = c->idev[i];
+        keep = a.nx == b.nx && a.ny == b.ny && a.cell_off == b.cell_off && a.seam_off == b.seam_off &&
+               a.wrap_off == b.wrap_off && a.nstrips == b.nstrips;
+    }
+    if (keep)
+        for (int i = 0; i < c->n_inst; ++i) {
+            InstDev &d = c->idev[i];
+            d.delta = prev[i].delta;
+            d.alpha = prev[i].alpha;
+            d.drive = prev[i].drive;
+            d.field = prev[i].field;
+        }
     c->ncell = cell;
     c->seam_half = seam;
     c->wrap_total = wrap;
@@ -476,16 +504,18 @@ static int build_layout(dvm_ctx *c)
     HIPCHK(c->d_smap.alloc(sk));
     HIPCHK(c->d_spos.alloc(cell * 4));
     HIPCHK(c->d_vt.alloc((size_t)c->n_inst * c->kp4 * VT_STRIDE));
-    HIPCHK(c->d_dfield.alloc(cell));
     HIPCHK(c->d_part.alloc((size_t)4 * c->gq * cell * 4));
-    HIPCHK(c->d_mom.alloc(cell * MOM_STRIDE));
-    HIPCHK(c->d_u1prev.alloc(cell));
-    HIPCHK(c->d_seam.alloc(2 * seam));
-    HIPCHK(c->d_wrap.alloc(wrap));
+    if (!keep) {
+        HIPCHK(c->d_dfield.alloc(cell));
+        HIPCHK(c->d_mom.alloc(cell * MOM_STRIDE));
+        HIPCHK(c->d_u1prev.alloc(cell));
+        HIPCHK(c->d_seam.alloc(2 * seam));
+        HIPCHK(c->d_wrap.alloc(wrap));
+        HIPCHK(c->d_st.alloc(c->n_inst));
+        HIPCHK(c->d_fb.alloc((size_t)2 * std::max<long long>(faces, 1) * c->kp4));
+    }
     HIPCHK(c->d_aux.alloc(cell));
-    HIPCHK(c->d_st.alloc(c->n_inst));
     HIPCHK(c->d_sface.alloc(sk));
-    HIPCHK(c->d_fb.alloc((size_t)2 * std::max<long long>(faces, 1) * c->kp4));
     HIPCHK(c->d_part5.alloc((size_t)4 * c->gq * cell));
 
     std::vector<uint8_t> codes(cell);
@@ -607,19 +637,22 @@ static int build_layout(dvm_ctx *c)
     HIPCHK(hipMemcpyAsync(c->d_spos.p, spos.data(), spos.size() * sizeof(long long), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipMemcpyAsync(c->d_sface.p, sface.data(), sk * sizeof(FaceRec), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(launch_zero(c->d_fb.p, c->d_fb.n, c->stream));
+    if (!keep)
+        HIPCHK(launch_zero(c->d_fb.p, c->d_fb.n, c->stream));
     HIPCHK(launch_zero(c->d_srec.p, c->d_srec.n, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_vt.p, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_items.p, c->items.data(), c->items.size() * sizeof(WorkItem),
                           hipMemcpyHostToDevice, c->stream));
-    HIPCHK(launch_zero(c->d_mom.p, c->d_mom.n, c->stream));
-    HIPCHK(launch_zero(c->d_u1prev.p, c->d_u1prev.n, c->stream));
-    HIPCHK(launch_zero(c->d_seam.p, c->d_seam.n, c->stream));
-    HIPCHK(launch_zero(c->d_wrap.p, c->d_wrap.n, c->stream));
-    HIPCHK(launch_zero(c->d_dfield.p, c->d_dfield.n, c->stream));
+    if (!keep) {
+        HIPCHK(launch_zero(c->d_mom.p, c->d_mom.n, c->stream));
+        HIPCHK(launch_zero(c->d_u1prev.p, c->d_u1prev.n, c->stream));
+        HIPCHK(launch_zero(c->d_seam.p, c->d_seam.n, c->stream));
+        HIPCHK(launch_zero(c->d_wrap.p, c->d_wrap.n, c->stream));
+        HIPCHK(launch_zero(c->d_dfield.p, c->d_dfield.n, c->stream));
+        for (auto &h : c->inst)
+            h.has_state = false;
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
-    for (auto &h : c->inst)
-        h.has_state = false;
     c->layout_ok = true;
     return DVM_OK;
 }
@@ -892,15 +925,25 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
 // With stall detection (DVM_ACCEL_AUTO) an instance whose relative change of
 // u1 has not dropped by 5% over the last 64 iterations is stopped and flagged
 // in stalled[] (its state is that of a completed iteration).
+// Stall test (when `stalled` is given): an instance whose relative change
+// has not dropped by 5% over the last 64 iterations stops, with stalled = 1;
+// = 2 if max |u1| also grew by more than 10% over that window, i.e. the
+// iterates run away instead of creeping towards the fixed point.  Instances
+// with grow_only set stop only in the second case.
 static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, int kind,
-                      std::vector<SolveState> &st, std::vector<char> *stalled = nullptr)
+                      std::vector<SolveState> &st, std::vector<char> *stalled = nullptr,
+                      const std::vector<char> *grow_only = nullptr)
 {
     const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
     const long long cap = c->cfg.max_iter;
     const long long W = 64;
     const double tol = kind == 2 ? refine_inner_tol(c) : c->cfg.tol;
     SolveState *dst = kind == 1 ? c->d_st_adj.p : kind == 2 ? c->d_st32.p : c->d_st.p;
-    std::vector<std::vector<std::pair<long long, double>>> hist(c->n_inst);
+    struct Hist {
+        long long it;
+        double eps, amax;
+    };
+    std::vector<std::vector<Hist>> hist(c->n_inst);
     for (;;) {
         int rc = enqueue_block(c, B, kind);
         if (rc)
@@ -920,16 +963,19 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
             if (stalled) {
                 auto &hv = hist[i];
                 const long long it = st[i].iter - iter0[i];
-                hv.emplace_back(it, st[i].eps);
-                double old = -1.0;
+                hv.push_back(Hist{it, st[i].eps, st[i].amax});
+                const Hist *old = nullptr;
                 for (const auto &e : hv)
-                    if (e.first <= it - W)
-                        old = e.second;
-                if (old > 0.0 && st[i].eps > tol && !(st[i].eps < 0.95 * old)) {
-                    st[i].active = 0;
-                    (*stalled)[i] = 1;
-                    stop = true;
-                    continue;
+                    if (e.it <= it - W)
+                        old = &e;
+                if (old && old->eps > 0.0 && st[i].eps > tol && !(st[i].eps < 0.95 * old->eps)) {
+                    const bool grows = st[i].amax > 1.1 * old->amax;
+                    if (grows || !(grow_only && (*grow_only)[i])) {
+                        st[i].active = 0;
+                        (*stalled)[i] = grows ? 2 : 1;
+                        stop = true;
+                        continue;
+                    }
                 }
             }
             running = true;
@@ -948,14 +994,26 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
 // taking over stalled instances.  Leaves per-instance sweep counts in
 // c->sweeps_done.
 static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, bool adj,
-                   std::vector<SolveState> &st)
+                   std::vector<SolveState> &st, std::vector<char> *need_skew = nullptr)
 {
     if (c->cfg.accel == DVM_ACCEL_GMRES) {
         std::vector<long long> prior;
         return gmres_run(c, i0, i1, adj, st, prior);
     }
+    // stall detection: for GMRES takeover (accel AUTO), and for instances on
+    // the wrap-around diagonal under DVM_SCHED_AUTO, which move to the skewed
+    // order when their iterates run away
+    auto on_wrap = [&](int i) {
+        return need_skew && c->cfg.schedule == DVM_SCHED_AUTO && !c->inst[i].force_skew &&
+               c->inst[i].nx >= WRAP_MIN;
+    };
+    const bool gm = c->cfg.accel == DVM_ACCEL_AUTO;
+    bool detect = gm;
+    std::vector<char> grow_only(c->n_inst, gm ? 0 : 1);
+    for (int i = i0; i < i1; ++i)
+        detect = detect || on_wrap(i);
     std::vector<char> stalled(c->n_inst, 0);
-    int rc = run_blocks(c, i0, i1, iter0, adj ? 1 : 0, st, c->cfg.accel == DVM_ACCEL_AUTO ? &stalled : nullptr);
+    int rc = run_blocks(c, i0, i1, iter0, adj ? 1 : 0, st, detect ? &stalled : nullptr, &grow_only);
     if (rc)
         return rc;
     std::vector<long long> prior(c->n_inst, 0);
@@ -963,10 +1021,16 @@ static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &ite
     for (int i = i0; i < i1; ++i) {
         prior[i] = st[i].iter - iter0[i];
         c->sweeps_done[i] = prior[i];
-        if (stalled[i]) {
-            st[i].active = 1;
-            st[i].status = STATUS_RUNNING;
-            any = true;
+        if (on_wrap(i) && (stalled[i] == 2 || st[i].status == STATUS_DIVERGED)) {
+            (*need_skew)[i] = 1;
+        } else if (stalled[i]) {
+            if (gm) {
+                st[i].active = 1;
+                st[i].status = STATUS_RUNNING;
+                any = true;
+            } else {
+                st[i].status = STATUS_DIVERGED;  // runs away: the plain iteration cannot converge
+            }
         }
     }
     if (!any)
@@ -1416,7 +1480,7 @@ static bool debug_on()
     return on == 1;
 }
 
-static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st)
+static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::vector<char> *need_skew)
 {
     int rc = ensure_fp32(c);
     if (rc)
@@ -1695,7 +1759,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st)
     std::vector<long long> before(c->n_inst);
     for (const auto &d : slots)
         before[d.inst] = c->sweeps_done[d.inst];
-    rc = iterate(c, i0, i1, iter0, false, st);
+    rc = iterate(c, i0, i1, iter0, false, st, need_skew);
     for (const auto &d : slots)
         if (d.fallback) {
             c->sweeps64_done[d.inst] += c->sweeps_done[d.inst];
@@ -1724,7 +1788,8 @@ static std::string tune_key(const dvm_ctx *c)
     std::string k = "nv" + std::to_string(c->nv) + " p" + std::to_string(c->cfg.precision) + " s" +
                     std::to_string(c->cfg.schedule);
     for (const auto &h : c->inst)
-        k += " " + std::to_string(h.nx) + "x" + std::to_string(h.ny) + (h.periodic_y ? "p" : "w");
+        k += " " + std::to_string(h.nx) + "x" + std::to_string(h.ny) + (h.periodic_y ? "p" : "w") +
+             (h.force_skew ? "s" : "");
     return k;
 }
 
@@ -1894,7 +1959,7 @@ static int check_instance(const dvm_ctx *c, int instance)
 }
 
 static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_field,
-                    double alpha, dvm_info *info, bool warm)
+                    double alpha, dvm_info *info, bool warm, int depth = 0)
 {
     if (!c)
         return fail(DVM_EINVAL, "context is NULL");
@@ -2023,22 +2088,50 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
     for (int i = i0; i < i1; ++i)
         c->inst[i].has_state = true;
 
+    if (depth == 0) {
+        std::fill(c->sweeps_wasted.begin(), c->sweeps_wasted.end(), 0);
+        std::fill(c->sweeps64_wasted.begin(), c->sweeps64_wasted.end(), 0);
+    }
     {
-        int rc = c->cfg.precision == DVM_FP32_REFINE ? dc_run(c, i0, i1, st)
-                                                     : iterate(c, i0, i1, iter0, false, st);
+        std::vector<char> need_skew(c->n_inst, 0);
+        int rc = c->cfg.precision == DVM_FP32_REFINE ? dc_run(c, i0, i1, st, &need_skew)
+                                                     : iterate(c, i0, i1, iter0, false, st, &need_skew);
         if (rc)
             return rc;
+        bool restart = false;
+        for (int i = i0; i < i1; ++i)
+            if (need_skew[i]) {
+                // the wrap-around diagonal stopped contracting on this geometry:
+                // skewed order from now on, and the solve starts over
+                c->inst[i].force_skew = true;
+                restart = true;
+            }
+        if (restart && depth == 0) {
+            // the new layout keeps the other instances' states: they restart
+            // warm from what this pass reached, the moved ones from zero
+            for (int i = i0; i < i1; ++i) {
+                c->sweeps_wasted[i] += c->sweeps_done[i];
+                c->sweeps64_wasted[i] += c->cfg.precision == DVM_FP32_REFINE ? c->sweeps64_done[i]
+                                                                             : c->sweeps_done[i];
+                if (need_skew[i])
+                    c->inst[i].has_state = false;
+            }
+            c->layout_ok = false;
+            return do_solve(c, instance, delta, delta_is_field, alpha, info, true, depth + 1);
+        }
     }
     int rc = DVM_OK;
     for (int i = i0; i < i1; ++i) {
         const SolveState &s = st[i];
         if (info) {
             dvm_info &o = info[instance < 0 ? i : 0];
-            o.iters = c->sweeps_done[i];
-            o.sweeps_fp64 = c->cfg.precision == DVM_FP32_REFINE ? c->sweeps64_done[i] : o.iters;
+            o.iters = c->sweeps_done[i] + c->sweeps_wasted[i];
+            o.sweeps_fp64 = c->sweeps64_wasted[i] +
+                            (c->cfg.precision == DVM_FP32_REFINE ? c->sweeps64_done[i] : c->sweeps_done[i]);
             o.rel_change = s.eps;
             o.est_error = s.est;
             o.status = s.status;
+            o.schedule = c->idev[i].tp == c->idev[i].nx && c->idev[i].nx > 1 ? DVM_SCHED_WRAP : DVM_SCHED_SKEW;
         }
         c->inst[i].converged = s.status == STATUS_CONVERGED;
         if (s.status == STATUS_DIVERGED)
@@ -2248,7 +2341,7 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
         return fail(DVM_EINVAL, "max_iter must be > 0");
     if (c.block_iters < 0 || c.block_iters > 4096)
         return fail(DVM_EINVAL, "block_iters must be in [0, 4096]");
-    if (c.schedule != DVM_SCHED_SKEW && c.schedule != DVM_SCHED_WRAP)
+    if (c.schedule != DVM_SCHED_AUTO && c.schedule != DVM_SCHED_SKEW && c.schedule != DVM_SCHED_WRAP)
         return fail(DVM_EINVAL, "unknown schedule");
     if (c.accel != DVM_ACCEL_AUTO && c.accel != DVM_ACCEL_NONE && c.accel != DVM_ACCEL_GMRES)
         return fail(DVM_EINVAL, "unknown acceleration");
@@ -2277,6 +2370,8 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->inst.assign(n_instances, HostInst{});
     ctx->sweeps_done.assign(n_instances, 0);
     ctx->sweeps64_done.assign(n_instances, 0);
+    ctx->sweeps_wasted.assign(n_instances, 0);
+    ctx->sweeps64_wasted.assign(n_instances, 0);
     ctx->stream = (hipStream_t)hip_stream;   // NULL: a stream is made on first use
     build_quadrature(ctx);
     *out = ctx;
@@ -2443,6 +2538,23 @@ int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms
         *other_ms = ctx->prof_other_ms;
     ctx->prof_sweep_ms = ctx->prof_other_ms = 0.0;
     ctx->prof_sweeps = 0;
+    return DVM_OK;
+}
+
+int dvm_launch_shape(const dvm_ctx *ctx, int *vel_per_lane, int *waves_per_block, int *vel_per_lane32,
+                     int *waves_per_block32)
+{
+    if (!ctx)
+        return fail(DVM_EINVAL, "context is NULL");
+    const bool known = !ctx->autotune || ctx->tuned;
+    if (vel_per_lane)
+        *vel_per_lane = known ? ctx->V : 0;
+    if (waves_per_block)
+        *waves_per_block = known ? ctx->G : 0;
+    if (vel_per_lane32)
+        *vel_per_lane32 = known ? ctx->V32 : 0;
+    if (waves_per_block32)
+        *waves_per_block32 = known ? ctx->G32 : 0;
     return DVM_OK;
 }
 

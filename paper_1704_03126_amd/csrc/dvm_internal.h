@@ -96,7 +96,7 @@ struct SolveState {
     double eps, eps_prev, est;
     unsigned long long maxdiff_bits, maxabs_bits;
     double tol;           // stop tolerance of this instance (0: the launch's)
-    double pad1;
+    double amax;          // max |u1| of the last iteration
 };
 
 // face record of a sweep entry (alpha < 1 and the gradient): faces whose

@@ -796,6 +796,7 @@ __global__ void k_status(SolveState *st, int n, double tol, long long max_iter)
     s.maxdiff_bits = 0ull;
     s.maxabs_bits = 0ull;
     s.iter += 1;
+    s.amax = amax;
     double eps = amax > 0.0 ? dmax / amax : (dmax == 0.0 ? 0.0 : __builtin_inf());
     // iterates of this linear problem are O(delta) at most; values beyond
     // 1e30 (or non-finite) mean the lagged iteration is amplifying errors

@@ -25,16 +25,18 @@ DVM_ENOCONV = -5
 DVM_EDIVERGED = -6
 DVM_FP64 = 0
 DVM_FP32_REFINE = 1
-DVM_SCHED_SKEW = 0
-DVM_SCHED_WRAP = 1
+DVM_SCHED_AUTO = 0
+DVM_SCHED_SKEW = 1
+DVM_SCHED_WRAP = 2
 DVM_ACCEL_AUTO = 0
 DVM_ACCEL_NONE = 1
 DVM_ACCEL_GMRES = 2
 STATUS_NAMES = {0: "running", 1: "converged", 2: "max_iter", 3: "diverged"}
+SCHED_NAMES = {DVM_SCHED_SKEW: "skew", DVM_SCHED_WRAP: "wrap"}
 
 EXPORTED = ("dvm_create", "dvm_set_geometry", "dvm_solve", "dvm_solve_warm",
             "dvm_flow_rate", "dvm_get_moments", "dvm_grad", "dvm_destroy",
-            "dvm_last_error", "dvm_version", "dvm_profile")
+            "dvm_last_error", "dvm_version", "dvm_profile", "dvm_launch_shape")
 
 
 class DVMError(RuntimeError):
@@ -55,7 +57,7 @@ class dvm_config(ctypes.Structure):
 class dvm_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_long), ("sweeps_fp64", ctypes.c_long),
                 ("rel_change", ctypes.c_double), ("est_error", ctypes.c_double),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int), ("schedule", ctypes.c_int)]
 
 
 _lib = None
@@ -83,6 +85,8 @@ def load_library(path: str = LIB_PATH):
     lib.dvm_grad.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double)]
     lib.dvm_profile.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long),
                                 ctypes.POINTER(ctypes.c_double)]
+    IP = ctypes.POINTER(ctypes.c_int)
+    lib.dvm_launch_shape.argtypes = [P, IP, IP, IP, IP]
     lib.dvm_destroy.argtypes = [P]
     lib.dvm_destroy.restype = None
     lib.dvm_last_error.restype = ctypes.c_char_p
@@ -119,6 +123,7 @@ class SolveInfo:
     rel_change: float
     est_error: float
     status: str
+    schedule: str = ""
 
 
 class Solver:
@@ -127,7 +132,7 @@ class Solver:
     def __init__(self, nv: int, n_instances: int = 1, *, precision: int = DVM_FP64,
                  tol: float = 1e-8, max_iter: int = 200000, block_iters: int = 32,
                  use_graphs: bool = True, vel_per_lane: int = 0,
-                 waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_SKEW,
+                 waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_AUTO,
                  accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, tune_cache: str | None = None,
                  stream=None):
         lib = load_library()
@@ -186,7 +191,8 @@ class Solver:
         if rc != DVM_OK and not (rc == DVM_ENOCONV and not raise_on_noconv):
             _check(rc)
         out = [SolveInfo(i.iters, i.sweeps_fp64, i.rel_change, i.est_error,
-                         STATUS_NAMES.get(i.status, str(i.status))) for i in infos]
+                         STATUS_NAMES.get(i.status, str(i.status)),
+                         SCHED_NAMES.get(i.schedule, str(i.schedule))) for i in infos]
         return out if instance < 0 else out[0]
 
     def flow_rate(self, instance: int = 0):
@@ -210,6 +216,13 @@ class Solver:
         sm, n, om = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
         _check(self._lib.dvm_profile(self._h, ctypes.byref(sm), ctypes.byref(n), ctypes.byref(om)))
         return sm.value, n.value, om.value
+
+    def launch_shape(self):
+        """((V, G) of the FP64 sweep, (V, G) of the FP32 sweep); zeros while
+        an autotuned context has not solved yet."""
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(self._lib.dvm_launch_shape(self._h, *[ctypes.byref(x) for x in v]))
+        return (v[0].value, v[1].value), (v[2].value, v[3].value)
 
     def grad(self, instance: int = 0):
         ny, nx = self.shapes[instance]

@@ -52,7 +52,7 @@ def test_create_validates_arguments(lib):
     assert _ctx(lib, precision=7)[0] == dvm.DVM_EINVAL
     assert _ctx(lib, tol=-1.0)[0] == dvm.DVM_EINVAL
     assert _ctx(lib, vel=3)[0] == dvm.DVM_EINVAL
-    assert _ctx(lib, schedule=2)[0] == dvm.DVM_EINVAL
+    assert _ctx(lib, schedule=3)[0] == dvm.DVM_EINVAL
     assert b"nv" in lib.dvm_last_error() or b"vel" in lib.dvm_last_error() or lib.dvm_last_error()
     rc, h = _ctx(lib)
     assert rc == dvm.DVM_OK

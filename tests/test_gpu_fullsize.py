@@ -1,0 +1,63 @@
+"""Full-size parity: the GPU solver in the benchmark's launch configuration
+(default shape selection, sweep order and acceleration) against stored FP64
+oracle results (tests/golden/, written by make_golden.py from the oracle
+only).  Bar: flow rate within 1e-8 relative (the target is 1e-6) and u1, u2
+at 16 seeded cells within 1e-8 (target 1e-5 max-abs)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1704_03126_amd.geometry import cfg_plane_channel, cfg_porous, cfg_rough_channel
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+MAKERS = {"plane_channel_64_nv32": cfg_plane_channel,
+          "rough_channel_256x128_nv64": cfg_rough_channel,
+          "porous_512_nv64": cfg_porous}
+
+
+@pytest.fixture(scope="module")
+def dvm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1704_03126_amd.dvm as d
+    d.load_library()
+    return d
+
+
+def _load(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle result {name}.json not generated (tests/golden/make_golden.py {name})")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,precision", [
+    ("plane_channel_64_nv32", "fp64"),
+    ("rough_channel_256x128_nv64", "fp64"),
+    ("rough_channel_256x128_nv64", "fp32_refine"),
+    ("porous_512_nv64", "fp64")])
+def test_full_size_against_oracle(dvm, name, precision):
+    ref = _load(name)
+    g = MAKERS[name]()
+    assert (g.nx, g.ny) == (ref["nx"], ref["ny"])
+    prec = dvm.DVM_FP32_REFINE if precision == "fp32_refine" else dvm.DVM_FP64
+    s = dvm.Solver(ref["nv"], 1, tol=1e-11, precision=prec)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    cells = np.array(ref["cells"])
+    for r in ref["results"]:
+        info = s.solve(0, r["delta"])
+        assert info.status == "converged", (r["delta"], info)
+        Q, _ = s.flow_rate(0)
+        mom = s.moments(0)
+        assert abs(Q - r["Q"]) <= 1e-8 * abs(r["Q"]), (r["delta"], Q, r["Q"])
+        u1 = mom["u1"][cells[:, 0], cells[:, 1]]
+        u2 = mom["u2"][cells[:, 0], cells[:, 1]]
+        assert np.max(np.abs(u1 - np.array(r["u1"]))) <= 1e-8, r["delta"]
+        assert np.max(np.abs(u2 - np.array(r["u2"]))) <= 1e-8, r["delta"]
+    s.close()

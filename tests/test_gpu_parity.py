@@ -218,14 +218,50 @@ def test_wrap_schedule_same_fixed_point(dvm, case):
 def test_block_in_periodic_cell_default_schedule(dvm):
     """A solid block inside a periodic cell: the default schedule converges
     to the oracle's solution (the wrap-around diagonal diverges here)."""
-    m = np.zeros((16, 16), np.uint8)
-    m[6:10, 4:10] = 1
-    from paper_1704_03126_amd.geometry import Geometry
-    g = Geometry(mask=m, periodic_y=True, cells_per_H=16.0)
+    g = _block_cell()
     ref = oracle_solve(g, 0.7, 8)
     Q, _, mom, info = gpu_solve(dvm, g, 0.7, 8)
     assert info.status == "converged"
     assert_parity(Q, mom, ref, qtol=1e-8, utol=1e-8)
+
+
+def _block_cell():
+    from paper_1704_03126_amd.geometry import Geometry
+    m = np.zeros((16, 16), np.uint8)
+    m[6:10, 4:10] = 1
+    return Geometry(mask=m, periodic_y=True, cells_per_H=16.0)
+
+
+def test_auto_schedule_moves_runaway_instance_to_skew(dvm):
+    """Default schedule without Krylov acceleration: the block-in-periodic
+    cell runs away on the wrap-around diagonal, is moved to the skewed order
+    and converges to the oracle's solution.  A second instance solved earlier
+    keeps its solution through the new layout, and a well-behaved instance in
+    a batch with it stays on the wrap-around diagonal and converges too."""
+    gb, gr = _block_cell(), rough_channel(32, 16, 3, 16)
+    refb = oracle_solve(gb, 0.7, 8)
+    refr = oracle_solve(gr, 1.0, 8)
+    s = dvm.Solver(8, 2, tol=1e-11, accel=dvm.DVM_ACCEL_NONE)
+    s.set_geometry(0, gb.mask, gb.periodic_y, gb.cells_per_H)
+    s.set_geometry(1, gr.mask, gr.periodic_y, gr.cells_per_H)
+    info_r = s.solve(1, 1.0)
+    Qr = s.flow_rate(1)[0]
+    mr = s.moments(1)
+    info_b = s.solve(0, 0.7)
+    assert info_r.status == "converged" and info_b.status == "converged"
+    assert info_r.schedule == "wrap" and info_b.schedule == "skew"
+    assert_parity(s.flow_rate(0)[0], s.moments(0), refb, qtol=1e-8, utol=1e-8)
+    # instance 1 untouched by the relayout: bit-identical moments
+    assert s.flow_rate(1)[0] == Qr
+    assert np.array_equal(s.moments(1)["u1"], mr["u1"])
+    assert_parity(Qr, mr, refr, qtol=1e-8, utol=1e-8)
+    # both at once, cold
+    infos = s.solve(-1, [0.7, 1.0])
+    assert all(i.status == "converged" for i in infos), infos
+    assert [i.schedule for i in infos] == ["skew", "wrap"]
+    assert_parity(s.flow_rate(0)[0], s.moments(0), refb, qtol=1e-8, utol=1e-8)
+    assert_parity(s.flow_rate(1)[0], s.moments(1), refr, qtol=1e-8, utol=1e-8)
+    s.close()
 
 
 def test_autotuner_cache(dvm, tmp_path):
