@@ -149,8 +149,21 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg,
 int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny,
                      const uint8_t *solid, int periodic_y, double cells_per_H);
 
-/* Solve the steady problem with a unit pressure gradient along +x (the drive
- * of the Poiseuille problem of Sec. III).
+/* What drives the flow of instance `instance` in its next solves: the
+ * source pressure_gradient * xi of every fluid cell (a pressure gradient
+ * along +x; 1 is the Poiseuille problem of Sec. III) and the x velocities of
+ * the outer bottom and top walls of a walled channel, whose diffuse emission
+ * becomes rho_w + 2 U xi (Eq. (diffuse1), U in units of v_m; the Couette
+ * problem of Sec. II is pressure_gradient = 0, top velocity 1).  The
+ * staircase itself is at rest.  Defaults: 1, 0, 0.  Kept across
+ * dvm_set_geometry; a solve of a periodic cell (periodic_y = 1) with a
+ * nonzero wall velocity fails with DVM_EINVAL.  DVM_EINVAL for non-finite
+ * values. */
+int dvm_set_driving(dvm_ctx *ctx, int instance, double pressure_gradient,
+                    double wall_velocity_bottom, double wall_velocity_top);
+
+/* Solve the steady problem driven as set by dvm_set_driving (by default a
+ * unit pressure gradient along +x, the Poiseuille problem of Sec. III).
  *   instance >= 0: solve that instance; delta points to 1 value
  *     (delta_is_field = 0) or to ny*nx values (delta_is_field = 1, ignored in
  *     solids).
@@ -191,6 +204,24 @@ int dvm_get_moments(const dvm_ctx *ctx, int instance, double *rho, double *u1,
  * to the accommodation coefficient, at the converged state of the last
  * dvm_solve of this instance.  Either output may be NULL. */
 int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha);
+
+/* Permeability of a porous medium from a rarefaction sweep of one geometry
+ * (Sec. III): n >= 3 solves at distinct delta[i] > 0 with flow rates Q[i]
+ * (dvm_flow_rate), porosity phi in (0, 1] (fluid fraction of the cell).
+ * With Kn = sqrt(pi)/(2 delta) and k_a = sqrt(4/pi) Q Kn = Q/delta:
+ *   k_inf   -- the intrinsic permeability, the limit of k_a as Kn -> 0,
+ *              taken as the value at Kn = 0 of the quadratic in Kn through
+ *              the three samples of smallest Kn;
+ *   H_star  -- the characteristic length H* = H sqrt(12 k_inf / phi), in
+ *              units of H;
+ *   Kn_star -- Kn* = Kn H / H* for every sample (n values);
+ *   ka_ratio -- k_a / k_inf for every sample (n values).
+ * Host-only arithmetic; any output may be NULL.  DVM_EINVAL if n < 3, a
+ * delta is not finite and > 0, two deltas coincide, phi is outside (0, 1],
+ * or the extrapolated k_inf is not positive. */
+int dvm_permeability(int n, const double *delta, const double *Q, double phi,
+                     double *k_inf, double *H_star, double *Kn_star,
+                     double *ka_ratio);
 
 /* Kernel timings gathered while cfg.profile == 1, since the previous call:
  * total milliseconds spent in sweep launches and their count, and total

@@ -48,9 +48,10 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_quadrature.argtypes = [ctypes.c_int, P, P, P, P, P, P]
         lib.oracle_codes.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
+        D = ctypes.c_double
         lib.oracle_si_solve.argtypes = [
-            ctypes.c_int, ctypes.c_int, P, ctypes.c_int, ctypes.c_double,
-            ctypes.c_int, P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+            ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D,
+            ctypes.c_int, P, ctypes.c_int, D, D, D, D, D,
             ctypes.c_long, P, P, P, P, P, P, P, P]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -121,11 +122,14 @@ class SIResult:
 
 def si_solve(mask: np.ndarray, delta, nv: int, *, periodic_y: bool = False,
              cells_per_H: float | None = None, alpha: float = 1.0,
+             drive: float = 1.0, wall_velocity=(0.0, 0.0),
              tol: float = 1e-12, max_iter: int = 100000,
              return_h: bool = False) -> SIResult:
     """Run the paper's source iteration to the stop rule (FP64, CPU).
 
     ``delta`` is a scalar or a (ny, nx) field; ``cells_per_H`` defaults to ny.
+    ``drive`` scales the pressure-gradient source (1: Poiseuille, 0: Couette);
+    ``wall_velocity`` = (bottom, top) x velocities of the outer walls.
     ``tol < 0`` runs exactly ``max_iter`` iterations.
     """
     lib = _load()
@@ -141,7 +145,9 @@ def si_solve(mask: np.ndarray, delta, nv: int, *, periodic_y: bool = False,
     hist = np.zeros(max_iter)
     h = np.zeros((nv * nv, ny, nx)) if return_h else None
     rc = lib.oracle_si_solve(nx, ny, _ptr(m), int(periodic_y), float(cells_per_H), nv,
-                             _ptr(d), field, float(alpha), float(tol), int(max_iter),
+                             _ptr(d), field, float(alpha), float(drive),
+                             float(wall_velocity[0]), float(wall_velocity[1]),
+                             float(tol), int(max_iter),
                              _ptr(rho), _ptr(u1), _ptr(u2), _ptr(tau), _ptr(p12),
                              _ptr(info), _ptr(hist), _ptr(h))
     if rc < 0:

@@ -71,7 +71,7 @@ class System:
     A: sp.csr_matrix        # steady operator on [h; g] (cells then wall faces)
     dA_dalpha: sp.csr_matrix
     T: sp.csr_matrix        # transport rows only (h rows), incl. face coupling
-    s: np.ndarray           # drive (zero on face rows)
+    s: np.ndarray           # drive on cell rows; moving-wall source on face rows
     fluid: np.ndarray       # (nf, 2) cell coordinates (y, x)
     cell_index: np.ndarray  # (ny, nx) -> fluid index or -1
     faces: list             # [(f, side)] wall faces; side 0 W, 1 E, 2 S, 3 N
@@ -82,6 +82,7 @@ class System:
     dx: float
     P: np.ndarray
     nh: int                 # number of cell unknowns nf * K
+    ds_dalpha: np.ndarray = None   # d s / d alpha (moving walls)
 
 
 _STEP = {0: (0, -1), 1: (0, 1), 2: (-1, 0), 3: (1, 0)}   # side -> (dy, dx)
@@ -98,7 +99,7 @@ def _solid(mask, periodic_y, y, x):
 
 
 def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
-             alpha=1.0, drive=(1.0, 0.0)) -> System:
+             alpha=1.0, drive=(1.0, 0.0), wall_velocity=(0.0, 0.0)) -> System:
     """Assemble the steady problem with explicit wall-face unknowns.
 
     Unknowns: h[f*K + k] for every fluid cell f and velocity k, then
@@ -116,7 +117,13 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
     Walls (Eq. (diffuse2) and Maxwell's specular share as a reading):
     g = alpha * rho_w + (1 - alpha) * h_inc(mirror k), with
     rho_w = sum_inc W |v_n| h_inc / D and h_inc the reconstructed incident
-    face value.
+    face value.  The outer bottom and top walls of a channel may slide
+    along x at wall_velocity = (U_bottom, U_top); their diffuse part is then
+    that of Eq. (diffuse1), rho_w + 2 U xi, a source term of the face rows.
+
+    drive = (a, b) is the source a xi + b eta of every cell (pressure
+    gradients along x and y; (1, 0) is the Poiseuille problem of Sec. III,
+    (0, 0) with U_top = 1 the Couette problem of Sec. II).
     """
     mask = np.asarray(mask, dtype=np.uint8)
     ny, nx = mask.shape
@@ -245,8 +252,21 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
     T = sp.csr_matrix((tvals, (trows, tcols)), shape=(N, N))
     s = np.zeros(N)
     s[:nh] = np.tile(drive[0] * xi + drive[1] * eta, nf)
+    ds = np.zeros(N)                    # d s / d alpha
+    if not periodic_y:
+        for phi, (f, side) in enumerate(faces):
+            y = fluid[f][0]
+            U = wall_velocity[0] if (side == 2 and y == 0) else \
+                wall_velocity[1] if (side == 3 and y == ny - 1) else 0.0
+            if U == 0.0:
+                continue
+            for k in range(K):
+                if leaves(side, k):
+                    ds[gid(f, side, k)] = 2.0 * U * xi[k]
+    s += alpha * ds
     return System(A=A, dA_dalpha=dA, T=T, s=s, fluid=fluid, cell_index=cell_index,
-                  faces=faces, delta_f=delta_f, Q=Q, nx=nx, ny=ny, dx=dx, P=P, nh=nh)
+                  faces=faces, delta_f=delta_f, Q=Q, nx=nx, ny=ny, dx=dx, P=P, nh=nh,
+                  ds_dalpha=ds)
 
 
 def _bordered_solve(M, rhs, g):
@@ -305,7 +325,8 @@ class AdjointResult:
 
 def adjoint(mask, delta, nv, **kw) -> AdjointResult:
     """Discrete adjoint of the flow rate: A^T lam = dQ/dh, then
-    dQ/dtheta = -lam^T (dA/dtheta) h for theta = delta_c and alpha."""
+    dQ/dtheta = -lam^T (dA/dtheta h - ds/dtheta) for theta = delta_c and
+    alpha (the source depends on alpha only through a moving wall)."""
     fwd = solve(mask, delta, nv, **kw)
     sys = fwd.sys
     K = sys.Q["K"]
@@ -324,5 +345,5 @@ def adjoint(mask, delta, nv, **kw) -> AdjointResult:
     dQ_ddelta = np.zeros((sys.ny, sys.nx))
     for f, (y, x) in enumerate(sys.fluid):
         dQ_ddelta[y, x] = dd[f]
-    dQ_dalpha = float(-lv @ (sys.dA_dalpha @ fwd.x))
+    dQ_dalpha = float(-lv @ (sys.dA_dalpha @ fwd.x - sys.ds_dalpha))
     return AdjointResult(lam=lam, dQ_ddelta=dQ_ddelta, dQ_dalpha=dQ_dalpha, Q=fwd.Q)

@@ -141,6 +141,8 @@ static inline int wrap(int a, int n) { return ((a % n) + n) % n; }
 typedef struct {
     int nx, ny, nv, K, nc, periodic_y;
     double dx, alpha;
+    double drive;                          /* pressure-gradient source factor */
+    double u_wall[2];                      /* x velocity of the outer bottom / top wall */
     const double *xi, *eta, *W;
     const uint8_t *solid, *codes;
     const double *dl;                      /* delta per cell */
@@ -158,13 +160,31 @@ static inline int mirror(int k, int d, int nv)
     return d < 2 ? (nv - 1 - i) * nv + j : i * nv + (nv - 1 - j);
 }
 
+/* x velocity of the wall behind side d of cell c: the outer bottom and top
+ * walls of a channel may slide along x (the moving plate of Sec. II); the
+ * solid staircase is at rest. */
+static inline double wall_speed(const si_ctx *s, int c, int d)
+{
+    if (s->periodic_y)
+        return 0.0;
+    int y = c / s->nx;
+    if (d == DIR_S && y == 0)
+        return s->u_wall[0];
+    if (d == DIR_N && y == s->ny - 1)
+        return s->u_wall[1];
+    return 0.0;
+}
+
 /* Value of h on the wall face on side d of cell c for a velocity k leaving
- * that face: Eq. (diffuse2) (full accommodation) plus, as a reading for
+ * that face: Eq. (diffuse2) (full accommodation) -- for a wall sliding at
+ * speed U along x, Eq. (diffuse1): the reflected density plus 2 U xi (the
+ * linearised Maxwellian of the moving wall) -- plus, as a reading for
  * alpha < 1, Maxwell's specular share 1 - alpha of the mirrored incident
- * face value.  Both come from the previous iterate. */
+ * face value.  The density and incident values come from the previous
+ * iterate. */
 static inline double face_out(const si_ctx *s, int c, int d, int k)
 {
-    double f = s->alpha * s->rho_w[4 * c + d];
+    double f = s->alpha * (s->rho_w[4 * c + d] + 2.0 * wall_speed(s, c, d) * s->xi[k]);
     if (s->alpha < 1.0)
         f += (1.0 - s->alpha) *
              s->hinc[((size_t)s->wall_slot[c] * 4 + d) * s->K + mirror(k, d, s->nv)];
@@ -225,7 +245,7 @@ static void sweep_velocity(const si_ctx *s, int k)
             if (s->solid[c])
                 continue;
             double E = s->a0[c] + s->a1[c] * xi + s->a2[c] * eta + s->a3[c] * q;
-            double num = s->dl[c] * E + xi; /* unit pressure-gradient drive */
+            double num = s->dl[c] * E + s->drive * xi; /* pressure-gradient drive */
             double den = s->dl[c];
             upwind_axis(s, hk, s->codes[4 * c + dxs], c,
                         y * nx + wrap(x + sx, nx), y * nx + wrap(x + 2 * sx, nx),
@@ -240,6 +260,10 @@ static void sweep_velocity(const si_ctx *s, int k)
 
 /* Source iteration (Eq. iteration) to the stop rule.
  *   delta: 1 value or one per cell (ny*nx); alpha in (0,1].
+ *   drive: factor of the pressure-gradient source xi (1: Poiseuille flow of
+ *   Sec. III, 0: Couette flow of Sec. II); u_bottom, u_top: x velocities of
+ *   the outer walls (walled channels only; Eq. (diffuse1) with U0/v_m = 1
+ *   is u_top = 1).
  *   tol < 0 runs exactly max_iter iterations (timing mode).
  *   Outputs (ny*nx, zero in solids): rho (zero fluid mean), u1, u2, tau, p12.
  *   info_out = {Q, iterations, final relative change}.
@@ -249,13 +273,16 @@ static void sweep_velocity(const si_ctx *s, int k)
  * negative on bad input. */
 int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
                     double cells_per_H, int nv, const double *delta,
-                    int delta_is_field, double alpha, double tol, long max_iter,
+                    int delta_is_field, double alpha, double drive,
+                    double u_bottom, double u_top, double tol, long max_iter,
                     double *rho, double *u1, double *u2, double *tau,
                     double *p12, double *info_out, double *eps_hist,
                     double *h_out)
 {
     if (!(nx == 1 || nx >= 4) || ny < 4 || nv < 4 || (nv % 2) || cells_per_H <= 0 ||
-        !(alpha > 0 && alpha <= 1) || max_iter < 1)
+        !(alpha > 0 && alpha <= 1) || max_iter < 1 || !isfinite(drive) ||
+        !isfinite(u_bottom) || !isfinite(u_top) ||
+        (periodic_y && (u_bottom != 0.0 || u_top != 0.0)))
         return -2;
     const int K = nv * nv, nc = nx * ny;
     double *v = malloc(sizeof(double) * nv), *w1 = malloc(sizeof(double) * nv);
@@ -290,7 +317,8 @@ int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
     double *hinc_new = calloc((size_t)(nwall > 0 ? nwall : 1) * 4 * K, sizeof(double));
     if (!hinc || !hinc_new)
         return -3;
-    si_ctx s = {nx, ny, nv, K, nc, periodic_y, 1.0 / cells_per_H, alpha, xi, eta, W,
+    si_ctx s = {nx, ny, nv, K, nc, periodic_y, 1.0 / cells_per_H, alpha, drive,
+                {u_bottom, u_top}, xi, eta, W,
                 solid, codes, dl, a, a + nc, a + 2 * nc, a + 3 * nc,
                 rho_w, wall_slot, hinc, h};
 

@@ -103,6 +103,12 @@ struct dvm_ctx {
     std::vector<double> v, w1;
     double m0 = 0, m2 = 0, M2 = 0, M4 = 0, c2 = 0, c4 = 0, D = 0;
     std::vector<HostInst> inst;
+    // what drives each instance's flow (dvm_set_driving): pressure-gradient
+    // factor and x velocities of the outer bottom / top walls
+    struct Driving {
+        double drive = 1.0, u_bot = 0.0, u_top = 0.0;
+    };
+    std::vector<Driving> driving;
 
     // layout of the device buffers
     bool layout_ok = false;
@@ -487,6 +493,8 @@ static int build_layout(dvm_ctx *c)
             d.delta = prev[i].delta;
             d.alpha = prev[i].alpha;
             d.drive = prev[i].drive;
+            d.u_bot = prev[i].u_bot;
+            d.u_top = prev[i].u_top;
             d.field = prev[i].field;
         }
     c->ncell = cell;
@@ -1970,9 +1978,13 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
     if (!(alpha > 0.0 && alpha <= 1.0))
         return fail(DVM_EINVAL, "alpha must lie in (0, 1]");
     const int i0 = instance < 0 ? 0 : instance, i1 = instance < 0 ? c->n_inst : instance + 1;
-    for (int i = i0; i < i1; ++i)
+    for (int i = i0; i < i1; ++i) {
         if (!c->inst[i].has_geom)
             return fail(DVM_ESTATE, "dvm_set_geometry has not been called for instance " + std::to_string(i));
+        if (c->inst[i].periodic_y && (c->driving[i].u_bot != 0.0 || c->driving[i].u_top != 0.0))
+            return fail(DVM_EINVAL, "instance " + std::to_string(i) +
+                                        ": sliding walls need a walled channel (periodic_y = 0)");
+    }
     // validate delta on the host before any device work
     {
         size_t off = 0;
@@ -2015,7 +2027,9 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
         h.field = delta_is_field != 0;
         d.alpha = alpha;
         d.field = h.field ? 1 : 0;
-        d.drive = 1.0;
+        d.drive = c->driving[i].drive;
+        d.u_bot = c->driving[i].u_bot;
+        d.u_top = c->driving[i].u_top;
         if (h.field) {
             size_t n = (size_t)h.nx * h.ny;
             h.dfield.assign(delta + off, delta + off + n);
@@ -2371,6 +2385,7 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->sweeps_done.assign(n_instances, 0);
     ctx->sweeps64_done.assign(n_instances, 0);
     ctx->sweeps_wasted.assign(n_instances, 0);
+    ctx->driving.assign(n_instances, dvm_ctx::Driving{});
     ctx->sweeps64_wasted.assign(n_instances, 0);
     ctx->stream = (hipStream_t)hip_stream;   // NULL: a stream is made on first use
     build_quadrature(ctx);
@@ -2414,6 +2429,22 @@ int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny, const uint8_t *
     return DVM_OK;
 }
 
+int dvm_set_driving(dvm_ctx *ctx, int instance, double pressure_gradient, double wall_velocity_bottom,
+                    double wall_velocity_top)
+{
+    int rc = check_instance(ctx, instance);
+    if (rc)
+        return rc;
+    if (!std::isfinite(pressure_gradient) || !std::isfinite(wall_velocity_bottom) ||
+        !std::isfinite(wall_velocity_top))
+        return fail(DVM_EINVAL, "driving parameters must be finite");
+    auto &dr = ctx->driving[instance];
+    dr.drive = pressure_gradient;
+    dr.u_bot = wall_velocity_bottom;
+    dr.u_top = wall_velocity_top;
+    return DVM_OK;
+}
+
 int dvm_solve(dvm_ctx *ctx, int instance, const double *delta, int delta_is_field, double alpha,
               dvm_info *info)
 {
@@ -2450,6 +2481,53 @@ int dvm_flow_rate(const dvm_ctx *cc, int instance, double *Q, double *k_a)
     *Q = s / (h.cph * h.nx);   // (1/L) sum u1 dA, L = nx / cells_per_H
     if (k_a)
         *k_a = h.field ? NAN : *Q / h.delta;
+    return DVM_OK;
+}
+
+int dvm_permeability(int n, const double *delta, const double *Q, double phi, double *k_inf, double *H_star,
+                     double *Kn_star, double *ka_ratio)
+{
+    if (n < 3 || !delta || !Q)
+        return fail(DVM_EINVAL, "need n >= 3 samples (delta, Q)");
+    if (!(phi > 0.0 && phi <= 1.0))
+        return fail(DVM_EINVAL, "porosity must lie in (0, 1]");
+    std::vector<double> kn(n), ka(n);
+    for (int i = 0; i < n; ++i) {
+        if (!(std::isfinite(delta[i]) && delta[i] > 0.0 && std::isfinite(Q[i])))
+            return fail(DVM_EINVAL, "delta must be finite and > 0, Q finite");
+        kn[i] = std::sqrt(M_PI) / (2.0 * delta[i]);    // delta = sqrt(pi) / (2 Kn)
+        ka[i] = Q[i] / delta[i];                         // k_a = sqrt(4/pi) Q Kn
+    }
+    // the three samples closest to the continuum limit
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i)
+        idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return kn[a] < kn[b]; });
+    for (int i = 0; i + 1 < n; ++i)
+        if (kn[idx[i]] == kn[idx[i + 1]])
+            return fail(DVM_EINVAL, "two samples share the same delta");
+    // Lagrange form of the interpolating quadratic, evaluated at Kn = 0
+    double k0 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double l = 1.0;
+        for (int b = 0; b < 3; ++b)
+            if (b != a)
+                l *= (0.0 - kn[idx[b]]) / (kn[idx[a]] - kn[idx[b]]);
+        k0 += ka[idx[a]] * l;
+    }
+    if (!(k0 > 0.0 && std::isfinite(k0)))
+        return fail(DVM_EINVAL, "the extrapolated intrinsic permeability is not positive");
+    const double hs = std::sqrt(12.0 * k0 / phi);       // H* / H
+    if (k_inf)
+        *k_inf = k0;
+    if (H_star)
+        *H_star = hs;
+    for (int i = 0; i < n; ++i) {
+        if (Kn_star)
+            Kn_star[i] = kn[i] / hs;
+        if (ka_ratio)
+            ka_ratio[i] = ka[i] / k0;
+    }
     return DVM_OK;
 }
 

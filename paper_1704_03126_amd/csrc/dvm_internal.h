@@ -72,6 +72,7 @@ struct InstDev {
     double alpha;         // accommodation coefficient
     double drive;         // coefficient of the pressure-gradient source
     double inv_dx;
+    double u_bot, u_top;  // x velocities of the outer bottom / top walls
 };
 
 struct WorkItem {

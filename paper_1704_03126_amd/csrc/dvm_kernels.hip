@@ -334,11 +334,13 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
         const bool solid = craw < 0;
         const int cl = craw & SMAP_CELL;
         const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
-        // wall values only where the cell has a wall term (LDS bandwidth)
-        T gx = T(0), gy = T(0);
+        // wall values only where the cell has a wall term (LDS bandwidth);
+        // mw = 2 alpha U of a sliding wall on the y-upwind side (else 0)
+        T gx = T(0), gy = T(0), mw = T(0);
         if (FIELD || (craw & SMAP_WALL) != 0) {
             gx = rec[4];
             gy = rec[5];
+            mw = rec[7];
         }
         const T px = lds_lut[xn & 7][0], qx = lds_lut[xn & 7][1];
         const T py = lds_lut[yn & 7][0], qy = lds_lut[yn & 7][1];
@@ -351,6 +353,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             dl = rec[6];
         }
         const T sbase = XU ? fma(b1, cxi[0], b0) : T(0);
+        const T gyw = XU ? fma(mw, cxi[0], gy) : T(0);
         FaceRec fr;
         if (FACES)
             fr = st_face[b][s][lane];
@@ -363,7 +366,8 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             const T sm2 = st_seam[b][s][0][wave * V + v];
             const T hS1 = dpp_shr1(sm1, p1);
             const T hS2 = dpp_shr1(sm2, h1);
-            T gxv = gx, gyv = gy;
+            // a sliding wall emits rho_w + 2 U xi (Eq. diffuse1)
+            T gxv = gx, gyv = XU ? gyw : fma(mw, cxi[v], gy);
             if (SPEC) {
                 // Maxwell's specular share: mirrored value of the previous iterate
                 if (fr.rdx >= 0)
@@ -615,8 +619,7 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
             rec[2] = T(dl * (u2 / a.m2));
             rec[3] = T(dl * t);
             rec[6] = T(dl);
-            rec[7] = T(0);
-            double gside[4];
+            double gside[4], mside[4];
             const int x = c % in.nx, y = c / in.nx;
             for (int d = 0; d < 4; ++d) {
                 const int cd = (code >> (2 * d)) & 3;
@@ -636,7 +639,17 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
                     return in.cell_off + (long long)nyy * in.nx + nxx;
                 };
                 double gval = 0.0;
+                mside[d] = 0.0;
                 if (!a.adjoint) {
+                    // the outer bottom / top wall of a channel may slide along
+                    // x: its diffuse emission gains 2 U xi (Eq. diffuse1), a
+                    // source term (left out of the homogeneous map)
+                    if (cd == CODE_WALL && !in.periodic_y && !a.homog) {
+                        if (d == SIDE_S && y == 0)
+                            mside[d] = 2.0 * in.alpha * in.u_bot;
+                        else if (d == SIDE_N && y == in.ny - 1)
+                            mside[d] = 2.0 * in.alpha * in.u_top;
+                    }
                     if (cd == CODE_WALL) {
                         // incident flux through the wall face on side d: the
                         // half-range flux of the cell, extrapolated from the
@@ -666,6 +679,7 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
             for (int qd = 0; qd < 4; ++qd) {
                 rec[4] = T(gside[(qd & 1) ? SIDE_E : SIDE_W]);
                 rec[5] = T(gside[(qd & 2) ? SIDE_N : SIDE_S]);
+                rec[7] = T(mside[(qd & 2) ? SIDE_N : SIDE_S]);
                 const long long pos = a.spos[cg * 4 + qd];
                 T *dst = a.srec + pos * 8;
                 for (int i = 0; i < 8; ++i)
@@ -728,8 +742,10 @@ __global__ void __launch_bounds__(256) k_grad_cell(GradArgs a, int instance)
 }
 
 // dQ/d alpha, part of wall face phi: sum over the velocities j that cross
-// the face towards the wall of (|v_n|/dx) W_j nu_j (rho_w - h_inc(mirror(-j))),
-// rho_w the diffuse density of the face from the forward incident values.
+// the face towards the wall of
+// (|v_n|/dx) W_j nu_j (rho_w + 2 U xi(-j) - h_inc(mirror(-j))),
+// rho_w the diffuse density of the face from the forward incident values and
+// U the x velocity of a sliding outer wall (0 for the staircase).
 __global__ void __launch_bounds__(256) k_grad_face(GradArgs a)
 {
     const int f = a.face0 + blockIdx.x;
@@ -745,6 +761,10 @@ __global__ void __launch_bounds__(256) k_grad_face(GradArgs a)
     const int qa = side == SIDE_W ? 1 : side == SIDE_E ? 0 : side == SIDE_S ? 2 : 0;
     const int qb = side == SIDE_W ? 3 : side == SIDE_E ? 2 : side == SIDE_S ? 3 : 1;
     const int mflip = xface ? 1 : 2;
+    const int fy = (int)((a.face_cell[f] - in.cell_off) / in.nx);
+    const double uw = in.periodic_y ? 0.0
+                    : (side == SIDE_S && fy == 0) ? in.u_bot
+                    : (side == SIDE_N && fy == in.ny - 1) ? in.u_top : 0.0;
     __shared__ double red[256];
     double r = 0.0;
     for (int e = threadIdx.x; e < 2 * a.kq; e += 256) {
@@ -769,7 +789,8 @@ __global__ void __launch_bounds__(256) k_grad_face(GradArgs a)
         const int j = q * a.kq + idx;
         const int jm = (q ^ 3 ^ mflip) * a.kq + idx;
         const double vn = fabs(vt[(size_t)j * VT_STRIDE + (xface ? VT_XI : VT_ETA)]);
-        g += vt[(size_t)j * VT_STRIDE + VT_W] * vn * fa[j] * (rho_w - ff[jm]);
+        const double emit = rho_w - 2.0 * uw * vt[(size_t)j * VT_STRIDE + VT_XI];   // xi(-j) = -xi(j)
+        g += vt[(size_t)j * VT_STRIDE + VT_W] * vn * fa[j] * (emit - ff[jm]);
     }
     red[threadIdx.x] = g;
     __syncthreads();

@@ -36,7 +36,8 @@ SCHED_NAMES = {DVM_SCHED_SKEW: "skew", DVM_SCHED_WRAP: "wrap"}
 
 EXPORTED = ("dvm_create", "dvm_set_geometry", "dvm_solve", "dvm_solve_warm",
             "dvm_flow_rate", "dvm_get_moments", "dvm_grad", "dvm_destroy",
-            "dvm_last_error", "dvm_version", "dvm_profile", "dvm_launch_shape")
+            "dvm_last_error", "dvm_version", "dvm_profile", "dvm_launch_shape",
+            "dvm_permeability", "dvm_set_driving")
 
 
 class DVMError(RuntimeError):
@@ -87,6 +88,8 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(ctypes.c_double)]
     IP = ctypes.POINTER(ctypes.c_int)
     lib.dvm_launch_shape.argtypes = [P, IP, IP, IP, IP]
+    lib.dvm_set_driving.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.dvm_permeability.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P]
     lib.dvm_destroy.argtypes = [P]
     lib.dvm_destroy.restype = None
     lib.dvm_last_error.restype = ctypes.c_char_p
@@ -124,6 +127,22 @@ class SolveInfo:
     est_error: float
     status: str
     schedule: str = ""
+
+
+def permeability(delta, Q, porosity: float) -> dict:
+    """Intrinsic permeability k_inf (Kn -> 0 limit of k_a), H*/H, and Kn*,
+    k_a/k_inf per sample of a rarefaction sweep (dvm_permeability)."""
+    lib = load_library()
+    d = np.ascontiguousarray(delta, dtype=np.float64).ravel()
+    q = np.ascontiguousarray(Q, dtype=np.float64).ravel()
+    if d.shape != q.shape:
+        raise ValueError("delta and Q must have the same length")
+    k, h = ctypes.c_double(), ctypes.c_double()
+    kns, rat = np.zeros_like(d), np.zeros_like(d)
+    _check(lib.dvm_permeability(len(d), _ptr(d), _ptr(q), float(porosity), ctypes.byref(k),
+                                ctypes.byref(h), _ptr(kns), _ptr(rat)))
+    return {"k_inf": k.value, "H_star": h.value, "Kn_star": kns, "ka_ratio": rat,
+            "Kn": np.sqrt(np.pi) / (2.0 * d), "k_a": q / d}
 
 
 class Solver:
@@ -194,6 +213,22 @@ class Solver:
                          STATUS_NAMES.get(i.status, str(i.status)),
                          SCHED_NAMES.get(i.schedule, str(i.schedule))) for i in infos]
         return out if instance < 0 else out[0]
+
+    def set_driving(self, instance: int, pressure_gradient: float = 1.0, wall_velocity=(0.0, 0.0)):
+        """Source of the flow: pressure-gradient factor (1: Poiseuille) and the
+        x velocities (bottom, top) of the outer walls ((0, 1) with gradient 0:
+        the Couette problem)."""
+        _check(self._lib.dvm_set_driving(self._h, instance, float(pressure_gradient),
+                                         float(wall_velocity[0]), float(wall_velocity[1])))
+
+    def delta_sweep(self, instance: int, deltas, alpha: float = 1.0):
+        """Solve one instance along a rarefaction sweep, each solve starting
+        from the previous solution; returns (Q per delta, SolveInfo per delta)."""
+        Qs, infos = [], []
+        for i, d in enumerate(deltas):
+            infos.append(self.solve(instance, float(d), alpha, warm=i > 0))
+            Qs.append(self.flow_rate(instance)[0])
+        return np.array(Qs), infos
 
     def flow_rate(self, instance: int = 0):
         Q = ctypes.c_double()

@@ -77,6 +77,49 @@ def rough_channel(nx: int, ny: int, rough_rows: int, rough_cols: int,
                     porosity=phi)
 
 
+def wm_profile(x, A: float, D: float = 1.5, gamma: float = 1.5, n1: int = -4,
+               n_max: int = 0) -> np.ndarray:
+    """Weierstrass-Mandelbrot roughness r(x) of Eq. (WM), x = x1/H:
+    A * sum_{n=n1}^{n_max} cos(2 pi gamma^n x) / gamma^((2-D) n)."""
+    x = np.asarray(x, dtype=np.float64)
+    r = np.zeros_like(x)
+    for n in range(n1, n_max + 1):
+        r += np.cos(2.0 * np.pi * gamma ** n * x) / gamma ** ((2.0 - D) * n)
+    return A * r
+
+
+def fractal_couette_channel(cells_per_H: int, aspect: int = 5, D: float = 1.5,
+                            eps: float = 0.02, gamma: float = 1.5,
+                            n1: int = -4) -> Geometry:
+    """Channel of Sec. II: a smooth top plate at x2 = H and a bottom plate
+    whose surface is the Weierstrass-Mandelbrot profile r(x1/H) of Eq. (WM),
+    rendered as a staircase; length aspect * H (periodic along x).
+
+    Readings (the paper gives the series and eps = sigma/H only):
+      * the series is cut where a wavelength would drop below two cells,
+        gamma^n <= cells_per_H / 2;
+      * A is set so that the root mean square of r over the cell centres of
+        the period equals eps * H;
+      * H is measured from the mean line x2 = 0 of the bottom plate to the
+        top plate; cells whose centre lies below r are solid, and rows are
+        added below x2 = 0 down to the deepest valley.
+    """
+    nx = int(aspect * cells_per_H)
+    n_max = int(np.floor(np.log(cells_per_H / 2.0) / np.log(gamma)))
+    xc = (np.arange(nx) + 0.5) / cells_per_H
+    unit = wm_profile(xc, 1.0, D, gamma, n1, n_max)
+    A = eps / np.sqrt(np.mean(unit ** 2))
+    r = A * unit                                  # in units of H
+    nb = max(0, int(np.ceil(-r.min() * cells_per_H)))
+    ny = nb + int(cells_per_H)
+    yc = (np.arange(ny) - nb + 0.5) / cells_per_H  # centre heights, in units of H
+    m = (yc[:, None] < r[None, :]).astype(np.uint8)
+    return Geometry(m, periodic_y=False, cells_per_H=float(cells_per_H),
+                    name=f"wm_couette_{nx}x{ny}_D{D}_eps{eps}",
+                    porosity=float((m == 0).mean()),
+                    meta={"A": float(A), "n_max": n_max, "rows_below": nb, "profile": r})
+
+
 def component_labels(mask: np.ndarray, periodic_y: bool):
     """Label 4-connected fluid components on the (x-periodic) grid.
 

@@ -123,6 +123,28 @@ def test_call_order_and_solve_arguments(lib):
         lib.dvm_destroy(h)
 
 
+def test_driving_validation(lib):
+    from paper_1704_03126_amd.geometry import porous_discs
+    rc, h = _ctx(lib, n=2)
+    d = np.array([1.0])
+    dp = d.ctypes.data_as(ctypes.c_void_p)
+    info = dvm.dvm_info()
+    try:
+        assert lib.dvm_set_driving(h, 2, 1.0, 0.0, 0.0) == dvm.DVM_EINVAL
+        assert lib.dvm_set_driving(h, -1, 1.0, 0.0, 0.0) == dvm.DVM_EINVAL
+        for bad in ((np.nan, 0.0, 0.0), (1.0, np.inf, 0.0), (1.0, 0.0, -np.inf)):
+            assert lib.dvm_set_driving(h, 0, *bad) == dvm.DVM_EINVAL
+        # driving set before the geometry is kept; a periodic cell cannot
+        # have sliding walls (rejected before any device work)
+        assert lib.dvm_set_driving(h, 1, 0.0, 0.0, 1.0) == 0
+        g = porous_discs(16, 0.7, 3)
+        assert _set(lib, h, 1, g.mask, periodic_y=1) == 0
+        assert lib.dvm_solve(h, 1, dp, 0, 1.0, ctypes.byref(info)) == dvm.DVM_EINVAL
+        assert b"sliding walls" in lib.dvm_last_error()
+    finally:
+        lib.dvm_destroy(h)
+
+
 def test_python_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(ImportError):
         dvm.load_library.__wrapped__ if hasattr(dvm.load_library, "__wrapped__") else None

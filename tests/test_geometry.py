@@ -66,3 +66,23 @@ def test_batch_instances_uneven_and_seeded():
     assert len(sizes) > 1
     for x in b1:
         assert 64 <= x.nx <= 384 and 0.01 <= x.meta["delta"] <= 100
+
+
+def test_fractal_couette_channel():
+    from paper_1704_03126_amd.geometry import fractal_couette_channel, wm_profile
+    g = fractal_couette_channel(32, eps=0.02)
+    r = g.meta["profile"]
+    assert g.nx == 160 and not g.periodic_y
+    assert abs(np.sqrt(np.mean(r ** 2)) - 0.02) <= 1e-14           # sigma / H
+    # the profile is Eq. (WM) with the stored amplitude, cut at gamma^n <= 16
+    xc = (np.arange(160) + 0.5) / 32
+    assert g.meta["n_max"] == 6
+    assert np.allclose(r, wm_profile(xc, g.meta["A"], 1.5, 1.5, -4, 6), rtol=0, atol=1e-15)
+    # solid below the surface, fluid above, H = 32 rows above the mean line
+    nb = g.meta["rows_below"]
+    assert g.ny == nb + 32
+    yc = (np.arange(g.ny) - nb + 0.5) / 32
+    assert np.array_equal(g.mask, (yc[:, None] < r[None, :]).astype(np.uint8))
+    assert np.all(g.mask[nb + 8:] == 0)
+    # every column is solid from the bottom up to its surface only
+    assert np.all(np.diff(g.mask.astype(int), axis=0) <= 0)
