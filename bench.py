@@ -147,8 +147,11 @@ def main():
                           waves_per_block=args.waves, schedule=sched)
         prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
         prof_sched = set()
+        prof_iters = 0
         for d in DELTAS:
-            prof_sched.add(prof.solve(0, d).schedule)
+            pinfo = prof.solve(0, d)
+            prof_sched.add(pinfo.schedule)
+            prof_iters += pinfo.iters
         sweep_ms, n_sweeps, other_ms = prof.profile()
         (pv, pg), _ = prof.launch_shape()
         prof.close()
@@ -177,6 +180,7 @@ def main():
                     "kernel": f"k_sweep<double,{pv},{pg}> ({kernel_sched} order)",
                     "avg_launch_ms": avg_sweep_s * 1e3,
                     "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": nf * K,
+                    "launches_timed": n_sweeps, "iterations_timed": prof_iters,
                     "sweep_share_of_iteration": sweep_ms / max(sweep_ms + other_ms, 1e-30)}
 
     cpu = None

@@ -224,9 +224,11 @@ int dvm_permeability(int n, const double *delta, const double *Q, double phi,
                      double *ka_ratio);
 
 /* Kernel timings gathered while cfg.profile == 1, since the previous call:
- * total milliseconds spent in sweep launches and their count, and total
- * milliseconds of the other kernels of the iterations (moments, record,
- * stop rule).  Resets the totals.  Any output may be NULL. */
+ * total milliseconds spent in the sweep launches of the plain iteration and
+ * their count, and total milliseconds of the other kernels of those
+ * iterations (moments, record, stop rule).  Launches at the end of a
+ * 32-iteration block that find every instance stopped (and return at once)
+ * are not counted.  Resets the totals.  Any output may be NULL. */
 int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms);
 
 /* Sweep launch shape in use: velocities per lane and waves per workgroup of

@@ -761,18 +761,20 @@ static int next_event(dvm_ctx *c, hipEvent_t *e)
     return DVM_OK;
 }
 
-// Fold the recorded event pairs into the totals (the stream is idle).
-static int collect_profile(dvm_ctx *c)
+// Fold the recorded event pairs into the totals (the stream is idle).  Only
+// the first `real` iterations of the block did work: the later launches found
+// every instance stopped and returned at once, and are left out.
+static int collect_profile(dvm_ctx *c, long long real)
 {
-    for (auto &p : c->ev_sweep) {
+    for (size_t i = 0; i < c->ev_sweep.size() && (long long)i < real; ++i) {
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+        HIPCHK(hipEventElapsedTime(&ms, c->ev_sweep[i].first, c->ev_sweep[i].second));
         c->prof_sweep_ms += ms;
         ++c->prof_sweeps;
     }
-    for (auto &p : c->ev_other) {
+    for (size_t i = 0; i < c->ev_other.size() && (long long)i < real; ++i) {
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+        HIPCHK(hipEventElapsedTime(&ms, c->ev_other[i].first, c->ev_other[i].second));
         c->prof_other_ms += ms;
     }
     c->ev_sweep.clear();
@@ -952,7 +954,10 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
         double eps, amax;
     };
     std::vector<std::vector<Hist>> hist(c->n_inst);
+    std::vector<long long> before(c->n_inst);
     for (;;) {
+        for (int i = 0; i < c->n_inst; ++i)
+            before[i] = st[i].iter;
         int rc = enqueue_block(c, B, kind);
         if (rc)
             return rc;
@@ -960,7 +965,10 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                               c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         if (c->cfg.profile) {
-            int prc = collect_profile(c);
+            long long real = 0;
+            for (int i = 0; i < c->n_inst; ++i)
+                real = std::max(real, st[i].iter - before[i]);
+            int prc = collect_profile(c, real);
             if (prc)
                 return prc;
         }
