@@ -49,10 +49,11 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--workload", choices=["rough_channel", "batch64"], default="rough_channel",
+    p.add_argument("--workload", choices=["rough_channel", "batch64", "couette"], default="rough_channel",
                    help="rough_channel: the headline workload; batch64: 64 uneven instances "
-                        "(sides 64-384, 48 x 48 velocities) in one batched solve, throughput "
-                        "over a fixed number of iterations")
+                        "(sides 64-384, 48 x 48 velocities) in one batched solve, throughput over a "
+                        "fixed number of iterations; couette: the Couette flow of the fractal rough "
+                        "channel and the smooth one over Kn 0.03-10 (Q*)")
     p.add_argument("--batch-iters", type=int, default=24,
                    help="iterations per timed batched solve (batch64)")
     p.add_argument("--schedule", choices=["auto", "skew", "wrap"], default="auto",
@@ -98,6 +99,8 @@ def main():
 
     if args.workload == "batch64":
         return bench_batch(args, torch, dvm)
+    if args.workload == "couette":
+        return bench_couette(args, torch, dvm)
 
     g = cfg_rough_channel()
     nf = g.n_fluid
@@ -251,6 +254,59 @@ def bench_batch(args, torch, dvm):
                       "cells": int(sum(g.nx * g.ny for g in gs)), "fluid_cells": int(sum(nfl)),
                       "velocities": nv * nv, "iterations_per_solve": args.batch_iters,
                       "precision": args.precision, "parallelism": "single_gpu"},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
+def bench_couette(args, torch, dvm):
+    """Couette flow of Sec. II: the fractal (D = 1.5, eps = 2 %) rough channel
+    of aspect ratio 5 at 64 cells per H and the smooth channel, top plate
+    sliding at U0/v_m = 1, 32 x 32 velocities, Kn 0.03-10; one step
+    = every Kn for both channels, solved to tol 1e-8 (warm starts along the
+    Kn list).  Reports Q_r, Q_s and Q* = Q_r / Q_s per Kn."""
+    from paper_1704_03126_amd.geometry import fractal_couette_channel, plane_channel
+    nv = 32
+    kns = [0.03, 0.1, 0.3, 1.0, 3.0, 10.0]
+    deltas = [float(np.sqrt(np.pi) / (2 * kn)) for kn in kns]
+    rough = fractal_couette_channel(64, aspect=5, D=1.5, eps=0.02)
+    smooth = plane_channel(64, 1)
+    solvers = []
+    for g in (rough, smooth):
+        s = dvm.Solver(nv, 1, tol=TOL, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
+                       else dvm.DVM_FP64)
+        s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        s.set_driving(0, 0.0, (0.0, 1.0))
+        solvers.append((s, g))
+
+    def step():
+        out, upd = [], 0.0
+        for s, g in solvers:
+            Qs, infos = s.delta_sweep(0, deltas[::-1])     # continuum end first: warm starts
+            out.append(Qs[::-1])
+            upd += sum(i.iters for i in infos) * g.n_fluid * nv * nv
+        return out, upd
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    upd = 0.0
+    for _ in range(args.steps):
+        (qr, qs), u = step()
+        upd += u
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for s, _ in solvers:
+        s.close()
+    out = {"metric": METRIC, "value": upd / elapsed, "unit": "updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+           "config": {"workload": "couette_wm_D1.5_eps0.02_aspect5_64perH_nv32",
+                      "rough_cells": [rough.ny, rough.nx], "Kn": kns, "tol": TOL,
+                      "precision": args.precision, "parallelism": "single_gpu"},
+           "Q_rough": [float(q) for q in qr], "Q_smooth": [float(q) for q in qs],
+           "Q_star": [float(a / b) for a, b in zip(qr, qs)],
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out))
 

@@ -101,11 +101,14 @@ typedef struct {
                                (seen with a solid block inside a periodic
                                cell); DVM_SCHED_AUTO (default) starts every
                                instance on the wrap-around diagonal and moves
-                               an instance whose relative change of u1 has not
-                               dropped by 5% over 64 iterations to the skewed
-                               order for good: the layout is rebuilt and the
-                               solve restarts (other instances of the context
-                               lose their state, as after dvm_set_geometry)  */
+                               an instance that runs away there (relative
+                               change of u1 not down by 5% over 64 iterations
+                               while max |u1| grew by 10%, or non-finite
+                               iterates) to the skewed order for good: the
+                               layout is rebuilt, that instance's solve
+                               restarts from zero and the other instances of
+                               the call restart from their current state
+                               (instances outside the call keep theirs)     */
     int accel;              /* DVM_ACCEL_AUTO (default), DVM_ACCEL_NONE or
                                DVM_ACCEL_GMRES.  GMRES drives the iteration's
                                state (moments, lagged seam, wrap and wall
@@ -113,12 +116,14 @@ typedef struct {
                                same fixed point; it converges where the lagged
                                iteration diverges.  AUTO hands an instance to
                                GMRES when its relative change of u1 has not
-                               dropped by 5% over 64 iterations.  GMRES stop
+                               dropped by 0.5% over 64 iterations (a slowly
+                               contracting iteration stays plain).  GMRES stop
                                rule: one iteration from the result changes u1
                                by eps (relative) with eps / sigma <= tol,
                                sigma the smallest singular value of the last
                                Krylov projection clamped to [1e-3, 1]         */
-    int krylov_dim;         /* GMRES restart length; 0 -> 30 (max 64)         */
+    int krylov_dim;         /* GMRES restart length; 0 -> 64 (max 64); at large
+                               delta (Kn 0.01-0.03) a restart of 30 stagnated */
 } dvm_config;
 
 /* Per-instance result of dvm_solve. */

@@ -935,11 +935,13 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
 // With stall detection (DVM_ACCEL_AUTO) an instance whose relative change of
 // u1 has not dropped by 5% over the last 64 iterations is stopped and flagged
 // in stalled[] (its state is that of a completed iteration).
-// Stall test (when `stalled` is given): an instance whose relative change
-// has not dropped by 5% over the last 64 iterations stops, with stalled = 1;
-// = 2 if max |u1| also grew by more than 10% over that window, i.e. the
-// iterates run away instead of creeping towards the fixed point.  Instances
-// with grow_only set stop only in the second case.
+// Stall test (when `stalled` is given), over the last 64 iterations: an
+// instance whose relative change has not dropped by 5% while max |u1| grew
+// by more than 10% runs away instead of creeping towards the fixed point
+// (stalled = 2); one whose relative change has not dropped by 0.5% does not
+// contract at all (stalled = 1).  A slow but contracting iteration (large
+// delta) is left alone: restarted GMRES does worse there.  Instances with
+// grow_only set stop only in the first case.
 static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, int kind,
                       std::vector<SolveState> &st, std::vector<char> *stalled = nullptr,
                       const std::vector<char> *grow_only = nullptr)
@@ -984,11 +986,12 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                 for (const auto &e : hv)
                     if (e.it <= it - W)
                         old = &e;
-                if (old && old->eps > 0.0 && st[i].eps > tol && !(st[i].eps < 0.95 * old->eps)) {
-                    const bool grows = st[i].amax > 1.1 * old->amax;
-                    if (grows || !(grow_only && (*grow_only)[i])) {
+                if (old && old->eps > 0.0 && st[i].eps > tol) {
+                    const bool runaway = !(st[i].eps < 0.95 * old->eps) && st[i].amax > 1.1 * old->amax;
+                    const bool flat = !(st[i].eps < 0.995 * old->eps);
+                    if (runaway || (flat && !(grow_only && (*grow_only)[i]))) {
                         st[i].active = 0;
-                        (*stalled)[i] = grows ? 2 : 1;
+                        (*stalled)[i] = runaway ? 2 : 1;
                         stop = true;
                         continue;
                     }
@@ -1179,7 +1182,7 @@ static double sigma_min_tri(const std::vector<double> &R, int ld, int k)
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
                      const std::vector<long long> &prior)
 {
-    const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 30;
+    const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 64;
     const int mode = solve_mode(c) | (adj ? MODE_ADJ : 0);
     SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
     StateBufs sb;
