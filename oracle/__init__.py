@@ -50,7 +50,7 @@ def _load():
         lib.oracle_codes.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
         D = ctypes.c_double
         lib.oracle_si_solve.argtypes = [
-            ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D,
+            ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D, P,
             ctypes.c_int, P, ctypes.c_int, D, D, D, D, D,
             ctypes.c_long, P, P, P, P, P, P, P, P]
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -122,7 +122,7 @@ class SIResult:
 
 def si_solve(mask: np.ndarray, delta, nv: int, *, periodic_y: bool = False,
              cells_per_H: float | None = None, alpha: float = 1.0,
-             drive: float = 1.0, wall_velocity=(0.0, 0.0),
+             drive: float = 1.0, wall_velocity=(0.0, 0.0), dy=None,
              tol: float = 1e-12, max_iter: int = 100000,
              return_h: bool = False) -> SIResult:
     """Run the paper's source iteration to the stop rule (FP64, CPU).
@@ -130,6 +130,7 @@ def si_solve(mask: np.ndarray, delta, nv: int, *, periodic_y: bool = False,
     ``delta`` is a scalar or a (ny, nx) field; ``cells_per_H`` defaults to ny.
     ``drive`` scales the pressure-gradient source (1: Poiseuille, 0: Couette);
     ``wall_velocity`` = (bottom, top) x velocities of the outer walls.
+    ``dy`` = ny row heights in units of H (nonuniform rows), else uniform.
     ``tol < 0`` runs exactly ``max_iter`` iterations.
     """
     lib = _load()
@@ -144,7 +145,10 @@ def si_solve(mask: np.ndarray, delta, nv: int, *, periodic_y: bool = False,
     info = np.zeros(3)
     hist = np.zeros(max_iter)
     h = np.zeros((nv * nv, ny, nx)) if return_h else None
-    rc = lib.oracle_si_solve(nx, ny, _ptr(m), int(periodic_y), float(cells_per_H), nv,
+    dya = None if dy is None else np.ascontiguousarray(dy, dtype=np.float64)
+    if dya is not None and dya.shape != (ny,):
+        raise ValueError("dy needs one height per row")
+    rc = lib.oracle_si_solve(nx, ny, _ptr(m), int(periodic_y), float(cells_per_H), _ptr(dya), nv,
                              _ptr(d), field, float(alpha), float(drive),
                              float(wall_velocity[0]), float(wall_velocity[1]),
                              float(tol), int(max_iter),

@@ -83,6 +83,7 @@ class System:
     P: np.ndarray
     nh: int                 # number of cell unknowns nf * K
     ds_dalpha: np.ndarray = None   # d s / d alpha (moving walls)
+    area: np.ndarray = None        # dA / L per fluid cell (flow-rate weights)
 
 
 _STEP = {0: (0, -1), 1: (0, 1), 2: (-1, 0), 3: (1, 0)}   # side -> (dy, dx)
@@ -99,7 +100,7 @@ def _solid(mask, periodic_y, y, x):
 
 
 def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
-             alpha=1.0, drive=(1.0, 0.0), wall_velocity=(0.0, 0.0)) -> System:
+             alpha=1.0, drive=(1.0, 0.0), wall_velocity=(0.0, 0.0), dy=None) -> System:
     """Assemble the steady problem with explicit wall-face unknowns.
 
     Unknowns: h[f*K + k] for every fluid cell f and velocity k, then
@@ -121,6 +122,11 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
     along x at wall_velocity = (U_bottom, U_top); their diffuse part is then
     that of Eq. (diffuse1), rho_w + 2 U xi, a source term of the face rows.
 
+    dy (optional): row heights in units of H.  Along y the face value
+    extrapolated from the upwind cell u through uu is h_u + r (h_u - h_uu),
+    r = dy_u / (dy_u + dy_uu) (1/2 on a uniform grid), and the flux
+    difference is divided by the cell's own height.
+
     drive = (a, b) is the source a xi + b eta of every cell (pressure
     gradients along x and y; (1, 0) is the Poiseuille problem of Sec. III,
     (0, 0) with U_top = 1 the Couette problem of Sec. II).
@@ -130,6 +136,7 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
     if cells_per_H is None:
         cells_per_H = float(ny)
     dx = 1.0 / cells_per_H
+    hrow = np.full(ny, dx) if dy is None else np.asarray(dy, dtype=np.float64)
     Q = quad(nv)
     K = Q["K"]
     xi, eta, W, D = Q["xi"], Q["eta"], Q["W"], Q["D"]
@@ -202,7 +209,15 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
                 if axis == 0 and nx == 1:
                     continue
                 side = upwind_side(axis, k)
-                c = abs(xi[k] if axis == 0 else eta[k]) / dx
+                yc = fluid[f][0]
+                if axis == 0:
+                    c, rc, ru = abs(xi[k]) / dx, 0.5, 0.5
+                else:
+                    step = _STEP[side][0]
+                    y1, y2 = (yc + step) % ny, (yc + 2 * step) % ny
+                    c = abs(eta[k]) / hrow[yc]
+                    rc = hrow[yc] / (hrow[yc] + hrow[y1])
+                    ru = hrow[y1] / (hrow[y1] + hrow[y2])
                 f1 = nb(f, side, 1)
                 if f1 < 0:                      # wall face on the upwind side
                     add(u, u, 1.0 * c, True)
@@ -210,12 +225,12 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
                     continue
                 f2 = nb(f, side, 2)
                 if f2 < 0:                      # upwind neighbour touches a wall
-                    add(u, u, 1.5 * c, True)
-                    add(u, hid(f1, k), -1.5 * c, True)
+                    add(u, u, (1.0 + rc) * c, True)
+                    add(u, hid(f1, k), -(1.0 + rc) * c, True)
                 else:
-                    add(u, u, 1.5 * c, True)
-                    add(u, hid(f1, k), -2.0 * c, True)
-                    add(u, hid(f2, k), 0.5 * c, True)
+                    add(u, u, (1.0 + rc) * c, True)
+                    add(u, hid(f1, k), -(1.0 + rc + ru) * c, True)
+                    add(u, hid(f2, k), ru * c, True)
 
     nv_ = nv
     for phi, (f, side) in enumerate(faces):
@@ -223,11 +238,18 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
         fo = nb(f, opp, 1)
         inc = [k for k in range(K) if not leaves(side, k)]
 
+        # incident face value extrapolated across the wall cell (through its
+        # neighbour opposite the face)
+        if side >= 2 and fo >= 0:
+            rface = hrow[fluid[f][0]] / (hrow[fluid[f][0]] + hrow[fluid[fo][0]])
+        else:
+            rface = 0.5
+
         def h_inc_terms(k):
             # incident face value as a combination of unknowns
             if fo < 0:
                 return [(hid(f, k), 1.0)]
-            return [(hid(f, k), 1.5), (hid(fo, k), -0.5)]
+            return [(hid(f, k), 1.0 + rface), (hid(fo, k), -rface)]
 
         for k in range(K):
             r = gid(f, side, k)
@@ -266,7 +288,7 @@ def assemble(mask, delta, nv, *, periodic_y=False, cells_per_H=None,
     s += alpha * ds
     return System(A=A, dA_dalpha=dA, T=T, s=s, fluid=fluid, cell_index=cell_index,
                   faces=faces, delta_f=delta_f, Q=Q, nx=nx, ny=ny, dx=dx, P=P, nh=nh,
-                  ds_dalpha=ds)
+                  ds_dalpha=ds, area=hrow[fluid[:, 0]] / nx)
 
 
 def _bordered_solve(M, rhs, g):
@@ -311,7 +333,7 @@ def solve(mask, delta, nv, **kw) -> DenseResult:
     rho = np.zeros((sys.ny, sys.nx)); u1 = np.zeros_like(rho); u2 = np.zeros_like(rho)
     for f, (y, x) in enumerate(sys.fluid):
         rho[y, x], u1[y, x], u2[y, x] = r[f], m1[f], m2[f]
-    Qv = sys.dx / sys.nx * m1.sum()
+    Qv = float(sys.area @ m1)            # (1/L) sum u1 dA, dA / L = dy / nx
     return DenseResult(h=h, Q=Qv, rho=rho, u1=u1, u2=u2, border=lam, sys=sys, x=xv)
 
 
@@ -334,7 +356,7 @@ def adjoint(mask, delta, nv, **kw) -> AdjointResult:
     W, xi = sys.Q["W"], sys.Q["xi"]
     N = sys.A.shape[0]
     c = np.zeros(N)
-    c[:sys.nh] = np.tile(sys.dx / sys.nx * W * xi, nf)
+    c[:sys.nh] = (sys.area[:, None] * (W * xi)[None, :]).ravel()
     g = np.zeros(N)
     g[:sys.nh] = np.tile(W, nf)
     lv, _ = _bordered_solve(sys.A.T, c, g)

@@ -146,6 +146,7 @@ typedef struct {
     const double *xi, *eta, *W;
     const uint8_t *solid, *codes;
     const double *dl;                      /* delta per cell */
+    const double *dy;                      /* row heights (units of H), NULL: uniform dx */
     const double *a0, *a1, *a2, *a3;       /* equilibrium coefficients per cell */
     const double *rho_w;                   /* reflected density per cell and side */
     const int *wall_slot;                  /* cell -> wall-cell row or -1 */
@@ -199,19 +200,24 @@ static inline double face_out(const si_ctx *s, int c, int d, int k)
  * value h_u when that neighbour is solid; on a wall face the value leaving
  * the wall is the wall value.  In the interior this is exactly the paper's
  * (3 h_c - 4 h_1 + h_2) / (2 dx); every face carries one value for both cells
- * it separates, so the scheme conserves mass. */
+ * it separates, so the scheme conserves mass.  On rows of unequal height
+ * (the nonuniform spacing across the channel of Sec. II.A) the same linear
+ * extrapolation reads h_u + r (h_u - h_uu), r = dy_u / (dy_u + dy_uu) the
+ * ratio of the distances from the face and from uu's centre to u's centre:
+ * rc for the cell's own outgoing face, ru for the incoming one (both 1/2 on
+ * a uniform grid), and cv = |v| / dy_c. */
 static inline void upwind_axis(const si_ctx *s, const double *hk, int code,
                                int c, int c1, int c2, int d, int k, double cv,
-                               double *den, double *num)
+                               double rc, double ru, double *den, double *num)
 {
     switch (code) {
-    case ST_INT: /* faces: 1.5 h_c - 0.5 h_1 and 1.5 h_1 - 0.5 h_2 */
-        *den += 1.5 * cv;
-        *num += cv * (2.0 * hk[c1] - 0.5 * hk[c2]);
+    case ST_INT: /* faces: h_c + rc (h_c - h_1) and h_1 + ru (h_1 - h_2) */
+        *den += (1.0 + rc) * cv;
+        *num += cv * ((1.0 + rc + ru) * hk[c1] - ru * hk[c2]);
         break;
-    case ST_NEAR: /* faces: 1.5 h_c - 0.5 h_1 and h_1 */
-        *den += 1.5 * cv;
-        *num += 1.5 * cv * hk[c1];
+    case ST_NEAR: /* faces: h_c + rc (h_c - h_1) and h_1 */
+        *den += (1.0 + rc) * cv;
+        *num += (1.0 + rc) * cv * hk[c1];
         break;
     case ST_WALL: /* faces: h_c and the wall value */
         *den += cv;
@@ -231,7 +237,7 @@ static void sweep_velocity(const si_ctx *s, int k)
     const int nx = s->nx, ny = s->ny, nc = s->nc;
     const double xi = s->xi[k], eta = s->eta[k];
     const double q = xi * xi + eta * eta;
-    const double cx = fabs(xi) / s->dx, cy = fabs(eta) / s->dx;
+    const double cx = fabs(xi) / s->dx;
     const int dxs = xi > 0 ? DIR_W : DIR_E;
     const int dys = eta > 0 ? DIR_S : DIR_N;
     const int sx = xi > 0 ? -1 : 1; /* step towards the upwind side */
@@ -249,10 +255,16 @@ static void sweep_velocity(const si_ctx *s, int k)
             double den = s->dl[c];
             upwind_axis(s, hk, s->codes[4 * c + dxs], c,
                         y * nx + wrap(x + sx, nx), y * nx + wrap(x + 2 * sx, nx),
-                        dxs, k, cx, &den, &num);
+                        dxs, k, cx, 0.5, 0.5, &den, &num);
+            const int y1 = wrap(y + sy, ny), y2 = wrap(y + 2 * sy, ny);
+            double cy = fabs(eta) / s->dx, rc = 0.5, ru = 0.5;
+            if (s->dy) {
+                cy = fabs(eta) / s->dy[y];
+                rc = s->dy[y] / (s->dy[y] + s->dy[y1]);
+                ru = s->dy[y1] / (s->dy[y1] + s->dy[y2]);
+            }
             upwind_axis(s, hk, s->codes[4 * c + dys], c,
-                        wrap(y + sy, ny) * nx + x, wrap(y + 2 * sy, ny) * nx + x,
-                        dys, k, cy, &den, &num);
+                        y1 * nx + x, y2 * nx + x, dys, k, cy, rc, ru, &den, &num);
             hk[c] = num / den;
         }
     }
@@ -260,6 +272,9 @@ static void sweep_velocity(const si_ctx *s, int k)
 
 /* Source iteration (Eq. iteration) to the stop rule.
  *   delta: 1 value or one per cell (ny*nx); alpha in (0,1].
+ *   dy: ny row heights in units of H (nonuniform spacing across the
+ *   channel), or NULL for rows of height 1/cells_per_H; cells_per_H always
+ *   sets the x spacing.
  *   drive: factor of the pressure-gradient source xi (1: Poiseuille flow of
  *   Sec. III, 0: Couette flow of Sec. II); u_bottom, u_top: x velocities of
  *   the outer walls (walled channels only; Eq. (diffuse1) with U0/v_m = 1
@@ -272,7 +287,7 @@ static void sweep_velocity(const si_ctx *s, int k)
  * Returns 0 when the stop rule was met, 1 when max_iter was exhausted,
  * negative on bad input. */
 int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
-                    double cells_per_H, int nv, const double *delta,
+                    double cells_per_H, const double *dy, int nv, const double *delta,
                     int delta_is_field, double alpha, double drive,
                     double u_bottom, double u_top, double tol, long max_iter,
                     double *rho, double *u1, double *u2, double *tau,
@@ -284,6 +299,10 @@ int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
         !isfinite(u_bottom) || !isfinite(u_top) ||
         (periodic_y && (u_bottom != 0.0 || u_top != 0.0)))
         return -2;
+    if (dy)
+        for (int y = 0; y < ny; ++y)
+            if (!(dy[y] > 0 && isfinite(dy[y])))
+                return -2;
     const int K = nv * nv, nc = nx * ny;
     double *v = malloc(sizeof(double) * nv), *w1 = malloc(sizeof(double) * nv);
     double *xi = malloc(sizeof(double) * K), *eta = malloc(sizeof(double) * K);
@@ -319,7 +338,7 @@ int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
         return -3;
     si_ctx s = {nx, ny, nv, K, nc, periodic_y, 1.0 / cells_per_H, alpha, drive,
                 {u_bottom, u_top}, xi, eta, W,
-                solid, codes, dl, a, a + nc, a + 2 * nc, a + 3 * nc,
+                solid, codes, dl, dy, a, a + nc, a + 2 * nc, a + 3 * nc,
                 rho_w, wall_slot, hinc, h};
 
     double eps = INFINITY, eps_prev = -1.0;
@@ -360,10 +379,15 @@ int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
                     if (vn <= 0) /* only velocities moving into this wall */
                         continue;
                     double hc = h[(size_t)k * nc + c], hf;
-                    if (codes[4 * c + od] == ST_WALL)
+                    if (codes[4 * c + od] == ST_WALL) {
                         hf = hc;
-                    else
+                    } else if (dy && d >= 2) {
+                        /* face value extrapolated across a row of height dy[y] */
+                        double r = dy[y] / (dy[y] + dy[nb / nx]);
+                        hf = (1.0 + r) * hc - r * h[(size_t)k * nc + nb];
+                    } else {
                         hf = 1.5 * hc - 0.5 * h[(size_t)k * nc + nb];
+                    }
                     hinc_new[((size_t)wall_slot[c] * 4 + d) * K + k] = hf;
                     num += W[k] * vn * hf;
                 }
@@ -439,7 +463,7 @@ int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
     for (int c = 0; c < nc; ++c)
         if (!solid[c]) {
             rmean += mom[c];
-            Qs += mom[nc + c];
+            Qs += dy ? mom[nc + c] * dy[c / nx] : mom[nc + c];
             ++nf;
         }
     rmean /= nf;
@@ -460,7 +484,8 @@ int oracle_si_solve(int nx, int ny, const uint8_t *solid, int periodic_y,
         }
     }
     if (info_out) {
-        info_out[0] = Qs / (cells_per_H * nx); /* Q = (1/L) * sum u1 * dA, L = nx*dx */
+        /* Q = (1/L) * sum u1 * dA, L = nx * dx, dA = dx * dy */
+        info_out[0] = dy ? Qs / nx : Qs / (cells_per_H * nx);
         info_out[1] = (double)it;
         info_out[2] = eps;
     }
