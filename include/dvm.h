@@ -154,6 +154,20 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg,
 int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny,
                      const uint8_t *solid, int periodic_y, double cells_per_H);
 
+/* Rows of unequal height across the channel (the nonuniform spacing of
+ * Sec. II.A, e.g. fine rows in a rough band): dy[ny] heights of the rows of
+ * instance `instance` in units of H, bottom row first; NULL restores rows
+ * of height 1 / cells_per_H.  cells_per_H keeps setting the x spacing.
+ * Along y the upwind face value becomes h_u + r (h_u - h_uu) with
+ * r = dy_u / (dy_u + dy_uu) (the paper's second-order difference on a
+ * uniform grid), the flux difference is divided by the cell's own height,
+ * and Q weighs u1 by dx dy.  Call after dvm_set_geometry (which resets the
+ * heights); discards the instance's solution.  Such instances take the
+ * per-cell path of the sweep; dvm_grad rejects them (DVM_EINVAL).
+ * DVM_EINVAL for a non-finite or non-positive height, DVM_ESTATE before
+ * dvm_set_geometry. */
+int dvm_set_row_heights(dvm_ctx *ctx, int instance, const double *dy);
+
 /* What drives the flow of instance `instance` in its next solves: the
  * source pressure_gradient * xi of every fluid cell (a pressure gradient
  * along +x; 1 is the Poiseuille problem of Sec. III) and the x velocities of

@@ -57,6 +57,9 @@ struct HostInst {
     bool has_state = false;   // a converged/partial solution is on the device
     bool force_skew = false;  // DVM_SCHED_AUTO: this geometry needs the skewed order
     bool converged = false;   // the last solve met the stop rule
+    // rows of unequal height across the channel (dvm_set_row_heights), in
+    // units of H; empty: every row 1 / cells_per_H
+    std::vector<double> rows;
 };
 
 template <typename T>
@@ -128,6 +131,7 @@ struct dvm_ctx {
     DevBuf<long long> d_spos;
     DevBuf<FaceRec> d_sface;
     DevBuf<double> d_srec, d_vt, d_dfield, d_part, d_mom, d_u1prev, d_seam, d_wrap, d_aux, d_fb;
+    DevBuf<double> d_rows;         // row heights of every instance, in units of H
     long long sk_total = 0, nfaces = 0;
     DevBuf<SolveState> d_st;
 
@@ -179,7 +183,7 @@ struct dvm_ctx {
             (void)hipEventDestroy(e);
         d_inst.release(); d_items.release(); d_codes.release(); d_srec.release();
         d_scode.release(); d_smap.release(); d_spos.release();
-        d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release();
+        d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release(); d_rows.release();
         d_u1prev.release(); d_seam.release(); d_wrap.release(); d_aux.release();
         d_st.release(); d_sface.release(); d_fb.release();
         d_scode_adj.release(); d_sface_adj.release(); d_face_cell.release(); d_face_side.release();
@@ -436,7 +440,7 @@ static int build_layout(dvm_ctx *c)
     c->kp4 = 4 * c->kq;
     c->idev.assign(c->n_inst, InstDev{});
     c->items.clear();
-    long long cell = 0, seam = 0, wrap = 0, sk = 0, faces = 0;
+    long long cell = 0, seam = 0, wrap = 0, sk = 0, faces = 0, rows_total = 0;
     int maxc = 0;
     for (int i = 0; i < c->n_inst; ++i) {
         HostInst &h = c->inst[i];
@@ -454,6 +458,9 @@ static int build_layout(dvm_ctx *c)
         d.seam_off = seam;
         d.wrap_off = wrap;
         d.sk_off = sk;
+        d.row_off = rows_total;
+        d.nonuniform = h.rows.empty() ? 0 : 1;
+        rows_total += h.ny;
         d.inv_dx = h.cph;
         d.delta = 1.0;
         d.alpha = 1.0;
@@ -524,6 +531,16 @@ static int build_layout(dvm_ctx *c)
     }
     HIPCHK(c->d_aux.alloc(cell));
     HIPCHK(c->d_sface.alloc(sk));
+    {
+        std::vector<double> rows;
+        rows.reserve(rows_total);
+        for (const auto &h : c->inst)
+            for (int y = 0; y < h.ny; ++y)
+                rows.push_back(h.rows.empty() ? 1.0 / h.cph : h.rows[y]);
+        HIPCHK(c->d_rows.alloc(std::max<size_t>(rows.size(), 1)));
+        if (!rows.empty())
+            HIPCHK(hipMemcpy(c->d_rows.p, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     HIPCHK(c->d_part5.alloc((size_t)4 * c->gq * cell));
 
     std::vector<uint8_t> codes(cell);
@@ -691,6 +708,7 @@ static SweepArgs<double> sweep_args(dvm_ctx *c, int force, bool adj = false)
     a.kq = c->kq;
     a.kp4 = c->kp4;
     a.force = force;
+    a.rows = c->d_rows.p;
     return a;
 }
 
@@ -727,6 +745,7 @@ static RecArgs<double> rec_args(dvm_ctx *c, bool adj = false)
     a.c2 = c->c2;
     a.c4 = c->c4;
     a.D = c->D;
+    a.rows = c->d_rows.p;
     return a;
 }
 
@@ -742,7 +761,8 @@ static int solve_mode(const dvm_ctx *c)
 {
     int m = 0;
     for (const auto &h : c->inst) {
-        if (h.field)
+        // rows of unequal height take the per-cell path (diagonal per cell)
+        if (h.field || !h.rows.empty())
             m |= MODE_FIELD;
         if (h.alpha < 1.0)
             m |= MODE_SPEC;
@@ -808,6 +828,7 @@ static SweepArgs<float> sweep_args32(dvm_ctx *c)
     a.kq = c->kq;
     a.kp4 = c->kp4;
     a.force = 0;
+    a.rows = c->d_rows.p;
     return a;
 }
 
@@ -830,6 +851,7 @@ static RecArgs<float> rec_args32(dvm_ctx *c)
     a.c2 = c->c2;
     a.c4 = c->c4;
     a.D = c->D;
+    a.rows = c->d_rows.p;
     return a;
 }
 
@@ -2440,6 +2462,27 @@ int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny, const uint8_t *
     return DVM_OK;
 }
 
+int dvm_set_row_heights(dvm_ctx *ctx, int instance, const double *dy)
+{
+    int rc = check_instance(ctx, instance);
+    if (rc)
+        return rc;
+    HostInst &h = ctx->inst[instance];
+    if (!h.has_geom)
+        return fail(DVM_ESTATE, "dvm_set_geometry has not been called for this instance");
+    std::vector<double> rows;
+    if (dy) {
+        rows.assign(dy, dy + h.ny);
+        for (double v : rows)
+            if (!(std::isfinite(v) && v > 0.0))
+                return fail(DVM_EINVAL, "row heights must be finite and > 0");
+    }
+    h.rows.swap(rows);
+    h.has_state = false;
+    ctx->layout_ok = false;
+    return DVM_OK;
+}
+
 int dvm_set_driving(dvm_ctx *ctx, int instance, double pressure_gradient, double wall_velocity_bottom,
                     double wall_velocity_top)
 {
@@ -2488,8 +2531,9 @@ int dvm_flow_rate(const dvm_ctx *cc, int instance, double *Q, double *k_a)
     double s = 0.0;
     for (size_t k = 0; k < n; ++k)
         if (!h.solid[k])
-            s += mom[k * MOM_STRIDE + MOM_U1];
-    *Q = s / (h.cph * h.nx);   // (1/L) sum u1 dA, L = nx / cells_per_H
+            s += h.rows.empty() ? mom[k * MOM_STRIDE + MOM_U1] : mom[k * MOM_STRIDE + MOM_U1] * h.rows[k / h.nx];
+    // (1/L) sum u1 dA, L = nx / cells_per_H, dA = dx dy
+    *Q = h.rows.empty() ? s / (h.cph * h.nx) : s / h.nx;
     if (k_a)
         *k_a = h.field ? NAN : *Q / h.delta;
     return DVM_OK;
@@ -2612,6 +2656,8 @@ int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha)
     const HostInst &h = ctx->inst[instance];
     if (!ctx->layout_ok || !h.has_state || !h.converged)
         return fail(DVM_ESTATE, "instance has no converged solution (call dvm_solve first)");
+    if (!h.rows.empty())
+        return fail(DVM_EINVAL, "the adjoint is not available on rows of unequal height");
     return grad_instance(ctx, instance, dQ_ddelta, dQ_dalpha);
 }
 

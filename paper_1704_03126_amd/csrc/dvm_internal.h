@@ -63,11 +63,12 @@ struct InstDev {
     int strip_h;     // rows per strip (last strip may be shorter, >= 2)
     int periodic_y;
     int field;       // delta given per cell
-    int pad0;
+    int nonuniform;  // rows of unequal height (row heights at rows + row_off)
     long long cell_off;   // first cell of this instance in the cell arrays
     long long seam_off;   // offset in one parity half of the seam buffer
     long long wrap_off;   // offset in the wrap-state buffer
     long long sk_off;     // first skewed entry: 4 quadrants x nstrips x tp x 64
+    long long row_off;    // first row height of this instance
     double delta;         // uniform delta (field == 0)
     double alpha;         // accommodation coefficient
     double drive;         // coefficient of the pressure-gradient source
@@ -132,6 +133,7 @@ struct SweepArgs {
     int kq;                   // padded velocities per quadrant (= gq * G * V)
     int kp4;                  // 4 * kq
     int force;                // run even for converged instances
+    const double *rows;       // row heights in units of H, [row_off + row]
 };
 
 struct MomArgs {
@@ -159,6 +161,7 @@ struct RecArgs {
     const long long *spos;    // [cell][quadrant] -> skewed entry
     SolveState *st;
     double m0, m2, c2, c4, D;
+    const double *rows;       // row heights in units of H, [row_off + row]
 };
 
 template <typename T>

@@ -294,6 +294,35 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     }
     const double xi0 = (double)cxi[0];
 
+    // per-cell-delta mode also serves rows of unequal height (nonuniform
+    // spacing across the channel): along y the face value extrapolated from
+    // the upwind cell u through uu is h_u + r (h_u - h_uu), r the ratio of
+    // the distances from the face and from uu's centre to u's centre; rc for
+    // this lane's row and its upwind neighbour (yrc), for the neighbour and
+    // the second one (yru), both 1/2 on a uniform grid; ysc = dx / dy scales
+    // |eta|/dx
+    T ysc = T(1), yrc = T(0.5), yru = T(0.5);
+    if constexpr (FIELD && !ADJ) {
+        if (in.nonuniform && lane < hs) {
+            const int row = ypos ? y0 + lane : y0 + hs - 1 - lane;
+            const int stp = ypos ? -1 : 1;
+            int r1 = row + stp, r2 = row + 2 * stp;
+            if (in.periodic_y) {
+                r1 = wrap_mod(r1, in.ny);
+                r2 = wrap_mod(r2, in.ny);
+            } else {
+                // beyond an outer wall the codes use the wall value instead
+                r1 = min(max(r1, 0), in.ny - 1);
+                r2 = min(max(r2, 0), in.ny - 1);
+            }
+            const double *rw = a.rows + in.row_off;
+            const double d0 = rw[row], d1 = rw[r1], d2 = rw[r2];
+            ysc = T(1.0 / (d0 * in.inv_dx));
+            yrc = T(d0 / (d0 + d1));
+            yru = T(d1 / (d1 + d2));
+        }
+    }
+
     // rotating registers: x-upwind values A (prev1), B (prev2), X (free);
     // y-upwind chain H0 (current hs1), H1 (free)
     T rA[V], rB[V], rX[V], rH0[V], rH1[V];
@@ -343,13 +372,20 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             mw = rec[7];
         }
         const T px = lds_lut[xn & 7][0], qx = lds_lut[xn & 7][1];
-        const T py = lds_lut[yn & 7][0], qy = lds_lut[yn & 7][1];
+        T py = lds_lut[yn & 7][0], qy = lds_lut[yn & 7][1];
+        if constexpr (FIELD && !ADJ) {
+            // forward y weights from the row ratios (2, -1/2 and 3/2 when
+            // both are 1/2)
+            const int yp = yn & 7;
+            py = yp == NIB_INT ? T(1) + yrc + yru : yp == NIB_NEAR ? T(1) + yrc : T(0);
+            qy = yp == NIB_INT ? -yru : T(0);
+        }
         const int aox = xn >> 3, aoy = yn >> 3;
         const int ci = solid ? STENCIL_SOLID : 2 * aox + aoy;
         T ax = T(0), ay = T(0), dl = T(0);
         if (FIELD) {
             ax = aox ? T(1) : T(1.5);
-            ay = aoy ? T(1) : T(1.5);
+            ay = aoy ? T(1) : (ADJ ? T(1.5) : T(1) + yrc);
             dl = rec[6];
         }
         const T sbase = XU ? fma(b1, cxi[0], b0) : T(0);
@@ -378,10 +414,11 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             const T S = fma(b3, cqq[v], fma(b2, ceta[v], XU ? sbase : fma(b1, cxi[v], b0)));
             const T ux = fma(px, p1, fma(qx, p2, gxv));
             const T uy = fma(py, hS1, fma(qy, hS2, gyv));
-            const T g = fma(ccx[v], ux, fma(ccy[v], uy, S));
+            const T cyv = FIELD ? ccy[v] * ysc : ccy[v];
+            const T g = fma(ccx[v], ux, fma(cyv, uy, S));
             T rinv;
             if (FIELD) {
-                const T den = fma(ax, ccx[v], fma(ay, ccy[v], dl));
+                const T den = fma(ax, ccx[v], fma(ay, cyv, dl));
                 rinv = (solid || cw[v] == 0.0) ? T(0) : rcp_full(den);
             } else {
                 rinv = lds_rinv[wave * V + v][ci];
@@ -408,7 +445,7 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
                         ADJ ? h : (aox ? h : T(1.5) * h - T(0.5) * p1);
                 if (fr.wry >= 0)
                     fb_wr[(size_t)fr.wry * a.kp4 + kw + v] =
-                        ADJ ? h : (aoy ? h : T(1.5) * h - T(0.5) * hS1);
+                        ADJ ? h : (aoy ? h : (FIELD ? (T(1) + yrc) * h - yrc * hS1 : T(1.5) * h - T(0.5) * hS1));
             }
             if (CKPT && !solid && xa)
                 a.ckpt[((size_t)cbase + cl) * a.kp4 + kw + v] = hd;
@@ -656,8 +693,17 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
                         // neighbour on the opposite side unless that side is
                         // a wall as well (first-order face value)
                         double f = m[hf];
-                        if (co != CODE_WALL && co != CODE_NONE)
-                            f = 1.5 * f - 0.5 * a.mom[nbr(od) * MOM_STRIDE + hf];
+                        if (co != CODE_WALL && co != CODE_NONE) {
+                            // face value extrapolated across the cell through
+                            // its neighbour opposite the face
+                            double r = 0.5;
+                            if (in.nonuniform && d >= SIDE_S) {
+                                const double *rw = a.rows + in.row_off;
+                                const int yo = (int)((nbr(od) - in.cell_off) / in.nx);
+                                r = rw[y] / (rw[y] + rw[yo]);
+                            }
+                            f = (1.0 + r) * f - r * a.mom[nbr(od) * MOM_STRIDE + hf];
+                        }
                         gval = in.alpha * sgn * f / a.D;
                     }
                 } else {

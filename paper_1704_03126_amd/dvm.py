@@ -37,7 +37,7 @@ SCHED_NAMES = {DVM_SCHED_SKEW: "skew", DVM_SCHED_WRAP: "wrap"}
 EXPORTED = ("dvm_create", "dvm_set_geometry", "dvm_solve", "dvm_solve_warm",
             "dvm_flow_rate", "dvm_get_moments", "dvm_grad", "dvm_destroy",
             "dvm_last_error", "dvm_version", "dvm_profile", "dvm_launch_shape",
-            "dvm_permeability", "dvm_set_driving")
+            "dvm_permeability", "dvm_set_driving", "dvm_set_row_heights")
 
 
 class DVMError(RuntimeError):
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(ctypes.c_double)]
     IP = ctypes.POINTER(ctypes.c_int)
     lib.dvm_launch_shape.argtypes = [P, IP, IP, IP, IP]
+    lib.dvm_set_row_heights.argtypes = [P, ctypes.c_int, P]
     lib.dvm_set_driving.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.dvm_permeability.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P]
     lib.dvm_destroy.argtypes = [P]
@@ -213,6 +214,19 @@ class Solver:
                          STATUS_NAMES.get(i.status, str(i.status)),
                          SCHED_NAMES.get(i.schedule, str(i.schedule))) for i in infos]
         return out if instance < 0 else out[0]
+
+    def set_row_heights(self, instance: int, dy=None):
+        """Rows of unequal height (units of H, bottom row first); None:
+        uniform rows of 1 / cells_per_H."""
+        if dy is None:
+            _check(self._lib.dvm_set_row_heights(self._h, instance, None))
+            return
+        ny, _ = self.shapes[instance]
+        d = np.ascontiguousarray(dy, dtype=np.float64).ravel()
+        if d.shape != (ny,):
+            raise ValueError(f"need {ny} row heights")
+        self._keep = getattr(self, "_keep", [])
+        _check(self._lib.dvm_set_row_heights(self._h, instance, _ptr(d)))
 
     def set_driving(self, instance: int, pressure_gradient: float = 1.0, wall_velocity=(0.0, 0.0)):
         """Source of the flow: pressure-gradient factor (1: Poiseuille) and the

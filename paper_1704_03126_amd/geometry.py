@@ -120,6 +120,32 @@ def fractal_couette_channel(cells_per_H: int, aspect: int = 5, D: float = 1.5,
                     meta={"A": float(A), "n_max": n_max, "rows_below": nb, "profile": r})
 
 
+def graded_fractal_couette_channel(nx_per_H: int = 64, n_band: int = 60, n_rest: int = 100,
+                                    aspect: int = 5, D: float = 1.5, eps: float = 0.02,
+                                    gamma: float = 1.5, n1: int = -4) -> Geometry:
+    """The channel of fractal_couette_channel on rows of unequal height, the
+    kind of grid Sec. II.A describes: n_band rows of equal height across the
+    rough band (from the deepest valley to the highest peak of r) and n_rest
+    rows of equal height from there to the top plate at x2 = H; nx_per_H
+    columns per H along the flow.  ``meta["dy"]`` holds the row heights in
+    units of H (bottom row first) for dvm_set_row_heights."""
+    nx = int(aspect * nx_per_H)
+    n_max = int(np.floor(np.log(nx_per_H / 2.0) / np.log(gamma)))
+    xc = (np.arange(nx) + 0.5) / nx_per_H
+    unit = wm_profile(xc, 1.0, D, gamma, n1, n_max)
+    A = eps / np.sqrt(np.mean(unit ** 2))
+    r = A * unit
+    lo, hi = float(r.min()), float(r.max())
+    edges = np.concatenate([np.linspace(lo, hi, n_band + 1), np.linspace(hi, 1.0, n_rest + 1)[1:]])
+    dy = np.diff(edges)
+    yc = 0.5 * (edges[1:] + edges[:-1])
+    m = (yc[:, None] < r[None, :]).astype(np.uint8)
+    return Geometry(m, periodic_y=False, cells_per_H=float(nx_per_H),
+                    name=f"wm_couette_graded_{nx}x{n_band + n_rest}_D{D}_eps{eps}",
+                    porosity=float((m == 0).mean()),
+                    meta={"A": float(A), "n_max": n_max, "profile": r, "dy": dy, "edges": edges})
+
+
 def component_labels(mask: np.ndarray, periodic_y: bool):
     """Label 4-connected fluid components on the (x-periodic) grid.
 

@@ -145,6 +145,24 @@ def test_driving_validation(lib):
         lib.dvm_destroy(h)
 
 
+def test_row_heights_validation(lib):
+    rc, h = _ctx(lib, n=1)
+    try:
+        dy = np.full(16, 1 / 16)
+        dp = dy.ctypes.data_as(ctypes.c_void_p)
+        assert lib.dvm_set_row_heights(h, 0, dp) == dvm.DVM_ESTATE      # no geometry yet
+        assert _set(lib, h, 0, plane_channel(16).mask) == 0
+        assert lib.dvm_set_row_heights(h, 1, dp) == dvm.DVM_EINVAL
+        for bad in (0.0, -0.1, np.nan, np.inf):
+            b = dy.copy()
+            b[5] = bad
+            assert lib.dvm_set_row_heights(h, 0, b.ctypes.data_as(ctypes.c_void_p)) == dvm.DVM_EINVAL
+        assert lib.dvm_set_row_heights(h, 0, dp) == 0
+        assert lib.dvm_set_row_heights(h, 0, None) == 0
+    finally:
+        lib.dvm_destroy(h)
+
+
 def test_python_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(ImportError):
         dvm.load_library.__wrapped__ if hasattr(dvm.load_library, "__wrapped__") else None
