@@ -260,21 +260,24 @@ def bench_batch(args, torch, dvm):
 
 def bench_couette(args, torch, dvm):
     """Couette flow of Sec. II: the fractal (D = 1.5, eps = 2 %) rough channel
-    of aspect ratio 5 at 64 cells per H and the smooth channel, top plate
-    sliding at U0/v_m = 1, 32 x 32 velocities, Kn 0.03-10; one step
-    = every Kn for both channels, solved to tol 1e-8 (warm starts along the
-    Kn list).  Reports Q_r, Q_s and Q* = Q_r / Q_s per Kn."""
-    from paper_1704_03126_amd.geometry import fractal_couette_channel, plane_channel
+    of aspect ratio 5 on graded rows (60 across the rough band, 100 above it,
+    64 columns per H) and the smooth channel, top plate sliding at
+    U0/v_m = 1, 32 x 32 velocities, Kn 0.03-10; one step = every Kn for both
+    channels, solved to tol 1e-8 (warm starts along the Kn list).  Reports
+    Q_r, Q_s and Q* = Q_r / Q_s per Kn."""
+    from paper_1704_03126_amd.geometry import graded_fractal_couette_channel, plane_channel
     nv = 32
     kns = [0.03, 0.1, 0.3, 1.0, 3.0, 10.0]
     deltas = [float(np.sqrt(np.pi) / (2 * kn)) for kn in kns]
-    rough = fractal_couette_channel(64, aspect=5, D=1.5, eps=0.02)
+    rough = graded_fractal_couette_channel(64, n_band=60, n_rest=100, aspect=5, D=1.5, eps=0.02)
     smooth = plane_channel(64, 1)
     solvers = []
     for g in (rough, smooth):
         s = dvm.Solver(nv, 1, tol=TOL, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
                        else dvm.DVM_FP64)
         s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        if "dy" in g.meta:
+            s.set_row_heights(0, g.meta["dy"])
         s.set_driving(0, 0.0, (0.0, 1.0))
         solvers.append((s, g))
 
@@ -302,7 +305,7 @@ def bench_couette(args, torch, dvm):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
-           "config": {"workload": "couette_wm_D1.5_eps0.02_aspect5_64perH_nv32",
+           "config": {"workload": "couette_wm_D1.5_eps0.02_aspect5_graded60+100rows_64perH_nv32",
                       "rough_cells": [rough.ny, rough.nx], "Kn": kns, "tol": TOL,
                       "precision": args.precision, "parallelism": "single_gpu"},
            "Q_rough": [float(q) for q in qr], "Q_smooth": [float(q) for q in qs],
