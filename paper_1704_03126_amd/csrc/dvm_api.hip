@@ -953,10 +953,9 @@ static int enqueue_block(dvm_ctx *c, int iters, int kind)
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
                      const std::vector<long long> &prior);
 
-// Replay blocks of iterations until no instance of [i0, i1) is active.
-// With stall detection (DVM_ACCEL_AUTO) an instance whose relative change of
-// u1 has not dropped by 5% over the last 64 iterations is stopped and flagged
-// in stalled[] (its state is that of a completed iteration).
+// Replay blocks of iterations until no instance of [i0, i1) is active.  A
+// stalled instance is stopped and flagged in stalled[] (its state is that of
+// a completed iteration).
 // Stall test (when `stalled` is given), over the last 64 iterations: an
 // instance whose relative change has not dropped by 5% while max |u1| grew
 // by more than 10% runs away instead of creeping towards the fixed point
@@ -1205,7 +1204,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                      const std::vector<long long> &prior)
 {
     const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 64;
-    const int mode = solve_mode(c) | (adj ? MODE_ADJ : 0);
+    const int mode = solve_mode(c) | (adj ? MODE_ADJ : xu_flag(c, c->V));
     SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
     StateBufs sb;
     sb.b[0] = adj ? c->d_mom_adj.p : c->d_mom.p;
@@ -1294,10 +1293,12 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         HIPCHK(launch_moments(mom_args(c, adj), c->max_cells, c->n_inst, c->stream));
         return DVM_OK;
     };
-    // dots of w against V_0..V_{nv-1} (and |w|^2) summed per slot into out[slot][.]
-    auto dots = [&](const double *w, int nv, bool norm, double *out) -> int {
+    // dots of w against V_0..V_{nv-1} (and |w|^2) summed per slot into
+    // out[slot][.]; with skip, slots whose first pass (skip's coefficients)
+    // kept |w| above 1/sqrt(2) of its length get zero dots
+    auto dots = [&](const double *w, int nv, bool norm, double *out, const double *skip = nullptr) -> int {
         const int nchl = (int)chunks.size();
-        HIPCHK(launch_vdots(kw.ch.p, nchl, w, kw.V.p, n, nv, norm ? 1 : 0, kw.part.p, c->stream));
+        HIPCHK(launch_vdots(kw.ch.p, nchl, w, kw.V.p, n, nv, norm ? 1 : 0, kw.part.p, skip, cst, c->stream));
         HIPCHK(launch_vsum(kw.c0.p, kw.nc.p, ns, kw.part.p, nchl, nv + (norm ? 1 : 0), out, cst, c->stream));
         return DVM_OK;
     };
@@ -1396,11 +1397,13 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             if ((rc = sweep_once(true, false)))
                 return rc;
             HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, Vj, c->stream));
-            if ((rc = dots(kw.w.p, j + 1, false, kw.c1.p)))
+            // classical Gram-Schmidt; the second pass only where the first
+            // one cancelled more than half of |w|^2
+            if ((rc = dots(kw.w.p, j + 1, true, kw.c1.p)))
                 return rc;
             HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c1.p, cst, nullptr,
                                   c->stream));
-            if ((rc = dots(kw.w.p, j + 1, true, kw.c2.p)))
+            if ((rc = dots(kw.w.p, j + 1, true, kw.c2.p, kw.c1.p)))
                 return rc;
             HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c2.p, cst,
                                   kw.V.p + (size_t)(j + 1) * n, c->stream));

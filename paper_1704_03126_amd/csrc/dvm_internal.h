@@ -223,9 +223,12 @@ enum { VCHUNK = 4096 };
 hipError_t launch_gather(const VSeg *seg, int nseg, StateBufs b, double *vec, const double *sub, hipStream_t s);
 // buf[buf_off..] = vec[vec_off..]
 hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const double *vec, hipStream_t s);
-// part[j][chunk] = <w, V_j> over the chunk, j < nvec; row nvec: <w, w> if with_norm
+// part[j][chunk] = <w, V_j> over the chunk, j < nvec; row nvec: <w, w> if with_norm.
+// skipc (or nullptr): per-slot coefficients [slot][cst] of a first projection
+// pass with |w|^2 before it in row nvec; slots where that pass removed at most
+// half of |w|^2 get zero in rows j < nvec (no second pass needed)
 hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const double *V, long long ldv, int nvec,
-                        int with_norm, double *part, hipStream_t s);
+                        int with_norm, double *part, const double *skipc, int cst, hipStream_t s);
 // out[slot][j] = sum of part[j][chunk] over the slot's chunks (fixed order)
 hipError_t launch_vsum(const int *slot_chunk0, const int *slot_nchunk, int nslots, const double *part, int nch,
                        int nrows, double *out, int ostride, hipStream_t s);

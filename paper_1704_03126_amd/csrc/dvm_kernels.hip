@@ -649,7 +649,7 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
             const double dl = in.field ? a.delta_field[cg] : in.delta;
             T rec[8];
             rec[0] = T(dl * (r / a.m0 - t * a.c2));
-            // drive: unit pressure gradient along x (forward); the adjoint
+            // drive: the pressure-gradient factor of the instance (forward); the adjoint
             // is driven by -dQ/dh / W = -(dx / nx) xi
             const double drive = a.homog ? 0.0 : a.adjoint ? -1.0 / (in.inv_dx * (double)in.nx) : in.drive;
             rec[1] = T(dl * (u1 / a.m2) + drive);

@@ -44,34 +44,85 @@ __device__ __forceinline__ double block_sum256(double v, double *red)
     return red[0];
 }
 
-// grid (chunks, nvec + with_norm)
+// Grid (chunks, row groups of VROWS): a block holds its chunk of w in
+// registers and forms the dots of up to VROWS rows at once (w against
+// V_0..V_{nvec-1}, then |w|^2 if asked in row nvec), so w is read once per
+// row group and the rows' loads overlap.  With skipc (the slot's
+// coefficients of a first projection pass, |w|^2 before it in row nvec) a
+// slot whose first pass removed at most half of |w|^2 needs no second pass
+// (the Kahan-Parlett "twice is enough" test): its dot rows are written as
+// zero without reading V.  Fixed-order reductions: wave butterflies, then the
+// four waves in order.
+constexpr int VROWS = 8;
+constexpr int VPER = VCHUNK / 256;
+
 __global__ void __launch_bounds__(256) k_vdots(const VChunk *ch, const double *w, const double *V, long long ldv,
-                                               int nvec, double *part, int nch)
+                                               int nvec, int with_norm, double *part, int nch,
+                                               const double *skipc, int cst)
 {
-    __shared__ double red[256];
+    __shared__ double red[4][VROWS];
     const VChunk c = ch[blockIdx.x];
-    const int j = blockIdx.y;
-    const double *v = j < nvec ? V + (size_t)j * ldv : w;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < c.len; i += 256)
-        s = fma(w[c.start + i], v[c.start + i], s);
-    s = block_sum256(s, red);
-    if (threadIdx.x == 0)
-        part[(size_t)j * nch + blockIdx.x] = s;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r0 = blockIdx.y * VROWS;
+    const int nrows = nvec + (with_norm ? 1 : 0);
+    bool skip = false;
+    if (skipc) {
+        const double *cf = skipc + (size_t)c.slot * cst;
+        double s = 0.0;
+        for (int j = 0; j < nvec; ++j)
+            s = fma(cf[j], cf[j], s);
+        skip = s <= 0.5 * cf[nvec];
+    }
+    double acc[VROWS];
+#pragma unroll
+    for (int rr = 0; rr < VROWS; ++rr)
+        acc[rr] = 0.0;
+#pragma unroll 4
+    for (int e = 0; e < VPER; ++e) {
+        const int i = tid + 256 * e;
+        if (i >= c.len)
+            break;
+        const double wi = w[c.start + i];
+#pragma unroll
+        for (int rr = 0; rr < VROWS; ++rr) {
+            const int r = r0 + rr;
+            if (r < nvec) {
+                if (!skip)
+                    acc[rr] = fma(wi, V[(size_t)r * ldv + c.start + i], acc[rr]);
+            } else if (r < nrows) {
+                acc[rr] = fma(wi, wi, acc[rr]);
+            }
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < VROWS; ++rr) {
+        double s = acc[rr];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            s += __shfl_xor(s, o);
+        if (lane == 0)
+            red[wv][rr] = s;
+    }
+    __syncthreads();
+    if (tid < VROWS && r0 + tid < nrows)
+        part[(size_t)(r0 + tid) * nch + blockIdx.x] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
 }
 
-// one block per slot, one thread per row
-__global__ void k_vsum(const int *slot_chunk0, const int *slot_nchunk, const double *part, int nch, int nrows,
-                       double *out, int ostride)
+// grid (slots, rows): 256 threads sum the slot's chunk partials of one row
+// (strided, then a fixed-order tree)
+__global__ void __launch_bounds__(256) k_vsum(const int *slot_chunk0, const int *slot_nchunk, const double *part,
+                                              int nch, double *out, int ostride)
 {
-    const int slot = blockIdx.x;
-    for (int j = threadIdx.x; j < nrows; j += blockDim.x) {
-        const double *p = part + (size_t)j * nch + slot_chunk0[slot];
-        double s = 0.0;
-        for (int c = 0; c < slot_nchunk[slot]; ++c)
-            s += p[c];
+    __shared__ double red[256];
+    const int slot = blockIdx.x, j = blockIdx.y;
+    const double *p = part + (size_t)j * nch + slot_chunk0[slot];
+    const int nc = slot_nchunk[slot];
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nc; c += 256)
+        s += p[c];
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0)
         out[(size_t)slot * ostride + j] = s;
-    }
 }
 
 __global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, const double *V, long long ldv,
@@ -89,8 +140,11 @@ __global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, co
     for (int i = threadIdx.x; i < c.len; i += 256) {
         const size_t e = c.start + i;
         double acc = w[e];
-        for (int j = 0; j < nvec; ++j)
-            acc = fma(-cf[j], V[(size_t)j * ldv + e], acc);
+        for (int j = 0; j < nvec; ++j) {
+            const double cj = cf[j];
+            if (cj != 0.0)               // rows a skipped second pass left at zero
+                acc = fma(-cj, V[(size_t)j * ldv + e], acc);
+        }
         w[e] = acc;
         if (vout)
             vout[e] = acc * inv;
@@ -171,17 +225,22 @@ hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const double *
 }
 
 hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const double *V, long long ldv, int nvec,
-                        int with_norm, double *part, hipStream_t s)
+                        int with_norm, double *part, const double *skipc, int cst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vdots, dim3(nch, nvec + (with_norm ? 1 : 0)), dim3(256), 0, s, ch, w, V, ldv, nvec,
-                       part, nch);
+    const int nrows = nvec + (with_norm ? 1 : 0);
+    if (nrows == 0 || nch == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_vdots, dim3(nch, (nrows + VROWS - 1) / VROWS), dim3(256), 0, s, ch, w, V, ldv, nvec,
+                       with_norm, part, nch, skipc, cst);
     return hipGetLastError();
 }
 
 hipError_t launch_vsum(const int *slot_chunk0, const int *slot_nchunk, int nslots, const double *part, int nch,
                        int nrows, double *out, int ostride, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vsum, dim3(nslots), dim3(64), 0, s, slot_chunk0, slot_nchunk, part, nch, nrows, out,
+    if (nslots == 0 || nrows == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_vsum, dim3(nslots, nrows), dim3(256), 0, s, slot_chunk0, slot_nchunk, part, nch, out,
                        ostride);
     return hipGetLastError();
 }
