@@ -163,7 +163,7 @@ int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny,
  * uniform grid), the flux difference is divided by the cell's own height,
  * and Q weighs u1 by dx dy.  Call after dvm_set_geometry (which resets the
  * heights); discards the instance's solution.  Such instances take the
- * per-cell path of the sweep; dvm_grad rejects them (DVM_EINVAL).
+ * per-cell path of the sweep; dvm_grad transposes the same weights.
  * DVM_EINVAL for a non-finite or non-positive height, DVM_ESTATE before
  * dvm_set_geometry. */
 int dvm_set_row_heights(dvm_ctx *ctx, int instance, const double *dy);

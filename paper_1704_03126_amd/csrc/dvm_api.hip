@@ -569,7 +569,7 @@ static int build_layout(dvm_ctx *c)
     // Per entry: the fluid cell (-1 for none or solid), the x / y stencil
     // nibbles of the forward and the adjoint problem, and the wall faces each
     // problem reads and writes.
-    const FaceRec none{-1, -1, -1, -1, 0.f, 0.f, 0.f, 0.f};
+    const FaceRec none{-1, -1, -1, -1, 0.0, 0.0};
     std::vector<uint8_t> scode(sk, NIB_ZERO * 17), scode_adj(sk, NIB_ZERO * 17);
     std::vector<int> smap(sk, -1);
     std::vector<long long> spos(cell * 4, -1);
@@ -629,21 +629,33 @@ static int build_layout(dvm_ctx *c)
                         fr.rdy = cyu == CODE_WALL ? gface(cl, dys) : -1;
                         fr.wrx = cxd == CODE_WALL ? gface(cl, dxd) : -1;
                         fr.wry = cyd == CODE_WALL ? gface(cl, dyd) : -1;
-                        fr.kx = fr.ky = 1.f;
+                        fr.kx = fr.ky = 1.0;
                         // adjoint: the upwind wall face of the cell (weight
                         // 1.5, or 1 with a wall on the far side too) or of its
                         // upwind neighbour (weight -0.5)
                         FaceRec &fa = sface_adj[e];
-                        auto adj_face = [&](int up, int down, int side, int &rd, float &k) {
+                        // (rows of unequal height, y faces: 1 + r and
+                        // -r dy_c / dy_n, r the face-extrapolation ratio)
+                        auto adj_face = [&](int up, int down, int side, int &rd, double &k) {
                             rd = -1;
-                            k = 0.f;
+                            k = 0.0;
+                            const bool nu = !h.rows.empty() && side >= SIDE_S;
+                            const double dyc = nu ? h.rows[cl / h.nx] : 0.0;
                             if (up == CODE_WALL) {
                                 rd = gface(cl, side);
-                                k = (down == CODE_WALL || down == CODE_NONE) ? 1.f : 1.5f;
+                                k = (down == CODE_WALL || down == CODE_NONE) ? 1.0 : 1.5;
+                                if (nu && k == 1.5) {
+                                    const double dyo = h.rows[neighbour(h, cl, side ^ 1) / h.nx];
+                                    k = 1.0 + dyc / (dyc + dyo);
+                                }
                             } else if (up == CODE_NEAR) {
                                 const long long u1 = neighbour(h, cl, side);
                                 rd = gface(u1, side);
-                                k = -0.5f;
+                                k = -0.5;
+                                if (nu) {
+                                    const double dyn = h.rows[u1 / h.nx];
+                                    k = -(dyn / (dyn + dyc)) * (dyc / dyn);
+                                }
                             }
                         };
                         adj_face(cxu, cxd, dxs, fa.rdx, fa.kx);
@@ -2323,6 +2335,7 @@ static int grad_instance(dvm_ctx *c, int instance, double *dqdd_out, double *dqd
     g.part5 = c->d_part5.p;
     g.dqdd = c->d_aux.p;
     g.face_cell = c->d_face_cell.p;
+    g.rows = c->d_rows.p;
     g.face_side = c->d_face_side.p;
     g.face_inst = c->d_face_inst.p;
     g.fb_fwd = c->d_fb.p + par_f * fh;
@@ -2659,8 +2672,6 @@ int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha)
     const HostInst &h = ctx->inst[instance];
     if (!ctx->layout_ok || !h.has_state || !h.converged)
         return fail(DVM_ESTATE, "instance has no converged solution (call dvm_solve first)");
-    if (!h.rows.empty())
-        return fail(DVM_EINVAL, "the adjoint is not available on rows of unequal height");
     return grad_instance(ctx, instance, dQ_ddelta, dQ_dalpha);
 }
 

@@ -106,7 +106,7 @@ struct SolveState {
 // cell's own faces on the x / y downstream side that receive values
 struct FaceRec {
     int rdx, rdy, wrx, wry;
-    float kx, ky, pad0, pad1;
+    double kx, ky;
 };
 
 template <typename T>
@@ -190,6 +190,7 @@ struct GradArgs {
     long long ncell;
     int ngroups, kq, kp4, face0, nfaces;
     double m0, m2, c2, c4, D;
+    const double *rows;       // row heights in units of H, [row_off + row]
 };
 hipError_t launch_grad(const GradArgs &a, int instance, int ncells, hipStream_t s);
 template <typename T>

@@ -301,25 +301,42 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
     // this lane's row and its upwind neighbour (yrc), for the neighbour and
     // the second one (yru), both 1/2 on a uniform grid; ysc = dx / dy scales
     // |eta|/dx
+    // The transposed problem (adjoint) couples the cell to the rows of its
+    // two upwind neighbours with their own forward weights, scaled by
+    // dy_c / dy_n (the coupling enters row n divided by dy_n): first
+    // neighbour (1 + rn + rd) dy_c/dy_1 or (1 + rn) dy_c/dy_1, second
+    // -rn dy_c/dy_2, with rn = dy_1/(dy_1 + dy_c), rd = dy_c/(dy_c + dy_d)
+    // (d the downstream neighbour); diagonal 1 + rd (2, 1.5, -1/2 and 1.5
+    // on a uniform grid).
     T ysc = T(1), yrc = T(0.5), yru = T(0.5);
-    if constexpr (FIELD && !ADJ) {
+    T yA1 = T(2), yA15 = T(1.5), yB = T(-0.5), yaD = T(1.5);
+    if constexpr (FIELD) {
         if (in.nonuniform && lane < hs) {
             const int row = ypos ? y0 + lane : y0 + hs - 1 - lane;
             const int stp = ypos ? -1 : 1;
-            int r1 = row + stp, r2 = row + 2 * stp;
+            int r1 = row + stp, r2 = row + 2 * stp, rd = row - stp;
             if (in.periodic_y) {
                 r1 = wrap_mod(r1, in.ny);
                 r2 = wrap_mod(r2, in.ny);
+                rd = wrap_mod(rd, in.ny);
             } else {
                 // beyond an outer wall the codes use the wall value instead
                 r1 = min(max(r1, 0), in.ny - 1);
                 r2 = min(max(r2, 0), in.ny - 1);
+                rd = min(max(rd, 0), in.ny - 1);
             }
             const double *rw = a.rows + in.row_off;
-            const double d0 = rw[row], d1 = rw[r1], d2 = rw[r2];
+            const double d0 = rw[row], d1 = rw[r1], d2 = rw[r2], dd = rw[rd];
             ysc = T(1.0 / (d0 * in.inv_dx));
             yrc = T(d0 / (d0 + d1));
             yru = T(d1 / (d1 + d2));
+            if (ADJ) {
+                const double rn = d1 / (d1 + d0), rdn = d0 / (d0 + dd);
+                yA1 = T((1.0 + rn + rdn) * (d0 / d1));
+                yA15 = T((1.0 + rn) * (d0 / d1));
+                yB = T(-rn * (d0 / d2));
+                yaD = T(1.0 + rdn);
+            }
         }
     }
 
@@ -380,12 +397,18 @@ __global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
             py = yp == NIB_INT ? T(1) + yrc + yru : yp == NIB_NEAR ? T(1) + yrc : T(0);
             qy = yp == NIB_INT ? -yru : T(0);
         }
+        if constexpr (FIELD && ADJ) {
+            // transposed y weights: pair index 2 w1 + w2 of the nibble
+            const int yp = yn & 7, w1i = yp >> 1;
+            py = w1i == 0 ? yA1 : w1i == 1 ? yA15 : T(0);
+            qy = ((yp & 1) == 0 && yp < 6) ? yB : T(0);
+        }
         const int aox = xn >> 3, aoy = yn >> 3;
         const int ci = solid ? STENCIL_SOLID : 2 * aox + aoy;
         T ax = T(0), ay = T(0), dl = T(0);
         if (FIELD) {
             ax = aox ? T(1) : T(1.5);
-            ay = aoy ? T(1) : (ADJ ? T(1.5) : T(1) + yrc);
+            ay = aoy ? T(1) : (ADJ ? yaD : T(1) + yrc);
             dl = rec[6];
         }
         const T sbase = XU ? fma(b1, cxi[0], b0) : T(0);
@@ -651,7 +674,9 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
             rec[0] = T(dl * (r / a.m0 - t * a.c2));
             // drive: the pressure-gradient factor of the instance (forward); the adjoint
             // is driven by -dQ/dh / W = -(dx / nx) xi
-            const double drive = a.homog ? 0.0 : a.adjoint ? -1.0 / (in.inv_dx * (double)in.nx) : in.drive;
+            const double *rw = in.nonuniform ? a.rows + in.row_off : nullptr;
+            const double dyc = rw ? rw[c / in.nx] : 1.0 / in.inv_dx;
+            const double drive = a.homog ? 0.0 : a.adjoint ? -dyc / (double)in.nx : in.drive;
             rec[1] = T(dl * (u1 / a.m2) + drive);
             rec[2] = T(dl * (u2 / a.m2));
             rec[3] = T(dl * t);
@@ -712,11 +737,26 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
                     // returns it to the two cells whose values built the
                     // face value (weights 1.5 / -0.5, or 1 next to a second
                     // wall on the opposite side)
+                    // (rows of unequal height: weights 1 + r / -r of the
+                    // face extrapolation, the neighbour's scaled by
+                    // dy_c / dy_n as it enters the neighbour's row)
                     if (cd == CODE_WALL) {
-                        const double kap = (co == CODE_WALL || co == CODE_NONE) ? 1.0 : 1.5;
+                        double kap = 1.0;
+                        if (co != CODE_WALL && co != CODE_NONE) {
+                            kap = 1.5;
+                            if (rw && d >= SIDE_S) {
+                                const double dyo = rw[(nbr(od) - in.cell_off) / in.nx];
+                                kap = 1.0 + dyc / (dyc + dyo);
+                            }
+                        }
                         gval = kap * in.alpha * sgn * m[hf] / a.D;
                     } else if (cd == CODE_NEAR) {
-                        gval = -0.5 * in.alpha * sgn * a.mom[nbr(d) * MOM_STRIDE + hf] / a.D;
+                        double kn = -0.5;
+                        if (rw && d >= SIDE_S) {
+                            const double dyn = rw[(nbr(d) - in.cell_off) / in.nx];
+                            kn = -(dyn / (dyn + dyc)) * (dyc / dyn);
+                        }
+                        gval = kn * in.alpha * sgn * a.mom[nbr(d) * MOM_STRIDE + hf] / a.D;
                     }
                 }
                 gside[d] = gval;
@@ -845,8 +885,13 @@ __global__ void __launch_bounds__(256) k_grad_face(GradArgs a)
             red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
+    // the face value enters its cell's row with |v_n| / dx (x faces) or
+    // |v_n| / dy of the cell's row (y faces)
+    double inv_h = in.inv_dx;
+    if (!xface && in.nonuniform)
+        inv_h = 1.0 / a.rows[in.row_off + fy];
     if (threadIdx.x == 0)
-        a.dqda_face[f] = red[0] * in.inv_dx;
+        a.dqda_face[f] = red[0] * inv_h;
 }
 
 // ------------------------------------------------------------------ status

@@ -135,3 +135,25 @@ def test_wall_clustering_helps_the_continuum_limit():
     # slip at Kn ~ 0.02 raises Q/delta slightly above 1/12; the first-order
     # wall closure lowers it -- more on the uniform grid
     assert abs(clu * 12 - 1) < abs(uni * 12 - 1)
+
+
+@pytest.mark.parametrize("couette", [False, True])
+def test_dense_adjoint_on_unequal_rows_vs_finite_differences(couette):
+    """The direct solver's adjoint (A^T lambda = dQ/dh with the dy-weighted
+    flow rate) against central differences, on rows of unequal height."""
+    m = rough_channel(8, 10, 2, 4).mask
+    dy = 0.1 * (1 + 0.6 * np.random.default_rng(5).random(10))
+    kw = dict(dy=dy, cells_per_H=8.0)
+    if couette:
+        kw.update(drive=(0.0, 0.0), wall_velocity=(0.0, 1.0))
+    a = dn.adjoint(m, 0.7, 6, alpha=0.8, **kw)
+    e = 1e-6
+    fda = (dn.solve(m, 0.7, 6, alpha=0.8 + e, **kw).Q - dn.solve(m, 0.7, 6, alpha=0.8 - e, **kw).Q) / (2 * e)
+    assert abs(a.dQ_dalpha - fda) <= 1e-7 * abs(fda)
+    base = np.full(m.shape, 0.7)
+    y, x = 5, 6
+    dp, dm_ = base.copy(), base.copy()
+    dp[y, x] += 1e-5
+    dm_[y, x] -= 1e-5
+    fd = (dn.solve(m, dp, 6, alpha=0.8, **kw).Q - dn.solve(m, dm_, 6, alpha=0.8, **kw).Q) / 2e-5
+    assert abs(a.dQ_ddelta[y, x] - fd) <= 1e-6 * abs(fd)
