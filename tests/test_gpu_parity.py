@@ -286,3 +286,19 @@ def test_autotuner_cache(dvm, tmp_path):
     s.solve(0, 1.0)
     s.close()
     assert len(open(cache).read().strip().splitlines()) == 1
+
+
+def test_profile_counts_real_sweeps_and_launch_shape(dvm):
+    """Profile mode times exactly the sweeps that did work (one per
+    iteration), and the launch-shape query reports the tuned shape."""
+    g = rough_channel(64, 32, 6, 32)
+    s = dvm.Solver(12, 1, tol=1e-10, profile=True)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    assert s.launch_shape() == ((0, 0), (0, 0))        # autotuned, not chosen yet
+    info = s.solve(0, 1.0)
+    sweep_ms, n, other_ms = s.profile()
+    (V, G), (V32, G32) = s.launch_shape()
+    s.close()
+    assert info.status == "converged"
+    assert n == info.iters and sweep_ms > 0 and other_ms > 0
+    assert (V, G) in [(4, 8), (8, 4), (4, 4), (2, 8)] and V * G == V32 * G32
