@@ -302,3 +302,16 @@ def test_profile_counts_real_sweeps_and_launch_shape(dvm):
     assert info.status == "converged"
     assert n == info.iters and sweep_ms > 0 and other_ms > 0
     assert (V, G) in [(4, 8), (8, 4), (4, 4), (2, 8)] and V * G == V32 * G32
+
+
+def test_largest_velocity_grid_and_narrow_channel(dvm):
+    """The largest velocity grid (128 x 128 nodes, 16384 velocities) on a
+    narrow rough channel of 5 columns (skewed order: fewer than 8 columns),
+    with Maxwell walls, against the oracle."""
+    g = rough_channel(5, 18, 3, 2)
+    nv = 128
+    ref = oracle.si_solve(g.mask, 0.8, nv, periodic_y=False, cells_per_H=g.cells_per_H,
+                          alpha=0.9, tol=1e-12)
+    Q, _, mom, info = gpu_solve(dvm, g, 0.8, nv, alpha=0.9)
+    assert info.status == "converged" and info.schedule == "skew"
+    assert_parity(Q, mom, ref, qtol=1e-9, utol=1e-9)
