@@ -61,8 +61,9 @@ def parse():
                         "that stop contracting), skew (lags periodic/strip seams only) or "
                         "wrap (fewer steps, not unconditionally stable)")
     p.add_argument("--accel", choices=["auto", "none", "gmres"], default="auto",
-                   help="auto: source iteration, GMRES for an instance that stops contracting; "
-                        "none: plain source iteration; gmres: GMRES on its fixed-point map")
+                   help="auto: source iteration with extrapolation of its dominant mode, GMRES for "
+                        "an instance that stops contracting; none: plain source iteration (the "
+                        "paper's); gmres: GMRES on its fixed-point map")
     p.add_argument("--vel", type=int, default=0)
     p.add_argument("--waves", type=int, default=0)
     p.add_argument("--no-roofline", action="store_true",

@@ -55,8 +55,11 @@ extern "C" {
 #define DVM_SCHED_SKEW 1    /* sweep order with lags at periodic/strip seams only */
 #define DVM_SCHED_WRAP 2    /* wrap-around diagonal: fewer steps on wide grids  */
 
-#define DVM_ACCEL_AUTO 0    /* plain source iteration; GMRES takes over an
-                               instance whose iteration stops contracting     */
+#define DVM_ACCEL_AUTO 0    /* source iteration with extrapolation of the
+                               dominant mode once its contraction rate has
+                               settled (q <= 0.98; not part of the paper's
+                               method); GMRES takes over an instance whose
+                               iteration stops contracting                   */
 #define DVM_ACCEL_NONE 1    /* plain source iteration only (the paper's)      */
 #define DVM_ACCEL_GMRES 2   /* restarted GMRES on the fixed-point map of the
                                iteration from the start                       */

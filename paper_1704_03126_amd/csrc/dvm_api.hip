@@ -965,6 +965,77 @@ static int enqueue_block(dvm_ctx *c, int iters, int kind)
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
                      const std::vector<long long> &prior);
 
+static long long state_segments(const dvm_ctx *c, int i, int pw, long long voff, std::vector<VSeg> *g,
+                                std::vector<VSeg> *sc);
+
+// Vector extrapolation of the dominant mode (DVM_ACCEL_AUTO): where the
+// plain iteration contracts at a settled rate q along one mode, the state
+// x_k and one more iteration x_{k+1} give x_{k+1} + q/(1-q) (x_{k+1} - x_k),
+// which removes that mode (Aitken's process on the whole iteration state:
+// moments, lagged seam and wrap values, wall-face values).  One extra
+// iteration for every instance; the candidates' stop statistics restart.
+static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const std::vector<double> &q,
+                       std::vector<SolveState> &st)
+{
+    const bool adj = kind == 1;
+    StateBufs sb;
+    sb.b[0] = adj ? c->d_mom_adj.p : c->d_mom.p;
+    sb.b[1] = adj ? c->d_seam_adj.p : c->d_seam.p;
+    sb.b[2] = adj ? c->d_wrap_adj.p : c->d_wrap.p;
+    sb.b[3] = adj ? c->d_fb_adj.p : c->d_fb.p;
+    SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
+    KrylovWork &kw = c->kw;
+    std::vector<VSeg> gseg, sseg;
+    std::vector<long long> off(cand.size()), len(cand.size());
+    long long n = 0;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        off[k] = n;
+        len[k] = state_segments(c, cand[k], (int)(st[cand[k]].iter & 1), n, &gseg, &sseg);
+        n += len[k];
+    }
+    if (n == 0)
+        return DVM_OK;
+    if (kw.x.n < (size_t)n)
+        HIPCHK(kw.x.alloc(n));
+    if (kw.w.n < (size_t)n)
+        HIPCHK(kw.w.alloc(n));
+    HIPCHK(kw.gseg.alloc(gseg.size()));
+    HIPCHK(kw.sseg.alloc(sseg.size()));
+    HIPCHK(hipMemcpyAsync(kw.gseg.p, gseg.data(), gseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(kw.sseg.p, sseg.data(), sseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
+    // x_k: the state the next sweep reads; then x_{k+1} = F(x_k)
+    HIPCHK(launch_gather(kw.sseg.p, (int)sseg.size(), sb, kw.x.p, nullptr, c->stream));
+    int rc = enqueue_iteration(c, kind);
+    if (rc)
+        return rc;
+    HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, nullptr, c->stream));
+    HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < cand.size(); ++k) {
+        if (!st[cand[k]].active)
+            continue;       // stopped in the extra iteration: keep F(x_k)
+        const double f = q[k] / (1.0 - q[k]);
+        HIPCHK(launch_axpy(kw.x.p + off[k], kw.w.p + off[k], -1.0, len[k], c->stream));   // x_k - x_{k+1}
+        HIPCHK(launch_axpy(kw.w.p + off[k], kw.x.p + off[k], -f, len[k], c->stream));
+    }
+    HIPCHK(launch_scatter(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, c->stream));
+    // records of the next sweep from the extrapolated moments
+    HIPCHK(launch_record<double>(rec_args(c, adj), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i : cand) {
+        SolveState &s = st[i];
+        if (!s.active)
+            continue;
+        s.maxdiff_bits = s.maxabs_bits = 0ull;
+        s.eps_prev = 0.0;
+        s.npass = 0;
+    }
+    HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DVM_OK;
+}
+
 // Replay blocks of iterations until no instance of [i0, i1) is active.  A
 // stalled instance is stopped and flagged in stalled[] (its state is that of
 // a completed iteration).
@@ -990,6 +1061,13 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
     };
     std::vector<std::vector<Hist>> hist(c->n_inst);
     std::vector<long long> before(c->n_inst);
+    // relative change at block ends since the last extrapolation; an
+    // instance whose relative change, a block after an extrapolation, is
+    // above the one the extrapolation started from is not extrapolated again
+    const bool extrap = c->cfg.accel == DVM_ACCEL_AUTO && kind != 2;
+    std::vector<std::vector<double>> eh(c->n_inst);
+    std::vector<double> eps_at(c->n_inst, -1.0);
+    std::vector<char> no_extrap(c->n_inst, 0);
     for (;;) {
         for (int i = 0; i < c->n_inst; ++i)
             before[i] = st[i].iter;
@@ -1039,6 +1117,41 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
         }
         if (!running)
             return DVM_OK;
+        if (extrap) {
+            // a settled rate: per-iteration contraction over the last two
+            // blocks agreeing to 5% of the gap 1 - q, and q <= 0.98 (the
+            // factor q/(1-q) also multiplies the next mode's error: closer
+            // to 1 it can amplify that mode more than it removes)
+            std::vector<int> cand;
+            std::vector<double> qs;
+            for (int i = i0; i < i1; ++i) {
+                if (!(st[i].active && st[i].iter - iter0[i] < cap) || no_extrap[i])
+                    continue;
+                auto &e = eh[i];
+                e.push_back(st[i].eps);
+                if (eps_at[i] > 0.0 && e.size() == 1 && !(st[i].eps < eps_at[i])) {
+                    no_extrap[i] = 1;
+                    continue;
+                }
+                if (e.size() < 3 || !(st[i].eps > tol) || !(st[i].eps > 1e-13))
+                    continue;
+                const double e0 = e[e.size() - 3], e1 = e[e.size() - 2], e2 = e.back();
+                if (!(e0 > 0.0 && e1 > 0.0 && e2 > 0.0))
+                    continue;
+                const double qa = std::pow(e2 / e1, 1.0 / B), qb = std::pow(e1 / e0, 1.0 / B);
+                if (qa > 0.5 && qa <= 0.98 && std::fabs(qa - qb) <= 0.05 * (1.0 - qa)) {
+                    cand.push_back(i);
+                    qs.push_back(qa);
+                    eps_at[i] = st[i].eps;
+                    e.clear();
+                }
+            }
+            if (!cand.empty()) {
+                rc = extrapolate(c, kind, cand, qs, st);
+                if (rc)
+                    return rc;
+            }
+        }
     }
 }
 

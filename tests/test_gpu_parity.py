@@ -315,3 +315,23 @@ def test_largest_velocity_grid_and_narrow_channel(dvm):
     Q, _, mom, info = gpu_solve(dvm, g, 0.8, nv, alpha=0.9)
     assert info.status == "converged" and info.schedule == "skew"
     assert_parity(Q, mom, ref, qtol=1e-9, utol=1e-9)
+
+
+def test_dominant_mode_extrapolation(dvm):
+    """Default acceleration at a delta where the source iteration settles on
+    one slow mode: fewer sweeps than the plain iteration, the same fixed
+    point (oracle), and no change where the rate never settles below 0.98."""
+    g = rough_channel(64, 32, 6, 32)
+    ref = oracle_solve(g, 10.0, 16)
+    its = {}
+    for acc in (dvm.DVM_ACCEL_NONE, dvm.DVM_ACCEL_AUTO):
+        s = dvm.Solver(16, 1, tol=1e-11, accel=acc)
+        s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        info = s.solve(0, 10.0)
+        Q = s.flow_rate(0)[0]
+        mom = s.moments(0)
+        s.close()
+        assert info.status == "converged"
+        assert_parity(Q, mom, ref, qtol=1e-9, utol=1e-9)
+        its[acc] = info.iters
+    assert its[dvm.DVM_ACCEL_AUTO] < 0.85 * its[dvm.DVM_ACCEL_NONE], its
