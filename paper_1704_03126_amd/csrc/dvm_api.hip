@@ -1011,6 +1011,8 @@ static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const
     HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, nullptr, c->stream));
     HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->cfg.profile && kind == 0 && (rc = collect_profile(c, 1)))
+        return rc;
     for (size_t k = 0; k < cand.size(); ++k) {
         if (!st[cand[k]].active)
             continue;       // stopped in the extra iteration: keep F(x_k)
