@@ -64,6 +64,9 @@ def parse():
                    help="auto: source iteration with extrapolation of its dominant mode, GMRES for "
                         "an instance that stops contracting; none: plain source iteration (the "
                         "paper's); gmres: GMRES on its fixed-point map")
+    p.add_argument("--tol", type=float, default=TOL,
+                   help="stop-rule tolerance of every solve (relative change of u1 and its "
+                        "a-posteriori error bound)")
     p.add_argument("--vel", type=int, default=0)
     p.add_argument("--waves", type=int, default=0)
     p.add_argument("--no-roofline", action="store_true",
@@ -109,7 +112,7 @@ def main():
     sched = {"auto": dvm.DVM_SCHED_AUTO, "skew": dvm.DVM_SCHED_SKEW, "wrap": dvm.DVM_SCHED_WRAP}[args.schedule]
     accel = {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE, "gmres": dvm.DVM_ACCEL_GMRES}[args.accel]
     prec = dvm.DVM_FP32_REFINE if args.precision == "fp32_refine" else dvm.DVM_FP64
-    solver = dvm.Solver(NV, 1, tol=TOL, vel_per_lane=args.vel, waves_per_block=args.waves,
+    solver = dvm.Solver(NV, 1, tol=args.tol, vel_per_lane=args.vel, waves_per_block=args.waves,
                         schedule=sched, accel=accel, precision=prec)
     solver.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
 
@@ -147,7 +150,7 @@ def main():
     if not args.no_roofline:
         # roofline of the sweep: one more step with every sweep bracketed by
         # HIP events on the solver's stream
-        prof = dvm.Solver(NV, 1, tol=TOL, profile=True, vel_per_lane=args.vel,
+        prof = dvm.Solver(NV, 1, tol=args.tol, profile=True, vel_per_lane=args.vel,
                           waves_per_block=args.waves, schedule=sched)
         prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
         prof_sched = set()
@@ -206,18 +209,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
                    "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
-                   "deltas": list(DELTAS), "tol": TOL, "precision": args.precision,
+                   "deltas": list(DELTAS), "tol": args.tol, "precision": args.precision,
                    "schedule": args.schedule, "accel": args.accel, "parallelism": "single_gpu"},
         "iterations_per_delta": all_its[-1],
         "schedule_per_delta": scheds,
         "time_to_solution_s": dict(zip([str(d) for d in DELTAS],
                                        np.mean(np.array(all_tts), axis=0).tolist())),
         "Q": dict(zip([str(d) for d in DELTAS], Qs)),
+        "Q_rel_err_vs_stored_oracle": stored_oracle_error(g, Qs),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     solver.close()
     print(json.dumps(out))
+
+
+def stored_oracle_error(g, Qs):
+    """|Q - Q_oracle| / |Q_oracle| per delta against the stored FP64 oracle
+    results of this geometry (solved to 1e-12 on the CPU and kept as JSON
+    with the tests), or None where none are stored."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        f"rough_channel_{g.nx}x{g.ny}_nv{NV}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = {float(r["delta"]): r["Q"] for r in json.load(f)["results"]}
+    return {str(d): (abs(q - ref[d]) / abs(ref[d]) if d in ref else None) for d, q in zip(DELTAS, Qs)}
 
 
 def bench_batch(args, torch, dvm):
@@ -231,7 +248,7 @@ def bench_batch(args, torch, dvm):
     gs = batch_instances(64)
     deltas = [g.meta["delta"] for g in gs]
     prec = dvm.DVM_FP32_REFINE if args.precision == "fp32_refine" else dvm.DVM_FP64
-    s = dvm.Solver(nv, len(gs), tol=TOL, max_iter=args.batch_iters, vel_per_lane=args.vel or 4,
+    s = dvm.Solver(nv, len(gs), tol=args.tol, max_iter=args.batch_iters, vel_per_lane=args.vel or 4,
                    waves_per_block=args.waves or 8, precision=prec)
     for i, g in enumerate(gs):
         s.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
@@ -274,7 +291,7 @@ def bench_couette(args, torch, dvm):
     smooth = plane_channel(64, 1)
     solvers = []
     for g in (rough, smooth):
-        s = dvm.Solver(nv, 1, tol=TOL, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
+        s = dvm.Solver(nv, 1, tol=args.tol, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
                        else dvm.DVM_FP64)
         s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
         if "dy" in g.meta:
@@ -307,7 +324,7 @@ def bench_couette(args, torch, dvm):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
            "config": {"workload": "couette_wm_D1.5_eps0.02_aspect5_graded60+100rows_64perH_nv32",
-                      "rough_cells": [rough.ny, rough.nx], "Kn": kns, "tol": TOL,
+                      "rough_cells": [rough.ny, rough.nx], "Kn": kns, "tol": args.tol,
                       "precision": args.precision, "parallelism": "single_gpu"},
            "Q_rough": [float(q) for q in qr], "Q_smooth": [float(q) for q in qs],
            "Q_star": [float(a / b) for a, b in zip(qr, qs)],
