@@ -1025,13 +1025,14 @@ static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const
     HIPCHK(launch_record<double>(rec_args(c, adj), c->max_cells, c->n_inst, c->stream));
     HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    for (int i : cand) {
-        SolveState &s = st[i];
+    for (size_t k = 0; k < cand.size(); ++k) {
+        SolveState &s = st[cand[k]];
         if (!s.active)
             continue;
         s.maxdiff_bits = s.maxabs_bits = 0ull;
         s.eps_prev = 0.0;
         s.npass = 0;
+        s.qfloor = std::max(s.qfloor, q[k]);
     }
     HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1847,6 +1848,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
             s.active = 1;
             s.status = STATUS_RUNNING;
             s.npass = 0;
+            s.qfloor = 0.0;
             s.eps_prev = 0.0;
             s.iter0 = s.iter;
             s.maxdiff_bits = s.maxabs_bits = 0ull;
@@ -2242,6 +2244,7 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
             s.status = STATUS_RUNNING;
             s.npass = 0;
             s.eps_prev = 0.0;
+            s.qfloor = 0.0;
             s.maxdiff_bits = s.maxabs_bits = 0ull;
             s.iter0 = s.iter;
             iter0[i] = s.iter;

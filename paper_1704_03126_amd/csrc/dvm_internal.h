@@ -99,6 +99,8 @@ struct SolveState {
     unsigned long long maxdiff_bits, maxabs_bits;
     double tol;           // stop tolerance of this instance (0: the launch's)
     double amax;          // max |u1| of the last iteration
+    double qfloor;        // lower bound on the contraction ratio of the stop
+                          // rule's error estimate (0: the observed ratio)
 };
 
 // face record of a sweep entry (alpha < 1 and the gradient): faces whose

@@ -920,14 +920,17 @@ __global__ void k_status(SolveState *st, int n, double tol, long long max_iter)
     }
     // Sec. II.A stop rule on the relative change of u1, with the a-posteriori
     // bound from the observed contraction, on 3 consecutive iterations; a
-    // change at the round-off floor passes without the bound.
+    // change at the round-off floor passes without the bound.  After an
+    // extrapolation of the dominant mode the ratio is held at least at that
+    // mode's rate: what is left of the mode still contracts at it, while two
+    // successive changes first show the faster modes.
     const double tl = s.tol > 0.0 ? s.tol : tol;
     int pass = 0;
     double est = eps;
     if (eps <= 16.0 * 2.220446049250313e-16) {
         pass = 1;
     } else if (eps <= tl && s.eps_prev > 0.0) {
-        const double rh = eps / s.eps_prev;
+        const double rh = fmax(eps / s.eps_prev, s.qfloor);
         est = rh < 1.0 ? eps * rh / (1.0 - rh) : __builtin_inf();
         pass = rh < 1.0 && est <= tl;
     }

@@ -61,3 +61,27 @@ def test_full_size_against_oracle(dvm, name, precision):
         assert np.max(np.abs(u1 - np.array(r["u1"]))) <= 1e-8, r["delta"]
         assert np.max(np.abs(u2 - np.array(r["u2"]))) <= 1e-8, r["delta"]
     s.close()
+
+
+def test_stop_rule_after_extrapolation(dvm):
+    """Default path (extrapolation of the dominant mode) at tol 1e-6 on the
+    full rough channel at delta 10: the stop rule's bound must still hold the
+    flow rate to 1e-6 of the oracle's, with fewer sweeps than the plain
+    iteration (so an extrapolation took place).  The bound's ratio is held at
+    the extrapolated mode's rate; with the raw ratio of two successive
+    changes this solve stopped 1.2e-6 away."""
+    name = "rough_channel_256x128_nv64"
+    ref = _load(name)
+    r = next(x for x in ref["results"] if x["delta"] == 10.0)
+    g = MAKERS[name]()
+    its = {}
+    for accel in (dvm.DVM_ACCEL_AUTO, dvm.DVM_ACCEL_NONE):
+        s = dvm.Solver(ref["nv"], 1, tol=1e-6, accel=accel)
+        s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        info = s.solve(0, 10.0)
+        assert info.status == "converged", (accel, info)
+        Q, _ = s.flow_rate(0)
+        assert abs(Q - r["Q"]) <= 1e-6 * abs(r["Q"]), (accel, Q, r["Q"])
+        its[accel] = info.iters
+        s.close()
+    assert its[dvm.DVM_ACCEL_AUTO] < its[dvm.DVM_ACCEL_NONE], its
