@@ -1853,9 +1853,17 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
             s.iter0 = s.iter;
             s.maxdiff_bits = s.maxabs_bits = 0ull;
             // relative accuracy this correction needs: the error estimate of
-            // x must drop below tol (with a margin), within what FP32 resolves
-            const double need = std::isfinite(st[d.inst].est) ? 0.3 * tol / st[d.inst].est : 1e-4;
-            s.tol = std::min(1e-4, std::max(need, 1e-5));
+            // x must drop below tol (with a margin), within what FP32
+            // resolves.  Before any contraction has been measured the error
+            // is taken as eps64 q/(1 - q) with q = 0.99 and the correction is
+            // solved to 1e-4 at most (a later FP64 step with the measured
+            // rate asks for another correction if either was optimistic)
+            double est = st[d.inst].est;
+            const bool first = !std::isfinite(est);
+            if (first)
+                est = st[d.inst].eps * 99.0;
+            const double need = est > 0.0 ? 0.3 * tol / est : 1e-4;
+            s.tol = std::min(0.1, std::max(need, first ? 1e-4 : 1e-5));
         }
         if ((rc = upload(c->d_st32.p, st32)))
             return rc;
@@ -1881,11 +1889,14 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
                              s.eps_prev, (int)stalled[d.inst]);
             // contraction of the last FP32 iterations: the stop rule's bound
             // est = eps q / (1 - q) (the status kernel has already replaced
-            // eps_prev by eps)
+            // eps_prev by eps).  Every correction iterates the same operator,
+            // so the slowest rate seen so far is kept: a short, loosely
+            // solved correction can end before its ratio shows the slowest
+            // mode.
+            double qn = 0.9999;
             if (s.status == STATUS_CONVERGED && s.eps > 0.0 && std::isfinite(s.est) && s.est > 0.0)
-                d.q = std::min(s.est / (s.eps + s.est), 0.9999);
-            else
-                d.q = 0.9999;
+                qn = std::min(s.est / (s.eps + s.est), 0.9999);
+            d.q = std::max(d.q, qn);
             if (stalled[d.inst] || s.status == STATUS_DIVERGED) {
                 d.fallback = true;
                 d.live = false;
