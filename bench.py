@@ -49,11 +49,13 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--workload", choices=["rough_channel", "batch64", "couette"], default="rough_channel",
+    p.add_argument("--workload", choices=["rough_channel", "batch64", "couette", "porous"], default="rough_channel",
                    help="rough_channel: the headline workload; batch64: 64 uneven instances "
                         "(sides 64-384, 48 x 48 velocities) in one batched solve, throughput over a "
                         "fixed number of iterations; couette: the Couette flow of the fractal rough "
-                        "channel and the smooth one over Kn 0.03-10 (Q*)")
+                        "channel and the smooth one over Kn 0.03-10 (Q*); porous: the rarefaction "
+                        "sweep of the 512 x 512 porous cell (8 deltas over 0.01-100, warm starts) "
+                        "and its permeability post-processing")
     p.add_argument("--batch-iters", type=int, default=24,
                    help="iterations per timed batched solve (batch64)")
     p.add_argument("--schedule", choices=["auto", "skew", "wrap"], default="auto",
@@ -105,6 +107,8 @@ def main():
         return bench_batch(args, torch, dvm)
     if args.workload == "couette":
         return bench_couette(args, torch, dvm)
+    if args.workload == "porous":
+        return bench_porous(args, torch, dvm)
 
     g = cfg_rough_channel()
     nf = g.n_fluid
@@ -328,6 +332,63 @@ def bench_couette(args, torch, dvm):
                       "precision": args.precision, "parallelism": "single_gpu"},
            "Q_rough": [float(q) for q in qr], "Q_smooth": [float(q) for q in qs],
            "Q_star": [float(a / b) for a, b in zip(qr, qs)],
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
+def bench_porous(args, torch, dvm):
+    """Rarefaction sweep of the periodic porous cell (Sec. III): 512 x 512
+    cells, seeded overlapping discs (radius 0.03-0.08 of the side) to
+    porosity 0.6 with non-percolating pores filled, 64 x 64 velocities,
+    delta log-spaced over [0.01, 100] (8 values), each solve warm-started
+    from the previous one (rarefied end first).  Reports per-delta sweeps,
+    time and Q, and the post-processing: k_inf, H*, Kn*, k_a/k_inf."""
+    from paper_1704_03126_amd.geometry import cfg_porous
+    nv = 64
+    g = cfg_porous()
+    deltas = [float(d) for d in np.logspace(-2, 2, 8)]
+    phi = float(np.mean(g.mask == 0))
+    s = dvm.Solver(nv, 1, tol=args.tol, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
+                   else dvm.DVM_FP64)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+
+    def step():
+        Qs, its, tts = [], [], []
+        for i, d in enumerate(deltas):
+            t = time.perf_counter()
+            info = s.solve(0, d, warm=i > 0)
+            Qs.append(s.flow_rate(0)[0])
+            torch.cuda.synchronize()
+            tts.append(time.perf_counter() - t)
+            if info.status != "converged":
+                raise RuntimeError(f"delta {d}: {info.status}")
+            its.append(info.iters)
+        return Qs, its, tts
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    upd = 0.0
+    for _ in range(args.steps):
+        Qs, its, tts = step()
+        upd += sum(its) * g.n_fluid * nv * nv
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s.close()
+    perm = dvm.permeability(deltas, Qs, phi)
+    out = {"metric": METRIC, "value": upd / elapsed, "unit": "updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+           "config": {"workload": "porous_discs_512x512_phi0.6_seed1003_nv64_delta0.01-100x8",
+                      "nx": g.nx, "ny": g.ny, "fluid_cells": g.n_fluid, "porosity": phi,
+                      "velocities": nv * nv, "deltas": deltas, "tol": args.tol,
+                      "precision": args.precision, "parallelism": "single_gpu"},
+           "iterations_per_delta": its, "time_to_solution_s": tts, "Q": Qs,
+           "k_inf": perm["k_inf"], "H_star": perm["H_star"],
+           "Kn_star": [float(x) for x in perm["Kn_star"]],
+           "ka_over_kinf": [float(x) for x in perm["ka_ratio"]],
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out))
 
