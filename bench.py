@@ -57,7 +57,8 @@ def parse():
                         "sweep of the 512 x 512 porous cell (8 deltas over 0.01-100, warm starts) "
                         "and its permeability post-processing")
     p.add_argument("--batch-iters", type=int, default=24,
-                   help="iterations per timed batched solve (batch64)")
+                   help="iterations per timed batched solve (batch64); 0: every instance "
+                        "to the stop rule")
     p.add_argument("--schedule", choices=["auto", "skew", "wrap"], default="auto",
                    help="sweep order: auto (wrap-around diagonal, skewed order for instances "
                         "that stop contracting), skew (lags periodic/strip seams only) or "
@@ -228,6 +229,14 @@ def main():
     print(json.dumps(out))
 
 
+def solver_options(args, dvm):
+    """Sweep order and acceleration chosen on the command line."""
+    return {"schedule": {"auto": dvm.DVM_SCHED_AUTO, "skew": dvm.DVM_SCHED_SKEW,
+                         "wrap": dvm.DVM_SCHED_WRAP}[args.schedule],
+            "accel": {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE,
+                      "gmres": dvm.DVM_ACCEL_GMRES}[args.accel]}
+
+
 def stored_oracle_error(g, Qs):
     """|Q - Q_oracle| / |Q_oracle| per delta against the stored FP64 oracle
     results of this geometry (solved to 1e-12 on the CPU and kept as JSON
@@ -246,14 +255,17 @@ def bench_batch(args, torch, dvm):
     64-384, delta log-uniform on [0.01, 100]), 48 x 48 velocities, all in one
     batched launch sequence; every timed solve runs a fixed number of
     iterations (instances converge at very different counts, so throughput
-    over a fixed budget is the comparable figure)."""
+    over a fixed budget is the comparable figure), or, with --batch-iters 0,
+    runs every instance to the stop rule (time to solution of the batch)."""
     from paper_1704_03126_amd.geometry import batch_instances
     nv = 48
     gs = batch_instances(64)
     deltas = [g.meta["delta"] for g in gs]
     prec = dvm.DVM_FP32_REFINE if args.precision == "fp32_refine" else dvm.DVM_FP64
-    s = dvm.Solver(nv, len(gs), tol=args.tol, max_iter=args.batch_iters, vel_per_lane=args.vel or 4,
-                   waves_per_block=args.waves or 8, precision=prec)
+    to_conv = args.batch_iters <= 0
+    s = dvm.Solver(nv, len(gs), tol=args.tol, max_iter=100000 if to_conv else args.batch_iters,
+                   vel_per_lane=args.vel or 4, waves_per_block=args.waves or 8, precision=prec,
+                   **solver_options(args, dvm))
     for i, g in enumerate(gs):
         s.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
     nfl = [g.n_fluid for g in gs]
@@ -267,6 +279,7 @@ def bench_batch(args, torch, dvm):
         updates += sum(inf.iters * n for inf, n in zip(infos, nfl)) * nv * nv
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    Qs = [s.flow_rate(i)[0] for i in range(len(gs))] if to_conv else None
     s.close()
     out = {"metric": METRIC, "value": updates / elapsed, "unit": "updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
@@ -274,9 +287,16 @@ def bench_batch(args, torch, dvm):
            "dtype": "f64" if prec == dvm.DVM_FP64 else "f32+f64", "data": "synthetic",
            "config": {"workload": "batch64_uneven_sides64-384_nv48", "instances": len(gs),
                       "cells": int(sum(g.nx * g.ny for g in gs)), "fluid_cells": int(sum(nfl)),
-                      "velocities": nv * nv, "iterations_per_solve": args.batch_iters,
-                      "precision": args.precision, "parallelism": "single_gpu"},
+                      "velocities": nv * nv,
+                      "iterations_per_solve": "to the stop rule" if to_conv else args.batch_iters,
+                      "tol": args.tol if to_conv else None, "precision": args.precision,
+                      "schedule": args.schedule, "accel": args.accel, "parallelism": "single_gpu"},
            "roofline": None, "cpu_baseline": None}
+    if to_conv:
+        out["iterations_per_instance"] = [inf.iters for inf in infos]
+        out["status_per_instance"] = [inf.status for inf in infos]
+        out["delta_per_instance"] = deltas
+        out["Q"] = Qs
     print(json.dumps(out))
 
 
@@ -296,7 +316,7 @@ def bench_couette(args, torch, dvm):
     solvers = []
     for g in (rough, smooth):
         s = dvm.Solver(nv, 1, tol=args.tol, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
-                       else dvm.DVM_FP64)
+                       else dvm.DVM_FP64, **solver_options(args, dvm))
         s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
         if "dy" in g.meta:
             s.set_row_heights(0, g.meta["dy"])
@@ -329,7 +349,8 @@ def bench_couette(args, torch, dvm):
            "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
            "config": {"workload": "couette_wm_D1.5_eps0.02_aspect5_graded60+100rows_64perH_nv32",
                       "rough_cells": [rough.ny, rough.nx], "Kn": kns, "tol": args.tol,
-                      "precision": args.precision, "parallelism": "single_gpu"},
+                      "precision": args.precision, "schedule": args.schedule, "accel": args.accel,
+                      "parallelism": "single_gpu"},
            "Q_rough": [float(q) for q in qr], "Q_smooth": [float(q) for q in qs],
            "Q_star": [float(a / b) for a, b in zip(qr, qs)],
            "roofline": None, "cpu_baseline": None}
@@ -349,7 +370,7 @@ def bench_porous(args, torch, dvm):
     deltas = [float(d) for d in np.logspace(-2, 2, 8)]
     phi = float(np.mean(g.mask == 0))
     s = dvm.Solver(nv, 1, tol=args.tol, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
-                   else dvm.DVM_FP64)
+                   else dvm.DVM_FP64, **solver_options(args, dvm))
     s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
 
     def step():
@@ -384,7 +405,8 @@ def bench_porous(args, torch, dvm):
            "config": {"workload": "porous_discs_512x512_phi0.6_seed1003_nv64_delta0.01-100x8",
                       "nx": g.nx, "ny": g.ny, "fluid_cells": g.n_fluid, "porosity": phi,
                       "velocities": nv * nv, "deltas": deltas, "tol": args.tol,
-                      "precision": args.precision, "parallelism": "single_gpu"},
+                      "precision": args.precision, "schedule": args.schedule, "accel": args.accel,
+                      "parallelism": "single_gpu"},
            "iterations_per_delta": its, "time_to_solution_s": tts, "Q": Qs,
            "k_inf": perm["k_inf"], "H_star": perm["H_star"],
            "Kn_star": [float(x) for x in perm["Kn_star"]],

@@ -59,7 +59,12 @@ extern "C" {
                                dominant mode once its contraction rate has
                                settled (q <= 0.98; not part of the paper's
                                method); GMRES takes over an instance whose
-                               iteration stops contracting                   */
+                               iteration stops contracting, and is tried on
+                               one that contracts slowly (q > 0.98 with over
+                               1000 iterations to go), kept while each cycle
+                               beats 1.5 x the plain rate per second; with
+                               DVM_FP32_REFINE an FP32 correction iteration
+                               slower than q = 0.995 continues in FP64      */
 #define DVM_ACCEL_NONE 1    /* plain source iteration only (the paper's)      */
 #define DVM_ACCEL_GMRES 2   /* restarted GMRES on the fixed-point map of the
                                iteration from the start                       */

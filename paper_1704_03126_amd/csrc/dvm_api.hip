@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -152,6 +153,11 @@ struct dvm_ctx {
     std::vector<long long> sweeps64_done; // of which FP64 sweeps
     std::vector<long long> sweeps_wasted;   // before a restart in the skewed order
     std::vector<long long> sweeps64_wasted; // of which FP64 sweeps
+    // AUTO: a slow plain iteration is handed to GMRES on trial; per instance
+    // the plain contraction per iteration, and the plain wall time per
+    // iteration of the last block
+    std::vector<double> trial_q;
+    double trial_t_iter = 0.0;
 
     // FP32 correction state of the refinement (allocated by the first
     // DVM_FP32_REFINE solve)
@@ -962,8 +968,20 @@ static int enqueue_block(dvm_ctx *c, int iters, int kind)
     return DVM_OK;
 }
 
+// diagnostics on stderr when DVM_DEBUG is set (not 0)
+static bool debug_on()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *e = std::getenv("DVM_DEBUG");
+        on = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
-                     const std::vector<long long> &prior);
+                     const std::vector<long long> &prior, const std::vector<char> *trial = nullptr,
+                     std::vector<char> *reverted = nullptr);
 
 static long long state_segments(const dvm_ctx *c, int i, int pw, long long voff, std::vector<VSeg> *g,
                                 std::vector<VSeg> *sc);
@@ -1047,11 +1065,16 @@ static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const
 // by more than 10% runs away instead of creeping towards the fixed point
 // (stalled = 2); one whose relative change has not dropped by 0.5% does not
 // contract at all (stalled = 1).  A slow but contracting iteration (large
-// delta) is left alone: restarted GMRES does worse there.  Instances with
-// grow_only set stop only in the first case.
+// delta) is left alone here.  Instances with grow_only set stop only in the
+// first case.
+// With no_trial given (AUTO), an instance whose contraction per iteration has
+// settled above 0.98 (no extrapolation there) with more than 1000 iterations
+// still to go is stopped for a GMRES trial (stalled = 3); its rate is left in
+// c->trial_q, the plain wall time per iteration in c->trial_t_iter.
 static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, int kind,
                       std::vector<SolveState> &st, std::vector<char> *stalled = nullptr,
-                      const std::vector<char> *grow_only = nullptr)
+                      const std::vector<char> *grow_only = nullptr,
+                      const std::vector<char> *no_trial = nullptr)
 {
     const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
     const long long cap = c->cfg.max_iter;
@@ -1068,18 +1091,31 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
     // instance whose relative change, a block after an extrapolation, is
     // above the one the extrapolation started from is not extrapolated again
     const bool extrap = c->cfg.accel == DVM_ACCEL_AUTO && kind != 2;
+    // FP32 correction iterations (AUTO): one whose rate settles above 0.995
+    // with more than 1000 iterations to go stops (stalled = 3); the
+    // refinement continues that instance in FP64, where GMRES can take over
+    const bool slow32 = c->cfg.accel == DVM_ACCEL_AUTO && kind == 2 && stalled;
     std::vector<std::vector<double>> eh(c->n_inst);
     std::vector<double> eps_at(c->n_inst, -1.0);
     std::vector<char> no_extrap(c->n_inst, 0);
     for (;;) {
         for (int i = 0; i < c->n_inst; ++i)
             before[i] = st[i].iter;
+        const auto t_blk = std::chrono::steady_clock::now();
         int rc = enqueue_block(c, B, kind);
         if (rc)
             return rc;
         HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
                               c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        {
+            long long adv = 0;
+            for (int i = i0; i < i1; ++i)
+                adv = std::max(adv, st[i].iter - before[i]);
+            if (adv > 0)
+                c->trial_t_iter = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_blk).count() /
+                                  (double)adv;
+        }
         if (c->cfg.profile) {
             long long real = 0;
             for (int i = 0; i < c->n_inst; ++i)
@@ -1120,13 +1156,14 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
         }
         if (!running)
             return DVM_OK;
-        if (extrap) {
+        if (extrap || slow32) {
             // a settled rate: per-iteration contraction over the last two
             // blocks agreeing to 5% of the gap 1 - q, and q <= 0.98 (the
             // factor q/(1-q) also multiplies the next mode's error: closer
             // to 1 it can amplify that mode more than it removes)
             std::vector<int> cand;
             std::vector<double> qs;
+            bool trial_stop = false;
             for (int i = i0; i < i1; ++i) {
                 if (!(st[i].active && st[i].iter - iter0[i] < cap) || no_extrap[i])
                     continue;
@@ -1142,12 +1179,37 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                 if (!(e0 > 0.0 && e1 > 0.0 && e2 > 0.0))
                     continue;
                 const double qa = std::pow(e2 / e1, 1.0 / B), qb = std::pow(e1 / e0, 1.0 / B);
-                if (qa > 0.5 && qa <= 0.98 && std::fabs(qa - qb) <= 0.05 * (1.0 - qa)) {
+                const bool settled = std::fabs(qa - qb) <= 0.05 * (1.0 - qa);
+                if (slow32) {
+                    const double tli = st[i].tol > 0.0 ? st[i].tol : tol;
+                    if (qa > 0.995 && qa < 1.0 && settled && st[i].eps > tli &&
+                        std::log(tli / st[i].eps) / std::log(qa) > 1000.0) {
+                        st[i].active = 0;
+                        (*stalled)[i] = 3;
+                        trial_stop = true;
+                    }
+                } else if (qa > 0.5 && qa <= 0.98 && settled) {
                     cand.push_back(i);
                     qs.push_back(qa);
                     eps_at[i] = st[i].eps;
                     e.clear();
+                } else if (stalled && no_trial && !(*no_trial)[i] && qa > 0.98 && qa < 1.0 && settled &&
+                           std::log(tol / st[i].eps) / std::log(qa) > 1000.0) {
+                    st[i].active = 0;
+                    (*stalled)[i] = 3;
+                    c->trial_q[i] = qa;
+                    trial_stop = true;
                 }
+            }
+            if (trial_stop) {
+                HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                                      c->stream));
+                HIPCHK(hipStreamSynchronize(c->stream));
+                bool left = false;
+                for (int i = i0; i < i1; ++i)
+                    left = left || (st[i].active && st[i].iter - iter0[i] < cap);
+                if (!left)
+                    return DVM_OK;
             }
             if (!cand.empty()) {
                 rc = extrapolate(c, kind, cand, qs, st);
@@ -1161,7 +1223,7 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
 // The iteration of [i0, i1) as configured: plain, GMRES, or plain with GMRES
 // taking over stalled instances.  Leaves per-instance sweep counts in
 // c->sweeps_done.
-static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, bool adj,
+static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0_in, bool adj,
                    std::vector<SolveState> &st, std::vector<char> *need_skew = nullptr)
 {
     if (c->cfg.accel == DVM_ACCEL_GMRES) {
@@ -1180,33 +1242,86 @@ static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &ite
     std::vector<char> grow_only(c->n_inst, gm ? 0 : 1);
     for (int i = i0; i < i1; ++i)
         detect = detect || on_wrap(i);
-    std::vector<char> stalled(c->n_inst, 0);
-    int rc = run_blocks(c, i0, i1, iter0, adj ? 1 : 0, st, detect ? &stalled : nullptr, &grow_only);
-    if (rc)
-        return rc;
-    std::vector<long long> prior(c->n_inst, 0);
-    bool any = false;
-    for (int i = i0; i < i1; ++i) {
-        prior[i] = st[i].iter - iter0[i];
-        c->sweeps_done[i] = prior[i];
-        if (on_wrap(i) && (stalled[i] == 2 || st[i].status == STATUS_DIVERGED)) {
-            (*need_skew)[i] = 1;
-        } else if (stalled[i]) {
-            if (gm) {
-                st[i].active = 1;
-                st[i].status = STATUS_RUNNING;
-                any = true;
-            } else {
-                st[i].status = STATUS_DIVERGED;  // runs away: the plain iteration cannot converge
+    // an instance whose GMRES trial lost to the plain iteration is not tried
+    // again and stays plain; base = its sweeps before the current plain pass
+    std::vector<char> no_trial(c->n_inst, gm ? 0 : 1);
+    std::vector<long long> iter0 = iter0_in, base(c->n_inst, 0);
+    std::vector<char> counted(c->n_inst, 0);   // finished in GMRES: count final
+    SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
+    for (;;) {
+        std::vector<char> stalled(c->n_inst, 0);
+        int rc = run_blocks(c, i0, i1, iter0, adj ? 1 : 0, st, detect ? &stalled : nullptr, &grow_only,
+                            gm ? &no_trial : nullptr);
+        if (rc)
+            return rc;
+        std::vector<long long> prior(c->n_inst, 0);
+        std::vector<char> trial(c->n_inst, 0);
+        bool any = false;
+        for (int i = i0; i < i1; ++i) {
+            if (counted[i])
+                continue;
+            prior[i] = base[i] + st[i].iter - iter0[i];
+            c->sweeps_done[i] = prior[i];
+            if (debug_on() && stalled[i])
+                std::fprintf(stderr, "[dvm iterate] inst %d stopped (%d) after %lld sweeps, eps %.3e\n", i,
+                             (int)stalled[i], prior[i], st[i].eps);
+            if (on_wrap(i) && (stalled[i] == 2 || st[i].status == STATUS_DIVERGED)) {
+                (*need_skew)[i] = 1;
+            } else if (stalled[i]) {
+                if (gm) {
+                    st[i].active = 1;
+                    st[i].status = STATUS_RUNNING;
+                    trial[i] = stalled[i] == 3;
+                    any = true;
+                } else {
+                    st[i].status = STATUS_DIVERGED;  // runs away: the plain iteration cannot converge
+                }
             }
         }
+        if (!any)
+            return DVM_OK;
+        HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::vector<char> reverted(c->n_inst, 0);
+        if ((rc = gmres_run(c, i0, i1, adj, st, prior, &trial, &reverted)))
+            return rc;
+        // trial instances handed back: the plain iteration resumes from the
+        // state GMRES reached (records from its moments, fresh stop history)
+        bool again = false;
+        for (int i = i0; i < i1; ++i) {
+            if (stalled[i] && !reverted[i])
+                counted[i] = 1;
+            if (!reverted[i])
+                continue;
+            again = true;
+            // back for good: neither another trial nor a takeover when the
+            // plain iteration then creeps (GMRES has just shown it is slower)
+            no_trial[i] = 1;
+            grow_only[i] = 1;
+            base[i] = c->sweeps_done[i];
+            iter0[i] = st[i].iter;
+            // the stop rule's ratio is held at least at the rate measured
+            // before the trial: the slow modes GMRES left still contract at
+            // it, while two successive changes first show faster ones
+            SolveState &s = st[i];
+            s.active = 1;
+            s.status = STATUS_RUNNING;
+            s.npass = 0;
+            s.eps_prev = 0.0;
+            s.qfloor = std::max(s.qfloor, c->trial_q[i]);
+            s.maxdiff_bits = s.maxabs_bits = 0ull;
+        }
+        if (!again)
+            return DVM_OK;
+        HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(launch_record<double>(rec_args(c, adj), c->max_cells, c->n_inst, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int i = i0; i < i1; ++i)
+            if (reverted[i])
+                st[i].maxdiff_bits = st[i].maxabs_bits = 0ull;
+        HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
     }
-    if (!any)
-        return DVM_OK;
-    SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
-    HIPCHK(hipMemcpyAsync(dst, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return gmres_run(c, i0, i1, adj, st, prior);
 }
 
 // --------------------------------------------------------------- GMRES
@@ -1329,7 +1444,8 @@ static double sigma_min_tri(const std::vector<double> &R, int ld, int k)
 }
 
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
-                     const std::vector<long long> &prior)
+                     const std::vector<long long> &prior, const std::vector<char> *trial,
+                     std::vector<char> *reverted)
 {
     const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 64;
     const int mode = solve_mode(c) | (adj ? MODE_ADJ : xu_flag(c, c->V));
@@ -1441,7 +1557,11 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
     HIPCHK(launch_gather(kw.sseg.p, (int)sseg.size(), sb, kw.x.p, nullptr, c->stream));
 
     std::vector<double> hc1((size_t)ns * cst), hc2((size_t)ns * cst), hy((size_t)ns * cst);
+    bool trials = false;
+    for (int q = 0; q < ns; ++q)
+        trials = trials || (trial && (*trial)[slots[q].inst]);
     for (;;) {
+        const auto t_cyc = std::chrono::steady_clock::now();
         // ---- one full iteration from x: residual w = x - F(x) and eps
         for (int q = 0; q < ns; ++q)
             if (hs[q].live)
@@ -1491,6 +1611,9 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             else if (h.sweeps >= cap)
                 fin = STATUS_MAXITER;
             if (fin) {
+                if (debug_on())
+                    std::fprintf(stderr, "[dvm gmres] inst %d done (%d) after %lld sweeps, eps %.3e est %.3e\n",
+                                 slots[q].inst, fin, h.sweeps, eps, est);
                 // the state now holds F(x): advance the parity like an iteration
                 s.iter += 1;
                 s.status = fin;
@@ -1593,6 +1716,50 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         }
         HIPCHK(hipMemcpyAsync(kw.y.p, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, k, kw.y.p, cst, nullptr, c->stream));
+        if (trials && k > 0) {
+            // a trial instance stays with GMRES while a cycle reduces its
+            // residual at least 1.5 times faster per second than the plain
+            // iteration's rate
+            HIPCHK(hipStreamSynchronize(c->stream));
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_cyc).count();
+            bool back = false, left = false;
+            for (int q = 0; q < ns; ++q) {
+                GmresSlotHost &h = hs[q];
+                const int inst = slots[q].inst;
+                if (!h.live)
+                    continue;
+                if ((*trial)[inst] && h.beta > 0.0) {
+                    const double red = std::max(std::fabs(h.g[k]) / h.beta, 1e-300);
+                    const double rate_g = -std::log(red) / std::max(dt, 1e-9);
+                    const double rate_p = -std::log(c->trial_q[inst]) / std::max(c->trial_t_iter, 1e-9);
+                    if (debug_on())
+                        std::fprintf(stderr, "[dvm trial] inst %d cycle of %d: residual x %.3e in %.3f s "
+                                     "(%.3g/s) vs plain q %.5f at %.3f ms (%.3g/s)\n", inst, k, red, dt, rate_g,
+                                     c->trial_q[inst], 1e3 * c->trial_t_iter, rate_p);
+                    if (rate_g < 1.5 * rate_p) {
+                        h.live = false;
+                        st[inst].active = 0;
+                        (*reverted)[inst] = 1;
+                        c->sweeps_done[inst] = h.sweeps;
+                        back = true;
+                        continue;
+                    }
+                }
+                left = true;
+            }
+            if (back) {
+                // the cycle's result goes back to the state the plain
+                // iteration reads (harmless for the others: every cycle
+                // starts by scattering x)
+                HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, kw.x.p, c->stream));
+                if ((rc = upload_st()))
+                    return rc;
+                if (!left)
+                    break;
+                if ((rc = rebuild()))
+                    return rc;
+            }
+        }
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     return DVM_OK;
@@ -1642,15 +1809,6 @@ static int ensure_fp32(dvm_ctx *c)
     return DVM_OK;
 }
 
-static bool debug_on()
-{
-    static int on = -1;
-    if (on < 0) {
-        const char *e = std::getenv("DVM_DEBUG");
-        on = (e && *e && *e != '0') ? 1 : 0;
-    }
-    return on == 1;
-}
 
 static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::vector<char> *need_skew)
 {
@@ -1674,6 +1832,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
         double q;
         long long s32, s64;
         bool fallback;
+        bool drop_e = false;   // this step's correction did not converge: not applied
     };
     std::vector<DSlot> slots;
     long long n = 0;
@@ -1897,14 +2056,27 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
             if (s.status == STATUS_CONVERGED && s.eps > 0.0 && std::isfinite(s.est) && s.est > 0.0)
                 qn = std::min(s.est / (s.eps + s.est), 0.9999);
             d.q = std::max(d.q, qn);
-            if (stalled[d.inst] || s.status == STATUS_DIVERGED) {
+            // a very slow correction iteration (q > 0.995, measured) goes on
+            // in FP64 under AUTO, where GMRES can take over: there Krylov
+            // steps beat any cheaper sweep
+            // (stalled = 3: stopped early for that reason; its partial
+            // correction is applied like a converged one)
+            const bool slow = c->cfg.accel == DVM_ACCEL_AUTO &&
+                              ((s.status == STATUS_CONVERGED && qn > 0.995) || stalled[d.inst] == 3);
+            if (stalled[d.inst] || s.status == STATUS_DIVERGED || slow) {
                 d.fallback = true;
                 d.live = false;
+                d.drop_e = !slow;
                 fb = true;
             }
         }
         // ---- x <- x - e
         HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_er.p, 2, c->stream));
+        for (auto &d : slots)
+            if (d.drop_e) {
+                HIPCHK(launch_zero(c->d_er.p + d.off, (size_t)d.len, c->stream));
+                d.drop_e = false;
+            }
         HIPCHK(launch_axpy(c->d_xr.p, c->d_er.p, -1.0, n, c->stream));
         if (fb) {
             // back to the FP64 state x for the instances that leave
@@ -1944,10 +2116,14 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
     for (const auto &d : slots)
         before[d.inst] = c->sweeps_done[d.inst];
     rc = iterate(c, i0, i1, iter0, false, st, need_skew);
+    // iterate() recounts every instance of [i0, i1): the ones that did not
+    // fall back keep their refinement counts
     for (const auto &d : slots)
         if (d.fallback) {
             c->sweeps64_done[d.inst] += c->sweeps_done[d.inst];
             c->sweeps_done[d.inst] += before[d.inst];
+        } else {
+            c->sweeps_done[d.inst] = before[d.inst];
         }
     return rc;
 }
@@ -2561,6 +2737,7 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->G = G;
     ctx->inst.assign(n_instances, HostInst{});
     ctx->sweeps_done.assign(n_instances, 0);
+    ctx->trial_q.assign(n_instances, 0.0);
     ctx->sweeps64_done.assign(n_instances, 0);
     ctx->sweeps_wasted.assign(n_instances, 0);
     ctx->driving.assign(n_instances, dvm_ctx::Driving{});

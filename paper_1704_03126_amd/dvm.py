@@ -202,13 +202,16 @@ class Solver:
 
     def solve(self, instance: int, delta, alpha: float = 1.0, warm: bool = False,
               raise_on_noconv: bool = True):
+        """Solve one instance (or all, instance -1) to the stop rule; returns
+        its SolveInfo (a list for -1).  With raise_on_noconv False, instances
+        that stop at max_iter or diverge do not raise: their status says so."""
         d, field = self._delta_arg(instance, delta)
         n = self.n_instances if instance < 0 else 1
         infos = (dvm_info * n)()
         fn = self._lib.dvm_solve_warm if warm else self._lib.dvm_solve
         self.epoch += 1
         rc = fn(self._h, instance, _ptr(d), field, float(alpha), infos)
-        if rc != DVM_OK and not (rc == DVM_ENOCONV and not raise_on_noconv):
+        if rc != DVM_OK and not (rc in (DVM_ENOCONV, DVM_EDIVERGED) and not raise_on_noconv):
             _check(rc)
         out = [SolveInfo(i.iters, i.sweeps_fp64, i.rel_change, i.est_error,
                          STATUS_NAMES.get(i.status, str(i.status)),

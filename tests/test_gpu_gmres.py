@@ -144,3 +144,43 @@ def test_auto_hands_diverging_instances_to_gmres(dvm):
     s.close()
     assert info.status == "converged"
     assert abs(Q3 - ref3.Q) <= 1e-8 * abs(ref3.Q)
+
+
+def test_auto_gmres_trial_on_slow_iteration(dvm):
+    """A periodic porous cell (199^2, seeded, 48^2 velocities) at delta 3.69
+    whose plain iteration contracts at about 0.9986 per sweep (some 11000
+    sweeps to tol 1e-8): AUTO hands it to GMRES on trial, GMRES keeps it
+    (its cycles reduce the residual faster per second than the plain rate),
+    and the result is GMRES's own to within the tolerance.  Also a solve of
+    the batch that holds it next to a fast instance: the fast one converges
+    plain and the counts stay per instance."""
+    from paper_1704_03126_amd.geometry import batch_instances
+    g = batch_instances(64)[6]
+    assert (g.ny, g.nx) == (199, 199) and g.periodic_y
+    d = g.meta["delta"]
+    res = {}
+    for name, acc in (("auto", dvm.DVM_ACCEL_AUTO), ("gmres", dvm.DVM_ACCEL_GMRES)):
+        s = dvm.Solver(48, 1, tol=1e-8, max_iter=30000, accel=acc)
+        s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        info = s.solve(0, d)
+        assert info.status == "converged", (name, info)
+        res[name] = (s.flow_rate(0)[0], info.iters)
+        s.close()
+    (qa, ia), (qg, ig) = res["auto"], res["gmres"]
+    assert abs(qa - qg) <= 1e-8 * abs(qg), (qa, qg)
+    assert ia < 2000, ia
+    g1 = rough_channel(64, 32, 6, 32)
+    s = dvm.Solver(48, 2, tol=1e-8, max_iter=30000)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    s.set_geometry(1, g1.mask, g1.periodic_y, g1.cells_per_H)
+    infos = s.solve(-1, [d, 1.0])
+    q0, q1 = s.flow_rate(0)[0], s.flow_rate(1)[0]
+    s.close()
+    assert all(i.status == "converged" for i in infos), infos
+    assert abs(q0 - qg) <= 1e-8 * abs(qg), (q0, qg)
+    assert 0 < infos[1].iters < 200 and infos[0].iters < 2000, infos
+    s = dvm.Solver(48, 1, tol=1e-8)
+    s.set_geometry(0, g1.mask, g1.periodic_y, g1.cells_per_H)
+    s.solve(0, 1.0)
+    assert abs(s.flow_rate(0)[0] - q1) <= 1e-9 * abs(q1)
+    s.close()

@@ -73,3 +73,32 @@ def test_refinement_batched_and_gradient(dvm):
     b.close()
     f.close()
     assert np.max(np.abs(gb - gf)) <= 1e-7 * np.max(np.abs(gf))
+
+
+def test_refinement_batch_counts_with_fp64_fallback(dvm):
+    """A batch where one instance's FP32 correction iteration does not
+    contract and continues in FP64 (a 78^2 periodic porous cell at delta
+    0.033, 48^2 velocities) next to one that refines normally: both solutions
+    match the plain FP64 solve, and every instance reports its own sweep
+    counts (the fallback's FP64 iteration must not reset the others')."""
+    from paper_1704_03126_amd.geometry import batch_instances
+    g0 = batch_instances(64)[62]
+    assert g0.nx == 78 and g0.periodic_y
+    g1 = rough_channel(64, 32, 6, 32)
+    deltas = [g0.meta["delta"], 1.0]
+    res = {}
+    for prec in (dvm.DVM_FP64, dvm.DVM_FP32_REFINE):
+        s = dvm.Solver(48, 2, tol=1e-10, precision=prec)
+        s.set_geometry(0, g0.mask, g0.periodic_y, g0.cells_per_H)
+        s.set_geometry(1, g1.mask, g1.periodic_y, g1.cells_per_H)
+        infos = s.solve(-1, deltas)
+        res[prec] = ([s.flow_rate(i)[0] for i in range(2)], infos)
+        s.close()
+    (q64, i64), (q32, i32) = res[dvm.DVM_FP64], res[dvm.DVM_FP32_REFINE]
+    for a, b in zip(q64, q32):
+        assert abs(a - b) <= 1e-8 * abs(a), (q64, q32)
+    for inf in i32:
+        assert inf.status == "converged"
+        assert inf.iters > 0 and 0 < inf.sweeps_fp64 <= inf.iters, i32
+    # the rough channel refines: most of its sweeps are FP32
+    assert i32[1].sweeps_fp64 < i32[1].iters // 4, i32
