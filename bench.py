@@ -49,13 +49,14 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--workload", choices=["rough_channel", "batch64", "couette", "porous"], default="rough_channel",
+    p.add_argument("--workload", choices=["rough_channel", "batch64", "couette", "porous", "adjoint"], default="rough_channel",
                    help="rough_channel: the headline workload; batch64: 64 uneven instances "
                         "(sides 64-384, 48 x 48 velocities) in one batched solve, throughput over a "
                         "fixed number of iterations; couette: the Couette flow of the fractal rough "
                         "channel and the smooth one over Kn 0.03-10 (Q*); porous: the rarefaction "
                         "sweep of the 512 x 512 porous cell (8 deltas over 0.01-100, warm starts) "
-                        "and its permeability post-processing")
+                        "and its permeability post-processing; adjoint: forward solve and gradient "
+                        "of the 256 x 256 porous cell with delta(x) and alpha 0.9")
     p.add_argument("--batch-iters", type=int, default=24,
                    help="iterations per timed batched solve (batch64); 0: every instance "
                         "to the stop rule")
@@ -110,6 +111,8 @@ def main():
         return bench_couette(args, torch, dvm)
     if args.workload == "porous":
         return bench_porous(args, torch, dvm)
+    if args.workload == "adjoint":
+        return bench_adjoint(args, torch, dvm)
 
     g = cfg_rough_channel()
     nf = g.n_fluid
@@ -411,6 +414,59 @@ def bench_porous(args, torch, dvm):
            "k_inf": perm["k_inf"], "H_star": perm["H_star"],
            "Kn_star": [float(x) for x in perm["Kn_star"]],
            "ka_over_kinf": [float(x) for x in perm["ka_ratio"]],
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
+def bench_adjoint(args, torch, dvm):
+    """The gradient workload: a 256 x 256 periodic porous cell (porosity
+    0.55, seed 3005), log-normal delta(x) of mean 1 smoothed over 8 cells
+    (seed 3006), accommodation 0.9, 48 x 48 velocities, FP64.  One step = the
+    forward solve to the stop rule and the gradient (dQ/d delta per cell and
+    dQ/d alpha: checkpoint sweep, adjoint solve, gradient sweep), timed
+    apart."""
+    from paper_1704_03126_amd.geometry import delta_field, porous_discs
+    nv, alpha = 48, 0.9
+    g = porous_discs(256, 0.55, 3005)
+    base = np.where(g.mask == 0, delta_field(g.mask.shape, 3006), 0.0)
+    s = dvm.Solver(nv, 1, tol=args.tol, **solver_options(args, dvm))
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+
+    def step():
+        t0 = time.perf_counter()
+        info = s.solve(0, base, alpha)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gd, ga = s.grad(0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return info, gd, ga, t1 - t0, t2 - t1
+
+    for _ in range(args.warmup):
+        step()
+    fwd, adj, its = [], [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info, gd, ga, tf, ta = step()
+        fwd.append(tf)
+        adj.append(ta)
+        its += info.iters
+    elapsed = time.perf_counter() - t0
+    Q = s.flow_rate(0)[0]
+    s.close()
+    out = {"metric": METRIC, "value": its * g.n_fluid * nv * nv / sum(fwd), "unit": "updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "adjoint_porous_256x256_phi0.55_seed3005_deltafield_alpha0.9_nv48",
+                      "nx": g.nx, "ny": g.ny, "fluid_cells": g.n_fluid, "velocities": nv * nv,
+                      "alpha": alpha, "tol": args.tol, "schedule": args.schedule, "accel": args.accel,
+                      "parallelism": "single_gpu"},
+           "value_is": "forward-solve updates/s", "forward_iterations": info.iters,
+           "forward_s": float(np.mean(fwd)), "gradient_s": float(np.mean(adj)),
+           "gradient_over_forward": float(np.mean(adj) / np.mean(fwd)),
+           "Q": Q, "dQ_dalpha": ga, "dQ_ddelta_max_abs": float(np.max(np.abs(gd))),
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out))
 

@@ -140,9 +140,30 @@ __global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, co
     for (int i = threadIdx.x; i < c.len; i += 256) {
         const size_t e = c.start + i;
         double acc = w[e];
-        for (int j = 0; j < nvec; ++j) {
+        // groups of 8 rows: the loads of a group are issued together (the
+        // sum keeps the row order); a group whose coefficients are all zero
+        // (rows a skipped second pass left at zero) is not read
+        int j = 0;
+        for (; j + 8 <= nvec; j += 8) {
+            double cj[8], vj[8];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cj[u] = cf[j + u];
+                any = any || cj[u] != 0.0;
+            }
+            if (!any)
+                continue;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                vj[u] = V[(size_t)(j + u) * ldv + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                acc = fma(-cj[u], vj[u], acc);
+        }
+        for (; j < nvec; ++j) {
             const double cj = cf[j];
-            if (cj != 0.0)               // rows a skipped second pass left at zero
+            if (cj != 0.0)
                 acc = fma(-cj, V[(size_t)j * ldv + e], acc);
         }
         w[e] = acc;
