@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--precision", choices=["fp64", "fp32_refine"], default="fp64",
                    help="fp64 sweeps, or FP32 sweeps with FP64 defect correction")
-    p.add_argument("--cpu-seconds", type=float, default=12.0,
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="budget of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--workload", choices=["rough_channel", "batch64", "couette", "porous", "adjoint"], default="rough_channel",
@@ -497,11 +497,18 @@ def cpu_baseline(g, budget_s):
     scaled to take about `budget_s` seconds."""
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    oracle.si_solve(g.mask, 1.0, NV, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
-                    tol=-1.0, max_iter=2)
-    t1 = (time.perf_counter() - t0) / 2.0
-    n = max(2, int(budget_s / max(t1, 1e-3)))
+
+    def run(n):
+        t0 = time.perf_counter()
+        oracle.si_solve(g.mask, 1.0, NV, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
+                        tol=-1.0, max_iter=n)
+        return time.perf_counter() - t0
+
+    # per-iteration cost from the difference of two short runs (a call also
+    # pays the oracle's set-up), then as many iterations as fill the budget
+    t1, t3 = run(1), run(3)
+    it_s = max((t3 - t1) / 2.0, 1e-3)
+    n = max(2, int(max(budget_s - t1 + it_s, it_s) / it_s))
     t0 = time.perf_counter()
     oracle.si_solve(g.mask, 1.0, NV, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
                     tol=-1.0, max_iter=n)
