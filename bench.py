@@ -71,6 +71,8 @@ def parse():
     p.add_argument("--tol", type=float, default=TOL,
                    help="stop-rule tolerance of every solve (relative change of u1 and its "
                         "a-posteriori error bound)")
+    p.add_argument("--block-iters", type=int, default=32,
+                   help="iterations per captured block (the stop and rate checks run between blocks)")
     p.add_argument("--vel", type=int, default=0)
     p.add_argument("--waves", type=int, default=0)
     p.add_argument("--no-roofline", action="store_true",
@@ -117,11 +119,9 @@ def main():
     g = cfg_rough_channel()
     nf = g.n_fluid
     K = NV * NV
-    sched = {"auto": dvm.DVM_SCHED_AUTO, "skew": dvm.DVM_SCHED_SKEW, "wrap": dvm.DVM_SCHED_WRAP}[args.schedule]
-    accel = {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE, "gmres": dvm.DVM_ACCEL_GMRES}[args.accel]
     prec = dvm.DVM_FP32_REFINE if args.precision == "fp32_refine" else dvm.DVM_FP64
     solver = dvm.Solver(NV, 1, tol=args.tol, vel_per_lane=args.vel, waves_per_block=args.waves,
-                        schedule=sched, accel=accel, precision=prec)
+                        precision=prec, **solver_options(args, dvm))
     solver.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
 
     scheds = {}
@@ -159,7 +159,7 @@ def main():
         # roofline of the sweep: one more step with every sweep bracketed by
         # HIP events on the solver's stream
         prof = dvm.Solver(NV, 1, tol=args.tol, profile=True, vel_per_lane=args.vel,
-                          waves_per_block=args.waves, schedule=sched)
+                          waves_per_block=args.waves, **solver_options(args, dvm))
         prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
         prof_sched = set()
         prof_iters = 0
@@ -218,7 +218,8 @@ def main():
         "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
                    "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
                    "deltas": list(DELTAS), "tol": args.tol, "precision": args.precision,
-                   "schedule": args.schedule, "accel": args.accel, "parallelism": "single_gpu"},
+                   "schedule": args.schedule, "accel": args.accel, "block_iters": args.block_iters,
+                   "parallelism": "single_gpu"},
         "iterations_per_delta": all_its[-1],
         "schedule_per_delta": scheds,
         "time_to_solution_s": dict(zip([str(d) for d in DELTAS],
@@ -233,11 +234,13 @@ def main():
 
 
 def solver_options(args, dvm):
-    """Sweep order and acceleration chosen on the command line."""
+    """Sweep order, acceleration and iteration-block length chosen on the
+    command line."""
     return {"schedule": {"auto": dvm.DVM_SCHED_AUTO, "skew": dvm.DVM_SCHED_SKEW,
                          "wrap": dvm.DVM_SCHED_WRAP}[args.schedule],
             "accel": {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE,
-                      "gmres": dvm.DVM_ACCEL_GMRES}[args.accel]}
+                      "gmres": dvm.DVM_ACCEL_GMRES}[args.accel],
+            "block_iters": args.block_iters}
 
 
 def stored_oracle_error(g, Qs):

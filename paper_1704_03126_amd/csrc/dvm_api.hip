@@ -1180,6 +1180,9 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                     continue;
                 const double qa = std::pow(e2 / e1, 1.0 / B), qb = std::pow(e1 / e0, 1.0 / B);
                 const bool settled = std::fabs(qa - qb) <= 0.05 * (1.0 - qa);
+                if (debug_on())
+                    std::fprintf(stderr, "[dvm rate] inst %d after %lld: eps %.3e q %.5f (previous block %.5f)%s\n",
+                                 i, st[i].iter - iter0[i], st[i].eps, qa, qb, settled ? " settled" : "");
                 if (slow32) {
                     const double tli = st[i].tol > 0.0 ? st[i].tol : tol;
                     if (qa > 0.995 && qa < 1.0 && settled && st[i].eps > tli &&
