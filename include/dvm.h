@@ -124,8 +124,9 @@ typedef struct {
                                same fixed point; it converges where the lagged
                                iteration diverges.  AUTO hands an instance to
                                GMRES when its relative change of u1 has not
-                               dropped by 0.5% over 64 iterations (a slowly
-                               contracting iteration stays plain).  GMRES stop
+                               dropped by 0.5% over 64 iterations; a slowly
+                               contracting one gets a GMRES trial (see
+                               DVM_ACCEL_AUTO).  GMRES stop
                                rule: one iteration from the result changes u1
                                by eps (relative) with eps / sigma <= tol,
                                sigma the smallest singular value of the last

@@ -1065,7 +1065,7 @@ static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const
 // by more than 10% runs away instead of creeping towards the fixed point
 // (stalled = 2); one whose relative change has not dropped by 0.5% does not
 // contract at all (stalled = 1).  A slow but contracting iteration (large
-// delta) is left alone here.  Instances with grow_only set stop only in the
+// delta) is not stopped by this test.  Instances with grow_only set stop only in the
 // first case.
 // With no_trial given (AUTO), an instance whose contraction per iteration has
 // settled above 0.98 (no extrapolation there) with more than 1000 iterations
