@@ -86,7 +86,8 @@ struct DevBuf {
 
 // device workspace of the GMRES driver (grown on demand)
 struct KrylovWork {
-    DevBuf<double> V, x, w, part, c1, c2, y;
+    DevBuf<float> V;    // GMRES basis, stored in FP32 (the residual, x, w and all sums are FP64)
+    DevBuf<double> x, w, part, c1, c2, y;
     DevBuf<VSeg> gseg, sseg;
     DevBuf<VChunk> ch;
     DevBuf<int> c0, nc;
@@ -1473,7 +1474,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
     if (ns == 0)
         return DVM_OK;
     KrylovWork &kw = c->kw;
-    auto grow = [&](DevBuf<double> &b, size_t cnt) -> hipError_t {
+    auto grow = [&](auto &b, size_t cnt) -> hipError_t {
         return b.n >= cnt ? hipSuccess : b.alloc(cnt);
     };
     const long long nchmax = n / VCHUNK + ns + 1;
@@ -1646,11 +1647,11 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                               c->stream));
         int k = 0;
         for (int j = 0; j < m; ++j) {
-            double *Vj = kw.V.p + (size_t)j * n;
+            float *Vj = kw.V.p + (size_t)j * n;
             HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, Vj, c->stream));
             if ((rc = sweep_once(true, false)))
                 return rc;
-            HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, Vj, c->stream));
+            HIPCHK(launch_gather_sub32(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, Vj, c->stream));
             // classical Gram-Schmidt; the second pass only where the first
             // one cancelled more than half of |w|^2
             if ((rc = dots(kw.w.p, j + 1, true, kw.c1.p)))

@@ -224,13 +224,19 @@ enum { VCHUNK = 4096 };
 // vec[vec_off..] = buf[buf_off..]        (sub == nullptr)
 // vec[vec_off..] = sub[..] - buf[..]     (sub != nullptr)
 hipError_t launch_gather(const VSeg *seg, int nseg, StateBufs b, double *vec, const double *sub, hipStream_t s);
+// the same with sub in FP32 (a Krylov basis vector)
+hipError_t launch_gather_sub32(const VSeg *seg, int nseg, StateBufs b, double *vec, const float *sub,
+                               hipStream_t s);
 // buf[buf_off..] = vec[vec_off..]
 hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const double *vec, hipStream_t s);
+hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const float *vec, hipStream_t s);
 // part[j][chunk] = <w, V_j> over the chunk, j < nvec; row nvec: <w, w> if with_norm.
 // skipc (or nullptr): per-slot coefficients [slot][cst] of a first projection
 // pass with |w|^2 before it in row nvec; slots where that pass removed at most
 // half of |w|^2 get zero in rows j < nvec (no second pass needed)
 hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const double *V, long long ldv, int nvec,
+                        int with_norm, double *part, const double *skipc, int cst, hipStream_t s);
+hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const float *V, long long ldv, int nvec,
                         int with_norm, double *part, const double *skipc, int cst, hipStream_t s);
 // out[slot][j] = sum of part[j][chunk] over the slot's chunks (fixed order)
 hipError_t launch_vsum(const int *slot_chunk0, const int *slot_nchunk, int nslots, const double *part, int nch,
@@ -261,5 +267,9 @@ hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream
 // (Pythagoras with the norm in coef[slot][nvec]); zero when hn == 0
 hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const double *V, long long ldv, int nvec,
                           const double *coef, int cstride, double *vout, hipStream_t s);
+// the same with the basis V (and vout) stored in FP32; w, coef and the sums
+// stay FP64
+hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
+                          const double *coef, int cstride, float *vout, hipStream_t s);
 
 } // namespace dvm

@@ -8,28 +8,30 @@
 
 namespace dvm {
 
-__global__ void __launch_bounds__(256) k_gather(const VSeg *seg, StateBufs b, double *vec, const double *sub)
+template <typename TS>
+__global__ void __launch_bounds__(256) k_gather(const VSeg *seg, StateBufs b, double *vec, const TS *sub)
 {
     const VSeg sg = seg[blockIdx.x];
     const double *src = b.b[sg.buf] + sg.buf_off;
     double *dst = vec + sg.vec_off;
     if (sub) {
-        const double *sb = sub + sg.vec_off;
+        const TS *sb = sub + sg.vec_off;
         for (int i = threadIdx.x; i < sg.len; i += 256)
-            dst[i] = sb[i] - src[i];
+            dst[i] = (double)sb[i] - src[i];
     } else {
         for (int i = threadIdx.x; i < sg.len; i += 256)
             dst[i] = src[i];
     }
 }
 
-__global__ void __launch_bounds__(256) k_scatter(const VSeg *seg, StateBufs b, const double *vec)
+template <typename TS>
+__global__ void __launch_bounds__(256) k_scatter(const VSeg *seg, StateBufs b, const TS *vec)
 {
     const VSeg sg = seg[blockIdx.x];
     double *dst = b.b[sg.buf] + sg.buf_off;
-    const double *src = vec + sg.vec_off;
+    const TS *src = vec + sg.vec_off;
     for (int i = threadIdx.x; i < sg.len; i += 256)
-        dst[i] = src[i];
+        dst[i] = (double)src[i];
 }
 
 __device__ __forceinline__ double block_sum256(double v, double *red)
@@ -56,7 +58,8 @@ __device__ __forceinline__ double block_sum256(double v, double *red)
 constexpr int VROWS = 8;
 constexpr int VPER = VCHUNK / 256;
 
-__global__ void __launch_bounds__(256) k_vdots(const VChunk *ch, const double *w, const double *V, long long ldv,
+template <typename TV>
+__global__ void __launch_bounds__(256) k_vdots(const VChunk *ch, const double *w, const TV *V, long long ldv,
                                                int nvec, int with_norm, double *part, int nch,
                                                const double *skipc, int cst)
 {
@@ -88,7 +91,7 @@ __global__ void __launch_bounds__(256) k_vdots(const VChunk *ch, const double *w
             const int r = r0 + rr;
             if (r < nvec) {
                 if (!skip)
-                    acc[rr] = fma(wi, V[(size_t)r * ldv + c.start + i], acc[rr]);
+                    acc[rr] = fma(wi, (double)V[(size_t)r * ldv + c.start + i], acc[rr]);
             } else if (r < nrows) {
                 acc[rr] = fma(wi, wi, acc[rr]);
             }
@@ -125,8 +128,9 @@ __global__ void __launch_bounds__(256) k_vsum(const int *slot_chunk0, const int 
         out[(size_t)slot * ostride + j] = s;
 }
 
-__global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, const double *V, long long ldv,
-                                                 int nvec, const double *coef, int cstride, double *vout)
+template <typename TV>
+__global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, const TV *V, long long ldv,
+                                                 int nvec, const double *coef, int cstride, TV *vout)
 {
     const VChunk c = ch[blockIdx.x];
     const double *cf = coef + (size_t)c.slot * cstride;
@@ -156,7 +160,7 @@ __global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, co
                 continue;
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                vj[u] = V[(size_t)(j + u) * ldv + e];
+                vj[u] = (double)V[(size_t)(j + u) * ldv + e];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 acc = fma(-cj[u], vj[u], acc);
@@ -164,11 +168,11 @@ __global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, co
         for (; j < nvec; ++j) {
             const double cj = cf[j];
             if (cj != 0.0)
-                acc = fma(-cj, V[(size_t)j * ldv + e], acc);
+                acc = fma(-cj, (double)V[(size_t)j * ldv + e], acc);
         }
         w[e] = acc;
         if (vout)
-            vout[e] = acc * inv;
+            vout[e] = (TV)(acc * inv);
     }
 }
 
@@ -229,31 +233,60 @@ hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream
     return hipGetLastError();
 }
 
+template <typename TS>
+static hipError_t gather_t(const VSeg *seg, int nseg, StateBufs b, double *vec, const TS *sub, hipStream_t s)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_gather<TS>), dim3(nseg), dim3(256), 0, s, seg, b, vec, sub);
+    return hipGetLastError();
+}
 hipError_t launch_gather(const VSeg *seg, int nseg, StateBufs b, double *vec, const double *sub, hipStream_t s)
 {
-    if (nseg == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(nseg), dim3(256), 0, s, seg, b, vec, sub);
-    return hipGetLastError();
+    return gather_t(seg, nseg, b, vec, sub, s);
+}
+hipError_t launch_gather_sub32(const VSeg *seg, int nseg, StateBufs b, double *vec, const float *sub, hipStream_t s)
+{
+    return gather_t(seg, nseg, b, vec, sub, s);
 }
 
-hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const double *vec, hipStream_t s)
+template <typename TS>
+static hipError_t scatter_t(const VSeg *seg, int nseg, StateBufs b, const TS *vec, hipStream_t s)
 {
     if (nseg == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(nseg), dim3(256), 0, s, seg, b, vec);
+    hipLaunchKernelGGL((k_scatter<TS>), dim3(nseg), dim3(256), 0, s, seg, b, vec);
     return hipGetLastError();
 }
+hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const double *vec, hipStream_t s)
+{
+    return scatter_t(seg, nseg, b, vec, s);
+}
+hipError_t launch_scatter(const VSeg *seg, int nseg, StateBufs b, const float *vec, hipStream_t s)
+{
+    return scatter_t(seg, nseg, b, vec, s);
+}
 
-hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const double *V, long long ldv, int nvec,
-                        int with_norm, double *part, const double *skipc, int cst, hipStream_t s)
+template <typename TV>
+static hipError_t vdots_t(const VChunk *ch, int nch, const double *w, const TV *V, long long ldv, int nvec,
+                          int with_norm, double *part, const double *skipc, int cst, hipStream_t s)
 {
     const int nrows = nvec + (with_norm ? 1 : 0);
     if (nrows == 0 || nch == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_vdots, dim3(nch, (nrows + VROWS - 1) / VROWS), dim3(256), 0, s, ch, w, V, ldv, nvec,
-                       with_norm, part, nch, skipc, cst);
+    hipLaunchKernelGGL((k_vdots<TV>), dim3(nch, (nrows + VROWS - 1) / VROWS), dim3(256), 0, s, ch, w, V, ldv,
+                       nvec, with_norm, part, nch, skipc, cst);
     return hipGetLastError();
+}
+hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const double *V, long long ldv, int nvec,
+                        int with_norm, double *part, const double *skipc, int cst, hipStream_t s)
+{
+    return vdots_t(ch, nch, w, V, ldv, nvec, with_norm, part, skipc, cst, s);
+}
+hipError_t launch_vdots(const VChunk *ch, int nch, const double *w, const float *V, long long ldv, int nvec,
+                        int with_norm, double *part, const double *skipc, int cst, hipStream_t s)
+{
+    return vdots_t(ch, nch, w, V, ldv, nvec, with_norm, part, skipc, cst, s);
 }
 
 hipError_t launch_vsum(const int *slot_chunk0, const int *slot_nchunk, int nslots, const double *part, int nch,
@@ -269,7 +302,13 @@ hipError_t launch_vsum(const int *slot_chunk0, const int *slot_nchunk, int nslot
 hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const double *V, long long ldv, int nvec,
                           const double *coef, int cstride, double *vout, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vupdate, dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout);
+    hipLaunchKernelGGL((k_vupdate<double>), dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout);
+    return hipGetLastError();
+}
+hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
+                          const double *coef, int cstride, float *vout, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_vupdate<float>), dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout);
     return hipGetLastError();
 }
 
