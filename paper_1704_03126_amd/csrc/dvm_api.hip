@@ -1467,7 +1467,9 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             continue;
         Slot sl{i, n, 0, (int)(st[i].iter & 1)};
         sl.len = state_segments(c, i, sl.pw, n, nullptr, nullptr);
-        n += sl.len;
+        // slots (and with them every chunk) start on a multiple of 4
+        // elements: the basis kernels load 4 at a time
+        n += (sl.len + 3) & ~3LL;
         slots.push_back(sl);
     }
     const int ns = (int)slots.size();
@@ -1546,7 +1548,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
     // kept |w| above 1/sqrt(2) of its length get zero dots
     auto dots = [&](const double *w, int nv, bool norm, double *out, const double *skip = nullptr) -> int {
         const int nchl = (int)chunks.size();
-        HIPCHK(launch_vdots(kw.ch.p, nchl, w, kw.V.p, n, nv, norm ? 1 : 0, kw.part.p, skip, cst, c->stream));
+        HIPCHK(launch_vdots4(kw.ch.p, nchl, w, kw.V.p, n, nv, norm ? 1 : 0, kw.part.p, skip, cst, c->stream));
         HIPCHK(launch_vsum(kw.c0.p, kw.nc.p, ns, kw.part.p, nchl, nv + (norm ? 1 : 0), out, cst, c->stream));
         return DVM_OK;
     };
@@ -1643,7 +1645,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             hs[q].g[0] = hs[q].beta;
         }
         // V_0 = w / beta (coefficient row holds |w|^2 with no vectors)
-        HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, 0, kw.c1.p, cst, kw.V.p,
+        HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, 0, kw.c1.p, cst, kw.V.p,
                               c->stream));
         int k = 0;
         for (int j = 0; j < m; ++j) {
@@ -1656,11 +1658,11 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             // one cancelled more than half of |w|^2
             if ((rc = dots(kw.w.p, j + 1, true, kw.c1.p)))
                 return rc;
-            HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c1.p, cst, nullptr,
+            HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c1.p, cst, nullptr,
                                   c->stream));
             if ((rc = dots(kw.w.p, j + 1, true, kw.c2.p, kw.c1.p)))
                 return rc;
-            HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c2.p, cst,
+            HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c2.p, cst,
                                   kw.V.p + (size_t)(j + 1) * n, c->stream));
             HIPCHK(hipMemcpyAsync(hc1.data(), kw.c1.p, hc1.size() * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
@@ -1719,7 +1721,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             h.sig = sigma_min_tri(h.H, m + 1, k);
         }
         HIPCHK(hipMemcpyAsync(kw.y.p, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(launch_vupdate(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, k, kw.y.p, cst, nullptr, c->stream));
+        HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, k, kw.y.p, cst, nullptr, c->stream));
         if (trials && k > 0) {
             // a trial instance stays with GMRES while a cycle reduces its
             // residual at least 1.5 times faster per second than the plain

@@ -271,5 +271,12 @@ hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const double *V,
 // stay FP64
 hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
                           const double *coef, int cstride, float *vout, hipStream_t s);
+// FP32-basis projections and updates with 16-byte loads: every chunk must
+// start on a multiple of 4 elements and ldv be one (V, w, vout 16-byte
+// aligned; checked where the pointers allow, hipErrorInvalidValue otherwise)
+hipError_t launch_vdots4(const VChunk *ch, int nch, const double *w, const float *V, long long ldv, int nvec,
+                         int with_norm, double *part, const double *skipc, int cst, hipStream_t s);
+hipError_t launch_vupdate4(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
+                           const double *coef, int cstride, float *vout, hipStream_t s);
 
 } // namespace dvm

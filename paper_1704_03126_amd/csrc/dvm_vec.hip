@@ -4,6 +4,8 @@
 // deterministic inner products and updates of the Krylov (GMRES) driver.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "dvm_internal.h"
 
 namespace dvm {
@@ -176,6 +178,154 @@ __global__ void __launch_bounds__(256) k_vupdate(const VChunk *ch, double *w, co
     }
 }
 
+// FP32-basis variants for chunks that start on a multiple of 4 elements with
+// a leading dimension that is one too (the GMRES driver lays its vectors out
+// so): each thread takes groups of 4 consecutive elements with 16-byte loads
+// of the basis (float4) and of w (two double2); the last len % 4 elements of
+// a chunk go one by one.
+__global__ void __launch_bounds__(256) k_vdots4(const VChunk *ch, const double *w, const float *V, long long ldv,
+                                                int nvec, int with_norm, double *part, int nch,
+                                                const double *skipc, int cst)
+{
+    __shared__ double red[4][VROWS];
+    const VChunk c = ch[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r0 = blockIdx.y * VROWS;
+    const int nrows = nvec + (with_norm ? 1 : 0);
+    bool skip = false;
+    if (skipc) {
+        const double *cf = skipc + (size_t)c.slot * cst;
+        double s = 0.0;
+        for (int j = 0; j < nvec; ++j)
+            s = fma(cf[j], cf[j], s);
+        skip = s <= 0.5 * cf[nvec];
+    }
+    double acc[VROWS];
+#pragma unroll
+    for (int rr = 0; rr < VROWS; ++rr)
+        acc[rr] = 0.0;
+    const int ng = c.len >> 2;
+    for (int g = tid; g < ng; g += 256) {
+        const size_t e = (size_t)c.start + 4 * (size_t)g;
+        const double2 wa = *reinterpret_cast<const double2 *>(w + e);
+        const double2 wb = *reinterpret_cast<const double2 *>(w + e + 2);
+#pragma unroll
+        for (int rr = 0; rr < VROWS; ++rr) {
+            const int r = r0 + rr;
+            if (r < nvec) {
+                if (!skip) {
+                    const float4 v = *reinterpret_cast<const float4 *>(V + (size_t)r * ldv + e);
+                    acc[rr] = fma(wa.x, (double)v.x, acc[rr]);
+                    acc[rr] = fma(wa.y, (double)v.y, acc[rr]);
+                    acc[rr] = fma(wb.x, (double)v.z, acc[rr]);
+                    acc[rr] = fma(wb.y, (double)v.w, acc[rr]);
+                }
+            } else if (r < nrows) {
+                acc[rr] = fma(wa.x, wa.x, acc[rr]);
+                acc[rr] = fma(wa.y, wa.y, acc[rr]);
+                acc[rr] = fma(wb.x, wb.x, acc[rr]);
+                acc[rr] = fma(wb.y, wb.y, acc[rr]);
+            }
+        }
+    }
+    for (int i = 4 * ng + tid; i < c.len; i += 256) {
+        const double wi = w[c.start + i];
+#pragma unroll
+        for (int rr = 0; rr < VROWS; ++rr) {
+            const int r = r0 + rr;
+            if (r < nvec) {
+                if (!skip)
+                    acc[rr] = fma(wi, (double)V[(size_t)r * ldv + c.start + i], acc[rr]);
+            } else if (r < nrows) {
+                acc[rr] = fma(wi, wi, acc[rr]);
+            }
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < VROWS; ++rr) {
+        double s = acc[rr];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            s += __shfl_xor(s, o);
+        if (lane == 0)
+            red[wv][rr] = s;
+    }
+    __syncthreads();
+    if (tid < VROWS && r0 + tid < nrows)
+        part[(size_t)(r0 + tid) * nch + blockIdx.x] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
+__global__ void __launch_bounds__(256) k_vupdate4(const VChunk *ch, double *w, const float *V, long long ldv,
+                                                  int nvec, const double *coef, int cstride, float *vout)
+{
+    const VChunk c = ch[blockIdx.x];
+    const double *cf = coef + (size_t)c.slot * cstride;
+    double inv = 0.0;
+    if (vout) {
+        double n2 = cf[nvec];
+        for (int j = 0; j < nvec; ++j)
+            n2 -= cf[j] * cf[j];
+        inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+    }
+    const int ng = c.len >> 2;
+    for (int g = threadIdx.x; g < ng; g += 256) {
+        const size_t e = (size_t)c.start + 4 * (size_t)g;
+        const double2 wa = *reinterpret_cast<const double2 *>(w + e);
+        const double2 wb = *reinterpret_cast<const double2 *>(w + e + 2);
+        double a0 = wa.x, a1 = wa.y, a2 = wb.x, a3 = wb.y;
+        int j = 0;
+        for (; j + 8 <= nvec; j += 8) {
+            double cj[8];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cj[u] = cf[j + u];
+                any = any || cj[u] != 0.0;
+            }
+            if (!any)
+                continue;
+            float4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = *reinterpret_cast<const float4 *>(V + (size_t)(j + u) * ldv + e);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a0 = fma(-cj[u], (double)v[u].x, a0);
+                a1 = fma(-cj[u], (double)v[u].y, a1);
+                a2 = fma(-cj[u], (double)v[u].z, a2);
+                a3 = fma(-cj[u], (double)v[u].w, a3);
+            }
+        }
+        for (; j < nvec; ++j) {
+            const double cj = cf[j];
+            if (cj != 0.0) {
+                const float4 v = *reinterpret_cast<const float4 *>(V + (size_t)j * ldv + e);
+                a0 = fma(-cj, (double)v.x, a0);
+                a1 = fma(-cj, (double)v.y, a1);
+                a2 = fma(-cj, (double)v.z, a2);
+                a3 = fma(-cj, (double)v.w, a3);
+            }
+        }
+        *reinterpret_cast<double2 *>(w + e) = make_double2(a0, a1);
+        *reinterpret_cast<double2 *>(w + e + 2) = make_double2(a2, a3);
+        if (vout)
+            *reinterpret_cast<float4 *>(vout + e) =
+                make_float4((float)(a0 * inv), (float)(a1 * inv), (float)(a2 * inv), (float)(a3 * inv));
+    }
+    for (int i = 4 * ng + threadIdx.x; i < c.len; i += 256) {
+        const size_t e = c.start + i;
+        double acc = w[e];
+        for (int j = 0; j < nvec; ++j) {
+            const double cj = cf[j];
+            if (cj != 0.0)
+                acc = fma(-cj, (double)V[(size_t)j * ldv + e], acc);
+        }
+        w[e] = acc;
+        if (vout)
+            vout[e] = (float)(acc * inv);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_state32(const VSeg2 *seg, const SolveState *st, StateBufs32 b,
                                                  double *vec, int what)
 {
@@ -303,6 +453,29 @@ hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const double *V,
                           const double *coef, int cstride, double *vout, hipStream_t s)
 {
     hipLaunchKernelGGL((k_vupdate<double>), dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout);
+    return hipGetLastError();
+}
+hipError_t launch_vdots4(const VChunk *ch, int nch, const double *w, const float *V, long long ldv, int nvec,
+                         int with_norm, double *part, const double *skipc, int cst, hipStream_t s)
+{
+    const int nrows = nvec + (with_norm ? 1 : 0);
+    if (nrows == 0 || nch == 0)
+        return hipSuccess;
+    if (ldv % 4 != 0 || reinterpret_cast<uintptr_t>(V) % 16 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vdots4, dim3(nch, (nrows + VROWS - 1) / VROWS), dim3(256), 0, s, ch, w, V, ldv, nvec,
+                       with_norm, part, nch, skipc, cst);
+    return hipGetLastError();
+}
+hipError_t launch_vupdate4(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
+                           const double *coef, int cstride, float *vout, hipStream_t s)
+{
+    if (nch == 0)
+        return hipSuccess;
+    if (ldv % 4 != 0 || reinterpret_cast<uintptr_t>(V) % 16 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(vout) % 16 != 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vupdate4, dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout);
     return hipGetLastError();
 }
 hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
