@@ -358,3 +358,77 @@ def test_gradient_dense_adjoint_vs_finite_difference():
           dn.solve(m, dl, 6, periodic_y=True, alpha=alpha - ea).Q) / (2 * ea)
     assert abs(adj.dQ_dalpha - fd) < 1e-6 * abs(fd)
     assert np.all(adj.dQ_ddelta[m == 1] == 0)
+
+
+# ------------------------------------------------- shear stress, temperature
+def test_shear_stress_momentum_balance():
+    """Shear stress P12 = 2 int v1 v2 h f_eq (Sec. II.A moments) in the
+    x-invariant channel.  Summing the x-momentum of Eq. (BGK) over velocities
+    (the collision term conserves momentum) leaves dP12/dy = 2 int v1^2 f_eq
+    = 2 m2 times the unit pressure gradient: P12 is the straight line
+    2 m2 (y - 1/2), odd about the centreline.  The cell-centred values of the
+    discrete solution approach that line under refinement, the slope at second
+    order.  A factor, sign or index slip in P12 (v1 v1, v2 v2, a lost 2) fails
+    the slope, the sign or the symmetry."""
+    m2 = oracle.quadrature(16).m2
+    slope_err, dev = [], []
+    for ny in (16, 32, 64, 128):
+        g = plane_channel(ny)
+        r = oracle.si_solve(g.mask, 1.0, 16, tol=1e-13)
+        assert r.converged
+        p = r.p12[:, 0]
+        y = (np.arange(ny) + 0.5) / ny
+        assert np.max(np.abs(p + p[::-1])) < 1e-14        # odd about y = 1/2
+        slope = np.polyfit(y - 0.5, p, 1)[0]
+        slope_err.append(abs(slope / (2.0 * m2) - 1.0))
+        dev.append(np.max(np.abs(p - 2.0 * m2 * (y - 0.5))))
+        assert np.all(np.sign(p[: ny // 2]) == -1.0)      # below the centreline: negative
+    assert slope_err[2] < 3e-3 and slope_err[3] < 1e-3
+    for a, b in zip(slope_err, slope_err[1:]):
+        assert a / b > 3.0                                  # second order
+    assert all(a > b for a, b in zip(dev, dev[1:]))
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_temperature_density_shear_against_direct_solve(case):
+    """rho, tau and P12 of the source iteration against the same moments
+    taken, by their definitions in Sec. II.A, from the perturbation h of the
+    independent direct solve: rho = sum W h (gauge: zero fluid mean),
+    tau = sum W |v|^2 h - rho, P12 = 2 sum W xi eta h.  Asymmetric geometries
+    (a rough channel with blocks on one wall, porous cells, Maxwell walls)
+    where all three are far from zero."""
+    rng = np.random.default_rng(400 + case)
+    if case == 0:
+        m = rough_channel(10, 8, 2, 5).mask.copy()
+        m[6:, :] = 0                          # blocks on the bottom wall only
+        args = dict(periodic_y=False, alpha=1.0)
+        dl, nv = 0.8, 6
+    elif case == 1:
+        m, dl, nv, args = _tiny_porous(21, n=8), 1.5, 6, dict(periodic_y=True, alpha=1.0)
+    elif case == 2:
+        m = _tiny_porous(22, n=8)
+        dl, nv, args = np.exp(0.3 * rng.standard_normal(m.shape)), 6, dict(periodic_y=True, alpha=0.7)
+    else:
+        m = np.zeros((7, 9), dtype=np.uint8)
+        m[0:3, 3:5] = 1
+        m[5, 6] = 1
+        dl, nv, args = 0.4, 8, dict(periodic_y=False, alpha=0.85)
+    s = oracle.si_solve(m, dl, nv, tol=1e-14, **args)
+    d = dn.solve(m, dl, nv, **args)
+    assert s.converged
+    q = dn.quad(nv)
+    W, xi, eta = q["W"], q["xi"], q["eta"]
+    h = d.h                                   # (fluid cells, velocities)
+    rho = h @ W                               # zero fluid mean: the direct solve's border row
+    assert abs(rho.mean()) < 1e-13
+    e = h @ (W * (xi ** 2 + eta ** 2))
+    tau = e - rho
+    p12 = 2.0 * (h @ (W * xi * eta))
+    fl = np.array(d.sys.fluid)
+    ys, xs = fl[:, 0], fl[:, 1]
+    assert np.max(np.abs(tau)) > 1e-3 and np.max(np.abs(p12)) > 1e-3
+    assert np.max(np.abs(s.rho[ys, xs] - rho)) < 1e-11
+    assert np.max(np.abs(s.tau[ys, xs] - tau)) < 1e-11
+    assert np.max(np.abs(s.p12[ys, xs] - p12)) < 1e-11
+    solid = m != 0
+    assert np.all(s.tau[solid] == 0.0) and np.all(s.p12[solid] == 0.0)
