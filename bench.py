@@ -1,18 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the gfx950 linearized-BGK DVM solver (one JSON line).
 
-Workload: the rough-surface channel -- a periodic cell 2H x H at 256 x 128
-cells with rectangular blocks 0.2H high over half the period on both walls,
-64 x 64 velocities of Eq. (nonuniform_v), delta in {0.1, 1, 10}.  One step is
-the whole hot path on that input: the source iteration of Eq. (iteration)
-run to the stop rule (relative change of u1, tolerance 1e-8 with the
-a-posteriori bound) for each of the three delta values, followed by the flow
-rate Q.  Inputs (geometry tables) are resident on the GPU before timing.
+Default workload: the uneven batch -- 64 independent instances (seeded
+periodic porous cells and rough channels, sides 64-384 cells, delta
+log-uniform on [0.01, 100]), 48 x 48 velocities of Eq. (nonuniform_v), all
+in one context and one batched launch sequence, solved by FP32 sweeps with
+FP64 moments and FP64 defect correction.  One step = one batched solve of
+every instance from zero for a fixed budget of source iterations (32 by
+default: a captured block of Eq. (iteration)), followed by the flow rate Q
+of Sec. III of every instance.  Inputs (geometry tables) are resident on the
+GPU before timing.
 
-Reported: fluid-cell x velocity updates per second over the timed steps,
-time to the converged flow rate per delta, the roofline of the dominant
-kernel (the sweep) measured with HIP events on the solver's stream, and the
-CPU oracle timed on the host on a bounded sample of the same workload.
+Reported on one line:
+* value: fluid-cell x velocity updates per second over the timed steps (FP32
+  and FP64 sweeps counted alike);
+* roofline: algorithmic HBM bytes of the dominant kernel (the FP32 sweep:
+  4 bytes per update -- one FP32 state element per fluid cell and velocity)
+  over its average launch time, measured with HIP events on the solver's
+  stream during the timed steps, against 8 TB/s; the FP64 sweeps of the
+  same steps (8 bytes per update) and the profiler-measured bytes alongside;
+* time to the converged flow rate (tol 1e-6) of the whole batch for FP32 +
+  refinement and for the FP64 solver, each once after the timed steps, with
+  Q's distance from the stored FP64 oracle results of four instances;
+* cpu_baseline: the FP64 CPU oracle on a bounded sample of the same batch
+  (all host cores, and one core).
+
+Other workloads (--workload): rough_channel, couette, porous, adjoint.
 """
 from __future__ import annotations
 
@@ -32,11 +45,19 @@ METRIC = ("cell×velocity updates/s + % HBM peak; "
 DELTAS = (0.1, 1.0, 10.0)
 NV = 64
 TOL = 1e-8
+HBM_PEAK = 8.0e12                 # MI355X HBM3E bytes/s
 FP64_VALU_PEAK = 78.6e12          # MI355X FP64 vector FLOP/s
 # arithmetic the sweep performs per fluid cell x velocity update (FMA = 2):
 # collision gain 3 FMA, upwind terms 2 x 2 FMA, combination 2 FMA,
 # reciprocal-diagonal scaling 1 MUL, quadrature moments 1 MUL + 1 ADD + 3 FMA
 FLOPS_PER_UPDATE = 6 + 8 + 4 + 1 + 8
+# algorithmic HBM bytes per fluid cell x velocity update of a sweep that
+# produces one state element per update and fuses the moments: the element
+# itself, 8 bytes in FP64 and 4 in FP32 (the moments, records and lagged
+# values add well under a byte per update)
+BYTES_PER_UPDATE = {"fp64": 8, "fp32": 4}
+BATCH_NV = 48
+BATCH_TTS_TOL = 1e-6
 
 
 def parse():
@@ -44,22 +65,28 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--precision", choices=["fp64", "fp32_refine"], default="fp64",
-                   help="fp64 sweeps, or FP32 sweeps with FP64 defect correction")
+    p.add_argument("--precision", choices=["fp64", "fp32_refine"], default=None,
+                   help="fp64 sweeps, or FP32 sweeps with FP64 defect correction (default: "
+                        "fp32_refine for batch64, fp64 for the other workloads)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="budget of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--workload", choices=["rough_channel", "batch64", "couette", "porous", "adjoint"], default="rough_channel",
-                   help="rough_channel: the headline workload; batch64: 64 uneven instances "
-                        "(sides 64-384, 48 x 48 velocities) in one batched solve, throughput over a "
-                        "fixed number of iterations; couette: the Couette flow of the fractal rough "
+    p.add_argument("--workload", choices=["rough_channel", "batch64", "couette", "porous", "adjoint"], default="batch64",
+                   help="batch64 (default): 64 uneven instances (sides 64-384, 48 x 48 velocities) "
+                        "in one batched solve, throughput over a fixed number of iterations per step "
+                        "and time to solution of the batch; rough_channel: the 256 x 128 rough channel "
+                        "at delta 0.1, 1, 10 to the stop rule; couette: the Couette flow of the fractal rough "
                         "channel and the smooth one over Kn 0.03-10 (Q*); porous: the rarefaction "
                         "sweep of the 512 x 512 porous cell (8 deltas over 0.01-100, warm starts) "
                         "and its permeability post-processing; adjoint: forward solve and gradient "
                         "of the 256 x 256 porous cell with delta(x) and alpha 0.9")
-    p.add_argument("--batch-iters", type=int, default=24,
+    p.add_argument("--batch-iters", type=int, default=32,
                    help="iterations per timed batched solve (batch64); 0: every instance "
                         "to the stop rule")
+    p.add_argument("--no-tts", action="store_true",
+                   help="batch64: skip the time-to-solution runs (for profiler runs)")
+    p.add_argument("--tts-tol", type=float, default=BATCH_TTS_TOL,
+                   help="batch64: stop-rule tolerance of the time-to-solution runs")
     p.add_argument("--schedule", choices=["auto", "skew", "wrap"], default="auto",
                    help="sweep order: auto (wrap-around diagonal, skewed order for instances "
                         "that stop contracting), skew (lags periodic/strip seams only) or "
@@ -68,7 +95,7 @@ def parse():
                    help="auto: source iteration with extrapolation of its dominant mode, GMRES for "
                         "an instance that stops contracting; none: plain source iteration (the "
                         "paper's); gmres: GMRES on its fixed-point map")
-    p.add_argument("--tol", type=float, default=TOL,
+    p.add_argument("--tol", type=float, default=None,
                    help="stop-rule tolerance of every solve (relative change of u1 and its "
                         "a-posteriori error bound)")
     p.add_argument("--block-iters", type=int, default=32,
@@ -88,6 +115,10 @@ def parse():
 
 def main():
     args = parse()
+    if args.precision is None:
+        args.precision = "fp32_refine" if args.workload == "batch64" else "fp64"
+    if args.tol is None:
+        args.tol = TOL
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
                           "the solver has no multi-GPU path", "n_gpus": args.gpus}))
@@ -157,9 +188,9 @@ def main():
     roofline = None
     if not args.no_roofline:
         # roofline of the sweep: one more step with every sweep bracketed by
-        # HIP events on the solver's stream
+        # HIP events on the solver's stream, in the same precision
         prof = dvm.Solver(NV, 1, tol=args.tol, profile=True, vel_per_lane=args.vel,
-                          waves_per_block=args.waves, **solver_options(args, dvm))
+                          waves_per_block=args.waves, precision=prec, **solver_options(args, dvm))
         prof.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
         prof_sched = set()
         prof_iters = 0
@@ -167,36 +198,43 @@ def main():
             pinfo = prof.solve(0, d)
             prof_sched.add(pinfo.schedule)
             prof_iters += pinfo.iters
-        sweep_ms, n_sweeps, other_ms = prof.profile()
-        (pv, pg), _ = prof.launch_shape()
+        p = prof.profile()
+        (pv, pg), (pv32, pg32) = prof.launch_shape()
         prof.close()
-        kernel_sched = prof_sched.pop() if len(prof_sched) == 1 else "mixed" 
-        avg_sweep_s = sweep_ms / max(n_sweeps, 1) / 1e3
-        flops_per_launch = float(nf) * K * FLOPS_PER_UPDATE
-        achieved = flops_per_launch / avg_sweep_s
+        kernel_sched = prof_sched.pop() if len(prof_sched) == 1 else "mixed"
+        f32 = p["n_sweeps32"] > 0 and p["sweep32_ms"] >= p["sweep_ms"]
+        leg = "fp32" if f32 else "fp64"
+        ms, n, upd = ((p["sweep32_ms"], p["n_sweeps32"], p["updates32"]) if f32
+                      else (p["sweep_ms"], p["n_sweeps"], p["updates"]))
+        avg_sweep_s = ms / max(n, 1) / 1e3
+        bytes_per_launch = BYTES_PER_UPDATE[leg] * upd / max(n, 1)
+        achieved = bytes_per_launch / avg_sweep_s
         traffic = None
         traffic_detail = None
-        tr = None
         if args.traffic_json:
             with open(args.traffic_json) as f:
                 tr = json.load(f)
         else:
-            tr = measured_traffic(kernel_sched, pv, pg)
+            tr = measured_traffic("rough_channel", leg, pv32 if f32 else pv, pg32 if f32 else pg,
+                                  schedule=kernel_sched)
         if tr is not None:
             traffic = tr["fetch_bytes"] + tr["write_bytes"]
             traffic_detail = {"fetch_bytes_per_launch": tr["fetch_bytes"],
                               "write_bytes_per_launch": tr["write_bytes"],
-                              "bytes_per_update": traffic / (nf * K),
-                              "hbm_GBps_at_avg_launch": traffic / avg_sweep_s / 1e9,
+                              "measured_over_algorithmic": traffic / bytes_per_launch,
                               "source": tr.get("source", "")}
-        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": traffic,
+        flops = float(upd / max(n, 1)) * FLOPS_PER_UPDATE / avg_sweep_s
+        roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
                     "traffic_detail": traffic_detail,
-                    "kernel": f"k_sweep<double,{pv},{pg}> ({kernel_sched} order)",
-                    "avg_launch_ms": avg_sweep_s * 1e3,
-                    "flops_per_update": FLOPS_PER_UPDATE, "updates_per_launch": nf * K,
-                    "launches_timed": n_sweeps, "iterations_timed": prof_iters,
-                    "sweep_share_of_iteration": sweep_ms / max(sweep_ms + other_ms, 1e-30)}
+                    "kernel": (f"k_sweep<{'float' if f32 else 'double'},{pv32 if f32 else pv},"
+                               f"{pg32 if f32 else pg}> ({kernel_sched} order)"),
+                    "avg_launch_ms": avg_sweep_s * 1e3, "bytes_per_update": BYTES_PER_UPDATE[leg],
+                    "updates_per_launch": upd / max(n, 1), "launches_timed": n,
+                    "iterations_timed": prof_iters,
+                    "valu": {"flops_per_update": FLOPS_PER_UPDATE, "achieved_TFLOPs": flops / 1e12,
+                             "frac_of_fp64_vector_peak": flops / FP64_VALU_PEAK},
+                    "sweep_share_of_iteration": p["sweep_ms"] / max(p["sweep_ms"] + p["other_ms"], 1e-30)}
 
     cpu = None
     if not args.no_cpu:
@@ -213,7 +251,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
                    "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
@@ -257,53 +295,158 @@ def stored_oracle_error(g, Qs):
 
 
 def bench_batch(args, torch, dvm):
-    """64 uneven instances (seeded rough channels and porous cells, sides
-    64-384, delta log-uniform on [0.01, 100]), 48 x 48 velocities, all in one
-    batched launch sequence; every timed solve runs a fixed number of
-    iterations (instances converge at very different counts, so throughput
-    over a fixed budget is the comparable figure), or, with --batch-iters 0,
-    runs every instance to the stop rule (time to solution of the batch)."""
+    """The uneven batch: 64 seeded instances (even i: s x s porous cell of
+    porosity 0.6; odd i: s x s/2 rough channel; s uniform on 64..384; delta
+    log-uniform on [0.01, 100]), 48 x 48 velocities, one context, one
+    batched launch sequence.  A step solves every instance from zero for
+    --batch-iters source iterations (FP32 correction sweeps and FP64 steps
+    of the refinement alike) and reads every Q; with --batch-iters 0 a step
+    runs every instance to the stop rule."""
     from paper_1704_03126_amd.geometry import batch_instances
-    nv = 48
+    nv = BATCH_NV
+    K = nv * nv
     gs = batch_instances(64)
     deltas = [g.meta["delta"] for g in gs]
+    nfl = [g.n_fluid for g in gs]
     prec = dvm.DVM_FP32_REFINE if args.precision == "fp32_refine" else dvm.DVM_FP64
     to_conv = args.batch_iters <= 0
-    s = dvm.Solver(nv, len(gs), tol=args.tol, max_iter=100000 if to_conv else args.batch_iters,
-                   vel_per_lane=args.vel or 4, waves_per_block=args.waves or 8, precision=prec,
+    vel, waves = args.vel or 4, args.waves or 8
+    prof_on = not args.no_roofline
+    s = dvm.Solver(nv, len(gs), tol=args.tol, max_iter=200000 if to_conv else args.batch_iters,
+                   vel_per_lane=vel, waves_per_block=waves, precision=prec, profile=prof_on,
                    **solver_options(args, dvm))
     for i, g in enumerate(gs):
         s.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
-    nfl = [g.n_fluid for g in gs]
-    for _ in range(max(args.warmup, 1)):
-        s.solve(-1, deltas, raise_on_noconv=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    updates = 0.0
-    for _ in range(args.steps):
+
+    def step():
         infos = s.solve(-1, deltas, raise_on_noconv=False)
-        updates += sum(inf.iters * n for inf, n in zip(infos, nfl)) * nv * nv
+        Qs = [s.flow_rate(i)[0] for i in range(len(gs))]
+        return infos, Qs
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    if prof_on:
+        s.profile()                       # timings of the timed steps only
+    t0 = time.perf_counter()
+    updates, sweeps32, sweeps64 = 0.0, 0, 0
+    for _ in range(args.steps):
+        infos, Qs = step()
+        updates += sum(inf.iters * n for inf, n in zip(infos, nfl)) * K
+        sweeps64 += sum(inf.sweeps_fp64 for inf in infos)
+        sweeps32 += sum(inf.iters - inf.sweeps_fp64 for inf in infos)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    Qs = [s.flow_rate(i)[0] for i in range(len(gs))] if to_conv else None
+    prof = s.profile() if prof_on else None
     s.close()
+
+    roofline = batch_roofline(prof, vel, waves, args) if prof else None
+    tts = None if args.no_tts else batch_time_to_solution(args, torch, dvm, gs, deltas, vel, waves)
+    cpu = None if args.no_cpu else cpu_baseline_batch(gs, nv, args.cpu_seconds)
+    prec_name = "fp32_refine" if prec == dvm.DVM_FP32_REFINE else "fp64"
     out = {"metric": METRIC, "value": updates / elapsed, "unit": "updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == dvm.DVM_FP64 else "f32+f64", "data": "synthetic",
-           "config": {"workload": "batch64_uneven_sides64-384_nv48", "instances": len(gs),
-                      "cells": int(sum(g.nx * g.ny for g in gs)), "fluid_cells": int(sum(nfl)),
-                      "velocities": nv * nv,
-                      "iterations_per_solve": "to the stop rule" if to_conv else args.batch_iters,
-                      "tol": args.tol if to_conv else None, "precision": args.precision,
-                      "schedule": args.schedule, "accel": args.accel, "parallelism": "single_gpu"},
-           "roofline": None, "cpu_baseline": None}
+           "dtype": "f64" if prec == dvm.DVM_FP64 else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "batch64_uneven_porous+rough_sides64-384_delta0.01-100_nv48",
+                      "instances": len(gs), "cells": int(sum(g.nx * g.ny for g in gs)),
+                      "fluid_cells": int(sum(nfl)), "velocities": K,
+                      "iterations_per_step": "to the stop rule" if to_conv else args.batch_iters,
+                      "tol": args.tol if to_conv else None, "precision": prec_name,
+                      "launch_shape": [vel, waves], "schedule": args.schedule, "accel": args.accel,
+                      "parallelism": "single_gpu"},
+           "sweeps_per_step": {"fp32": sweeps32 // max(args.steps, 1), "fp64": sweeps64 // max(args.steps, 1)},
+           "roofline": roofline, "time_to_solution": tts, "cpu_baseline": cpu}
     if to_conv:
         out["iterations_per_instance"] = [inf.iters for inf in infos]
         out["status_per_instance"] = [inf.status for inf in infos]
-        out["delta_per_instance"] = deltas
-        out["Q"] = Qs
+        out["Q_rel_err_vs_stored_oracle"] = batch_oracle_error(Qs)
     print(json.dumps(out))
+
+
+def batch_roofline(prof, vel, waves, args):
+    """Roofline of the dominant kernel of the timed steps: the sweep (FP32 in
+    the refinement, else FP64), algorithmic bytes (BYTES_PER_UPDATE x fluid
+    updates of the timed launches) over the launches' total event time."""
+    legs = {}
+    for name, ms, n, upd in (("fp64", prof["sweep_ms"], prof["n_sweeps"], prof["updates"]),
+                             ("fp32", prof["sweep32_ms"], prof["n_sweeps32"], prof["updates32"])):
+        if n == 0 or ms <= 0:
+            continue
+        t = ms / 1e3
+        bpl = BYTES_PER_UPDATE[name] * upd / n
+        legs[name] = {"launches": n, "avg_launch_ms": ms / n, "updates": upd,
+                      "algorithmic_bytes_per_launch": bpl,
+                      "achieved_GBps": BYTES_PER_UPDATE[name] * upd / t / 1e9,
+                      "updates_per_s": upd / t, "time_ms": ms}
+    if not legs:
+        return None
+    dom = max(legs, key=lambda k: legs[k]["time_ms"])
+    d = legs[dom]
+    tr = measured_traffic("batch64", dom, vel, waves)
+    traffic = None
+    detail = None
+    if tr is not None:
+        traffic = tr["fetch_bytes"] + tr["write_bytes"]
+        detail = {"fetch_bytes_per_launch": tr["fetch_bytes"], "write_bytes_per_launch": tr["write_bytes"],
+                  "measured_over_algorithmic": traffic / d["algorithmic_bytes_per_launch"],
+                  "source": tr.get("source", "")}
+    return {"bound": "hbm", "achieved": d["achieved_GBps"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": d["achieved_GBps"] * 1e9 / HBM_PEAK, "traffic": traffic, "traffic_detail": detail,
+            "kernel": f"k_sweep<{'float' if dom == 'fp32' else 'double'},{vel},{waves}>",
+            "bytes_per_update": BYTES_PER_UPDATE[dom], "legs": legs,
+            "timing": "HIP events around every sweep launch on the solver's stream, timed steps only"}
+
+
+def batch_oracle_error(Qs):
+    """|Q - Q_oracle| / |Q_oracle| for the instances with stored FP64 oracle
+    results (tests/golden/batch64_subset_nv48.json, solved to 1e-12)."""
+    path = os.path.join(ROOT, "tests", "golden", "batch64_subset_nv48.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f)
+    return {str(r["index"]): abs(Qs[r["index"]] - r["Q"]) / abs(r["Q"]) for r in ref["instances"]}
+
+
+def batch_time_to_solution(args, torch, dvm, gs, deltas, vel, waves):
+    """Time to the converged flow rate of the whole batch at --tts-tol: FP32
+    sweeps with FP64 refinement against the FP64 solver (AUTO acceleration
+    both, and the FP64 plain source iteration), each once, with Q's error
+    against the stored oracle results and between the two precisions."""
+    runs = {}
+    Qref = None
+    for name, prec, accel in (("fp32_refine", dvm.DVM_FP32_REFINE, dvm.DVM_ACCEL_AUTO),
+                              ("fp64", dvm.DVM_FP64, dvm.DVM_ACCEL_AUTO),
+                              ("fp64_plain_iteration", dvm.DVM_FP64, dvm.DVM_ACCEL_NONE)):
+        s = dvm.Solver(BATCH_NV, len(gs), tol=args.tts_tol, max_iter=200000, precision=prec, accel=accel,
+                       vel_per_lane=vel, waves_per_block=waves, block_iters=args.block_iters)
+        for i, g in enumerate(gs):
+            s.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
+        s.solve(1, deltas[1])             # layout, buffers and captured blocks, outside the timing
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = s.solve(-1, deltas, raise_on_noconv=False)
+        Qs = [s.flow_rate(i)[0] for i in range(len(gs))]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        conv = [inf.status == "converged" for inf in infos]
+        r = {"seconds": dt, "converged": int(sum(conv)), "status": [inf.status for inf in infos],
+             "sweeps_total": int(sum(inf.iters for inf in infos)),
+             "sweeps_fp64_total": int(sum(inf.sweeps_fp64 for inf in infos)),
+             "sweeps_max": int(max(inf.iters for inf in infos)),
+             "Q_rel_err_vs_stored_oracle": batch_oracle_error(Qs)}
+        if name == "fp32_refine":
+            Qref = Qs
+        elif Qref is not None:
+            r["max_rel_Q_diff_vs_fp32_refine"] = max(
+                abs(a - b) / abs(b) for a, b, ok in zip(Qref, Qs, conv) if ok)
+        runs[name] = r
+    runs["tol"] = args.tts_tol
+    runs["speedup_fp32_refine_vs_fp64"] = runs["fp64"]["seconds"] / runs["fp32_refine"]["seconds"]
+    return runs
 
 
 def bench_couette(args, torch, dvm):
@@ -474,24 +617,69 @@ def bench_adjoint(args, torch, dvm):
     print(json.dumps(out))
 
 
-def measured_traffic(schedule, vel, waves):
+def measured_traffic(workload, precision, vel, waves, schedule=None):
     """Profiler-measured HBM bytes per sweep launch (profiles/), valid only
-    while the kernel source, the sweep order and the launch shape are the
-    ones that were profiled."""
+    while the kernel source, the workload, the sweep precision, order and
+    launch shape are the ones that were profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sweep_traffic.json")
     src = os.path.join(ROOT, "paper_1704_03126_amd", "csrc", "dvm_kernels.hip")
     if not (os.path.exists(path) and os.path.exists(src)):
         return None
     with open(path) as f:
-        tr = json.load(f)
+        entries = json.load(f)
+    if isinstance(entries, dict):
+        entries = [entries]
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if not sha.startswith(tr.get("kernel_source_sha256_prefix", "-")):
-        return None
-    if tr.get("schedule") != schedule or tr.get("shape") != [vel, waves]:
-        return None
-    return tr
+    for tr in entries:
+        if not sha.startswith(tr.get("kernel_source_sha256_prefix", "-")):
+            continue
+        if tr.get("workload_key", "rough_channel") != workload:
+            continue
+        if tr.get("precision", "fp64") != precision or tr.get("shape") != [vel, waves]:
+            continue
+        if schedule is not None and tr.get("schedule") != schedule:
+            continue
+        return tr
+    return None
+
+
+def cpu_baseline_batch(gs, nv, budget_s):
+    """The CPU oracle (FP64 source iteration, OpenMP over velocities) on a
+    bounded sample of the batch: a fixed number of iterations of its largest
+    instance on every host core, and of a small instance on one core, each
+    scaled to about half of `budget_s`."""
+    import oracle
+    oracle.build(force=False)
+
+    def timed(g, n):
+        t0 = time.perf_counter()
+        oracle.si_solve(g.mask, g.meta["delta"], nv, periodic_y=g.periodic_y, cells_per_H=g.cells_per_H,
+                        tol=-1.0, max_iter=n)
+        return time.perf_counter() - t0
+
+    def sample(i, budget):
+        g = gs[i]
+        t1, t3 = timed(g, 1), timed(g, 3)
+        it_s = max((t3 - t1) / 2.0, 1e-4)
+        n = max(2, int(max(budget - t1 + it_s, it_s) / it_s))
+        dt = timed(g, n)
+        return n * g.n_fluid * nv * nv / dt, n, dt, g
+
+    cores = oracle.num_threads()
+    big = max(range(len(gs)), key=lambda i: gs[i].n_fluid)
+    small = min(range(len(gs)), key=lambda i: gs[i].n_fluid)
+    ups, n, dt, g = sample(big, 0.5 * budget_s)
+    oracle.set_num_threads(1)
+    ups1, n1, dt1, g1 = sample(small, 0.5 * budget_s)
+    oracle.set_num_threads(cores)
+    return {"value": ups, "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} source iterations of batch instance {big} ({g.nx}x{g.ny} cells, "
+                      f"{g.n_fluid} fluid, delta {g.meta['delta']:.4g}, {nv}x{nv} velocities), {dt:.1f} s",
+            "one_core": {"value": ups1, "unit": "updates/s", "cores": 1,
+                         "sample": f"{n1} source iterations of batch instance {small} ({g1.nx}x{g1.ny} "
+                                   f"cells, {g1.n_fluid} fluid), {dt1:.1f} s"}}
 
 
 def cpu_baseline(g, budget_s):

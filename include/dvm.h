@@ -62,7 +62,10 @@ extern "C" {
                                iteration stops contracting, and is tried on
                                one that contracts slowly (q > 0.98 with over
                                1000 iterations to go), kept while each cycle
-                               beats 1.5 x the plain rate per second; with
+                               reduces the residual 1.5 x faster than the
+                               plain iteration per unit of work (sweeps, the
+                               orthogonalisation counted in sweep
+                               equivalents: deterministic); with
                                DVM_FP32_REFINE an FP32 correction iteration
                                slower than q = 0.995 continues in FP64      */
 #define DVM_ACCEL_NONE 1    /* plain source iteration only (the paper's)      */
@@ -146,20 +149,45 @@ typedef struct {
                                or DVM_SCHED_WRAP                              */
 } dvm_info;
 
+/* Device allocator hooks of dvm_create: alloc(bytes, ud) returns device
+ * memory of at least `bytes` bytes aligned to 256 bytes (NULL on failure, which
+ * the calling entry point reports as DVM_ENOMEM); free_(ptr, ud) releases
+ * it.  Both may be called from any entry point that touches the device
+ * (dvm_solve, dvm_solve_warm, dvm_get_moments, dvm_grad) and from dvm_destroy,
+ * on the calling thread.  Memory is used on the context's stream only. */
+typedef void *(*dvm_alloc_fn)(size_t bytes, void *ud);
+typedef void (*dvm_free_fn)(void *ptr, void *ud);
+
 /* Create a context for n_instances independent problems sharing one
  * velocity grid of nv x nv nodes, Eq. (nonuniform_v) (nv even, 4 <= nv <= 128).
- * hip_stream: a hipStream_t, or NULL for the default stream.
- * On success *out receives the context. */
+ * hip_stream: a hipStream_t, or NULL for a stream of the library's own.
+ * alloc / free_ / alloc_ud: where every device buffer of the context comes
+ * from (e.g. a framework's caching allocator); both NULL: hipMalloc/hipFree.
+ * Exactly one of alloc and free_ NULL is DVM_EINVAL.  The context keeps the
+ * two function pointers and alloc_ud (not dereferenced) until dvm_destroy.
+ * On success *out receives the context; no device work happens here. */
 int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg,
-               void *hip_stream);
+               void *hip_stream, dvm_alloc_fn alloc, dvm_free_fn free_,
+               void *alloc_ud);
 
 /* Describe instance `instance` (0-based): an nx x ny staircase geometry,
- * solid[ny*nx] (1 = solid, 0 = fluid), periodic_y = 1 for periodic cells,
- * 0 for walls on the outer y faces.  nx == 1 means invariant along x
- * (plane channel); otherwise nx >= 4; ny >= 4.  Every fluid component must
- * carry flux along x (wrap around the x period); fully enclosed pores are
- * rejected with DVM_EINVAL.  Replaces any previous geometry of the instance
- * and discards its solution. */
+ * the "stair case" approximation of the solid surface of Sec. II.A (every
+ * solid cell is a square of side 1 / cells_per_H; the faces it shares with
+ * fluid cells are diffuse walls, Eq. (diffuse2)), with the periodic inlet and
+ * outlet along x of Sec. II.A and Sec. III.
+ *   solid[ny*nx]: host array, row-major (row y = 0 first), 1 = solid,
+ *     0 = fluid; any other value is DVM_EINVAL.  Copied during the call.
+ *   periodic_y: 1 for a periodic unit cell (the porous media of Sec. III),
+ *     0 for a channel with walls on the outer y faces (Sec. II and the rough
+ *     channel).
+ *   cells_per_H: cells per reference length H (> 0, finite); the flow rate
+ *     and rarefaction parameter are in units of H.
+ * nx == 1 means invariant along x (plane channel); otherwise nx >= 4;
+ * ny >= 4.  Every fluid component must carry flux along x (wrap around the x
+ * period); fully enclosed pores are rejected with DVM_EINVAL (the problem
+ * would have one null mode per pore).  Errors leave the instance as it was.
+ * Replaces any previous geometry of the instance and discards its solution;
+ * the device layout is rebuilt at the next solve. */
 int dvm_set_geometry(dvm_ctx *ctx, int instance, int nx, int ny,
                      const uint8_t *solid, int periodic_y, double cells_per_H);
 
@@ -217,7 +245,10 @@ int dvm_solve_warm(dvm_ctx *ctx, int instance, const double *delta,
 
 /* Flow rate of Sec. III, Q = (1/L) * sum over fluid of u1 dA (L = nx cells),
  * and apparent permeability k_a = sqrt(4/pi) Q Kn = Q / delta (NaN when delta
- * is a field).  k_a may be NULL. */
+ * is a field).  k_a may be NULL.  Q of every solved instance is reduced on the
+ * device (fixed summation order) at the end of each solve and kept with the
+ * context, so this call does no device work.  DVM_ESTATE before the
+ * instance's first solve. */
 int dvm_flow_rate(const dvm_ctx *ctx, int instance, double *Q, double *k_a);
 
 /* Moments of Sec. II.A at every cell (ny*nx each, 0 in solids): perturbed
@@ -236,28 +267,42 @@ int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha);
 /* Permeability of a porous medium from a rarefaction sweep of one geometry
  * (Sec. III): n >= 3 solves at distinct delta[i] > 0 with flow rates Q[i]
  * (dvm_flow_rate), porosity phi in (0, 1] (fluid fraction of the cell).
- * With Kn = sqrt(pi)/(2 delta) and k_a = sqrt(4/pi) Q Kn = Q/delta:
+ * With Kn = sqrt(pi)/(2 delta) (Sec. II.A) and k_a = sqrt(4/pi) Q Kn = Q/delta:
  *   k_inf   -- the intrinsic permeability, the limit of k_a as Kn -> 0,
  *              taken as the value at Kn = 0 of the quadratic in Kn through
  *              the three samples of smallest Kn;
  *   H_star  -- the characteristic length H* = H sqrt(12 k_inf / phi), in
  *              units of H;
  *   Kn_star -- Kn* = Kn H / H* for every sample (n values);
- *   ka_ratio -- k_a / k_inf for every sample (n values).
- * Host-only arithmetic; any output may be NULL.  DVM_EINVAL if n < 3, a
- * delta is not finite and > 0, two deltas coincide, phi is outside (0, 1],
- * or the extrapolated k_inf is not positive. */
+ *   ka_ratio -- k_a / k_inf for every sample (n values);
+ *   Kn      -- Kn of every sample (n values);
+ *   k_a     -- k_a of every sample (n values).
+ * Host-only arithmetic on host arrays; any output may be NULL.  DVM_EINVAL if
+ * n < 3, a delta is not finite and > 0, two deltas coincide, phi is outside
+ * (0, 1], or the extrapolated k_inf is not positive. */
 int dvm_permeability(int n, const double *delta, const double *Q, double phi,
                      double *k_inf, double *H_star, double *Kn_star,
-                     double *ka_ratio);
+                     double *ka_ratio, double *Kn, double *k_a);
 
-/* Kernel timings gathered while cfg.profile == 1, since the previous call:
- * total milliseconds spent in the sweep launches of the plain iteration and
- * their count, and total milliseconds of the other kernels of those
- * iterations (moments, record, stop rule).  Launches at the end of a
- * 32-iteration block that find every instance stopped (and return at once)
- * are not counted.  Resets the totals.  Any output may be NULL. */
-int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms);
+/* Kernel timings gathered while cfg.profile == 1 (HIP events on the
+ * context's stream around every sweep launch of the source iteration, the
+ * refinement's FP64 steps and FP32 correction iterations, and the
+ * extrapolation's extra iteration; GMRES sweeps are not timed).  Launches at
+ * the end of a block that find every instance stopped (and return at once)
+ * are not counted. */
+typedef struct {
+    double sweep_ms;        /* FP64 sweep launches: total milliseconds       */
+    long n_sweeps;          /*   their count                                 */
+    double updates;         /*   fluid cell x velocity updates they made      */
+    double other_ms;        /* moments, record and stop-rule kernels of the
+                               plain FP64 iterations                          */
+    double sweep32_ms;      /* FP32 sweep launches (DVM_FP32_REFINE)          */
+    long n_sweeps32;
+    double updates32;
+} dvm_prof;
+
+/* Totals since the previous call (then reset); out must not be NULL. */
+int dvm_profile(dvm_ctx *ctx, dvm_prof *out);
 
 /* Sweep launch shape in use: velocities per lane and waves per workgroup of
  * the FP64 sweep and of the FP32 sweep (the latter used by

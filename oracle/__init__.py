@@ -164,3 +164,11 @@ def si_solve(mask: np.ndarray, delta, nv: int, *, periodic_y: bool = False,
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Host threads (OpenMP) of the oracle's next solves."""
+    lib = _load()
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
+    lib.oracle_set_num_threads(int(n))

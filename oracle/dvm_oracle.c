@@ -48,6 +48,17 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the next solves (timing on a given number of host cores). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Eq. (nonuniform_v): v_j = 4 s_j^3 with s_j = (2j - Nv + 1)/(Nv - 1).
  * Reading: the 1-D weights are the trapezoid rule in s, w_j = (dv/ds) * ds,
  * halved at both ends.  The 2-D weight of velocity (v_i, v_j) carries the

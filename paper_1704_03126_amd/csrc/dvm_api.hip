@@ -36,10 +36,28 @@ static int fail(int code, const std::string &msg)
     do {                                                                               \
         hipError_t e_ = (x);                                                           \
         if (e_ != hipSuccess)                                                          \
-            return fail(DVM_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+            return fail(e_ == hipErrorOutOfMemory ? DVM_ENOMEM : DVM_EHIP,             \
+                        std::string(#x) + ": " + hipGetErrorString(e_));               \
     } while (0)
 
 namespace {
+
+// Where device buffers come from: the caller's allocator hooks of dvm_create,
+// or hipMalloc / hipFree.  The entry points that may allocate publish their
+// context's hooks for the duration of the call (AllocScope); a buffer keeps
+// the hooks it was allocated with, so that it is returned to the same place.
+struct DevAlloc {
+    dvm_alloc_fn alloc = nullptr;
+    dvm_free_fn free = nullptr;
+    void *ud = nullptr;
+};
+thread_local const DevAlloc *t_alloc = nullptr;
+
+struct AllocScope {
+    const DevAlloc *prev;
+    explicit AllocScope(const DevAlloc *a) : prev(t_alloc) { t_alloc = a; }
+    ~AllocScope() { t_alloc = prev; }
+};
 
 struct HostInst {
     bool has_geom = false;
@@ -67,20 +85,41 @@ template <typename T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    DevAlloc al{};
     hipError_t alloc(size_t count)
     {
         release();
-        n = count;
         if (count == 0)
             return hipSuccess;
-        return hipMalloc((void **)&p, count * sizeof(T));
+        if (t_alloc && t_alloc->alloc) {
+            al = *t_alloc;
+            p = static_cast<T *>(al.alloc(count * sizeof(T), al.ud));
+            if (!p) {
+                al = DevAlloc{};
+                return hipErrorOutOfMemory;
+            }
+            n = count;
+            return hipSuccess;
+        }
+        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        n = count;
+        return hipSuccess;
     }
     void release()
     {
-        if (p)
-            (void)hipFree(p);
+        if (p) {
+            if (al.free)
+                al.free(p, al.ud);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
+        al = DevAlloc{};
     }
 };
 
@@ -105,6 +144,11 @@ struct dvm_ctx {
     dvm_config cfg{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    DevAlloc dalloc;             // allocator hooks of dvm_create (both null: hipMalloc)
+    // flow rate of every instance, reduced on the device at the end of each
+    // solve (dvm_flow_rate reads it from here)
+    DevBuf<double> d_q;
+    std::vector<double> qcache;
     std::vector<double> v, w1;
     double m0 = 0, m2 = 0, M2 = 0, M4 = 0, c2 = 0, c4 = 0, D = 0;
     std::vector<HostInst> inst;
@@ -158,7 +202,6 @@ struct dvm_ctx {
     // the plain contraction per iteration, and the plain wall time per
     // iteration of the last block
     std::vector<double> trial_q;
-    double trial_t_iter = 0.0;
 
     // FP32 correction state of the refinement (allocated by the first
     // DVM_FP32_REFINE solve)
@@ -177,9 +220,9 @@ struct dvm_ctx {
     // profiling (cfg.profile): event pairs around sweep launches
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_other;
+    int ev_prec = 0;              // precision of the sweeps in ev_sweep: 0 FP64, 1 FP32
     size_t ev_next = 0;
-    double prof_sweep_ms = 0.0, prof_other_ms = 0.0;
-    long prof_sweeps = 0;
+    dvm_prof prof{};
 
     ~dvm_ctx()
     {
@@ -200,7 +243,7 @@ struct dvm_ctx {
         kw.release();
         d_srec32.release(); d_seam32.release(); d_wrap32.release(); d_fb32.release(); d_vt32.release();
         d_mom_d.release(); d_u1prev_d.release(); d_xr.release(); d_rr.release(); d_er.release();
-        d_st32.release(); d_seg32.release();
+        d_st32.release(); d_seg32.release(); d_q.release();
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
     }
@@ -435,6 +478,8 @@ static void drop_graphs(dvm_ctx *c)
 
 static int build_layout(dvm_ctx *c)
 {
+    // buffers are reallocated below: nothing queued may still use them
+    HIPCHK(hipStreamSynchronize(c->stream));
     drop_graphs(c);
     c->adj_ready = false;
     c->fp32_ready = false;
@@ -546,9 +591,12 @@ static int build_layout(dvm_ctx *c)
                 rows.push_back(h.rows.empty() ? 1.0 / h.cph : h.rows[y]);
         HIPCHK(c->d_rows.alloc(std::max<size_t>(rows.size(), 1)));
         if (!rows.empty())
-            HIPCHK(hipMemcpy(c->d_rows.p, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpyAsync(c->d_rows.p, rows.data(), rows.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
     }
     HIPCHK(c->d_part5.alloc((size_t)4 * c->gq * cell));
+    HIPCHK(c->d_q.alloc(c->n_inst));
+    c->qcache.assign(c->n_inst, 0.0);
 
     std::vector<uint8_t> codes(cell);
     std::vector<double> vt((size_t)c->n_inst * c->kp4 * VT_STRIDE, 0.0);
@@ -802,19 +850,23 @@ static int next_event(dvm_ctx *c, hipEvent_t *e)
 
 // Fold the recorded event pairs into the totals (the stream is idle).  Only
 // the first `real` iterations of the block did work: the later launches found
-// every instance stopped and returned at once, and are left out.
-static int collect_profile(dvm_ctx *c, long long real)
+// every instance stopped and returned at once, and are left out.  `updates`:
+// fluid cell x velocity updates of those launches.
+static int collect_profile(dvm_ctx *c, long long real, double updates)
 {
+    dvm_prof &p = c->prof;
+    const bool f32 = c->ev_prec == 1;
     for (size_t i = 0; i < c->ev_sweep.size() && (long long)i < real; ++i) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->ev_sweep[i].first, c->ev_sweep[i].second));
-        c->prof_sweep_ms += ms;
-        ++c->prof_sweeps;
+        (f32 ? p.sweep32_ms : p.sweep_ms) += ms;
+        ++(f32 ? p.n_sweeps32 : p.n_sweeps);
     }
+    (f32 ? p.updates32 : p.updates) += updates;
     for (size_t i = 0; i < c->ev_other.size() && (long long)i < real; ++i) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, c->ev_other[i].first, c->ev_other[i].second));
-        c->prof_other_ms += ms;
+        p.other_ms += ms;
     }
     c->ev_sweep.clear();
     c->ev_other.clear();
@@ -895,7 +947,7 @@ static double refine_inner_tol(const dvm_ctx *c)
 static int enqueue_iteration(dvm_ctx *c, int kind)
 {
     const bool adj = kind == 1;
-    const bool prof = c->cfg.profile != 0 && kind == 0;
+    const bool prof = c->cfg.profile != 0 && kind != 1;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     if (prof) {
         int rc = next_event(c, &e0);
@@ -904,10 +956,15 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         if (rc)
             return rc;
         HIPCHK(hipEventRecord(e0, c->stream));
+        c->ev_prec = kind == 2 ? 1 : 0;
     }
     if (kind == 2) {
         HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32,
                                    solve_mode(c) | xu_flag(c, c->V32), c->stream));
+        if (prof) {
+            HIPCHK(hipEventRecord(e1, c->stream));
+            c->ev_sweep.emplace_back(e0, e1);
+        }
         MomArgs m = mom_args(c);
         m.mom = c->d_mom_d.p;
         m.st = c->d_st32.p;
@@ -1024,13 +1081,17 @@ static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const
     HIPCHK(hipMemcpyAsync(kw.sseg.p, sseg.data(), sseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
     // x_k: the state the next sweep reads; then x_{k+1} = F(x_k)
     HIPCHK(launch_gather(kw.sseg.p, (int)sseg.size(), sb, kw.x.p, nullptr, c->stream));
+    double upd = 0.0;              // updates of the extra iteration (profiling)
+    for (int i = 0; i < c->n_inst; ++i)
+        if (st[i].active)
+            upd += (double)c->inst[i].nfluid * c->K;
     int rc = enqueue_iteration(c, kind);
     if (rc)
         return rc;
     HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, nullptr, c->stream));
     HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (c->cfg.profile && kind == 0 && (rc = collect_profile(c, 1)))
+    if (c->cfg.profile && kind != 1 && (rc = collect_profile(c, 1, upd)))
         return rc;
     for (size_t k = 0; k < cand.size(); ++k) {
         if (!st[cand[k]].active)
@@ -1071,7 +1132,7 @@ static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const
 // With no_trial given (AUTO), an instance whose contraction per iteration has
 // settled above 0.98 (no extrapolation there) with more than 1000 iterations
 // still to go is stopped for a GMRES trial (stalled = 3); its rate is left in
-// c->trial_q, the plain wall time per iteration in c->trial_t_iter.
+// c->trial_q.
 static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, int kind,
                       std::vector<SolveState> &st, std::vector<char> *stalled = nullptr,
                       const std::vector<char> *grow_only = nullptr,
@@ -1102,26 +1163,20 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
     for (;;) {
         for (int i = 0; i < c->n_inst; ++i)
             before[i] = st[i].iter;
-        const auto t_blk = std::chrono::steady_clock::now();
         int rc = enqueue_block(c, B, kind);
         if (rc)
             return rc;
         HIPCHK(hipMemcpyAsync(st.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
                               c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        {
-            long long adv = 0;
-            for (int i = i0; i < i1; ++i)
-                adv = std::max(adv, st[i].iter - before[i]);
-            if (adv > 0)
-                c->trial_t_iter = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_blk).count() /
-                                  (double)adv;
-        }
         if (c->cfg.profile) {
             long long real = 0;
-            for (int i = 0; i < c->n_inst; ++i)
+            double upd = 0.0;
+            for (int i = 0; i < c->n_inst; ++i) {
                 real = std::max(real, st[i].iter - before[i]);
-            int prc = collect_profile(c, real);
+                upd += (double)(st[i].iter - before[i]) * (double)c->inst[i].nfluid * c->K;
+            }
+            int prc = collect_profile(c, real, kind == 1 ? 0.0 : upd);
             if (prc)
                 return prc;
         }
@@ -1447,6 +1502,20 @@ static double sigma_min_tri(const std::vector<double> &R, int ld, int k)
     return 1.0 / std::sqrt(lam);
 }
 
+// Work of one GMRES cycle of k Arnoldi steps on one instance, in sweeps of
+// that instance: the cycle's k + 1 sweeps, plus the HBM traffic of the
+// orthogonalisation over its state vector of len elements (step j reads the
+// j FP32 basis vectors twice, dots and update, and w, the new basis vector
+// and the gathered state a few times: about 8 j + 60 bytes per element)
+// expressed at the bytes an FP64 sweep update costs in time (about 8 bytes
+// at the vector kernels' bandwidth: 200 us per 1.07e8 updates against
+// about 4.6 TB/s, measured on the rough channel).
+static double gmres_cycle_cost(int k, long long len, double updates_per_sweep)
+{
+    const double bytes = (4.0 * k * (k + 1) + 60.0 * k) * (double)len;
+    return (double)(k + 1) + bytes / (8.0 * std::max(updates_per_sweep, 1.0));
+}
+
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
                      const std::vector<long long> &prior, const std::vector<char> *trial,
                      std::vector<char> *reverted)
@@ -1567,7 +1636,6 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
     for (int q = 0; q < ns; ++q)
         trials = trials || (trial && (*trial)[slots[q].inst]);
     for (;;) {
-        const auto t_cyc = std::chrono::steady_clock::now();
         // ---- one full iteration from x: residual w = x - F(x) and eps
         for (int q = 0; q < ns; ++q)
             if (hs[q].live)
@@ -1724,10 +1792,11 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, k, kw.y.p, cst, nullptr, c->stream));
         if (trials && k > 0) {
             // a trial instance stays with GMRES while a cycle reduces its
-            // residual at least 1.5 times faster per second than the plain
-            // iteration's rate
+            // residual at least 1.5 times faster per unit of work than the
+            // plain iteration, both counted in sweeps of the instance
+            // (deterministic, so the path a solve takes does not depend on
+            // machine load or on the other instances of the batch)
             HIPCHK(hipStreamSynchronize(c->stream));
-            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_cyc).count();
             bool back = false, left = false;
             for (int q = 0; q < ns; ++q) {
                 GmresSlotHost &h = hs[q];
@@ -1736,12 +1805,13 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                     continue;
                 if ((*trial)[inst] && h.beta > 0.0) {
                     const double red = std::max(std::fabs(h.g[k]) / h.beta, 1e-300);
-                    const double rate_g = -std::log(red) / std::max(dt, 1e-9);
-                    const double rate_p = -std::log(c->trial_q[inst]) / std::max(c->trial_t_iter, 1e-9);
+                    const double cost = gmres_cycle_cost(k, slots[q].len, c->inst[inst].nfluid * (double)c->K);
+                    const double rate_g = -std::log(red) / cost;
+                    const double rate_p = -std::log(c->trial_q[inst]);
                     if (debug_on())
-                        std::fprintf(stderr, "[dvm trial] inst %d cycle of %d: residual x %.3e in %.3f s "
-                                     "(%.3g/s) vs plain q %.5f at %.3f ms (%.3g/s)\n", inst, k, red, dt, rate_g,
-                                     c->trial_q[inst], 1e3 * c->trial_t_iter, rate_p);
+                        std::fprintf(stderr, "[dvm trial] inst %d cycle of %d: residual x %.3e over %.1f "
+                                     "sweep-equivalents (%.3g per sweep) vs plain q %.5f (%.3g per sweep)\n",
+                                     inst, k, red, cost, rate_g, c->trial_q[inst], rate_p);
                     if (rate_g < 1.5 * rate_p) {
                         h.live = false;
                         st[inst].active = 0;
@@ -1788,6 +1858,8 @@ static int ensure_fp32(dvm_ctx *c)
 {
     if (c->fp32_ready)
         return DVM_OK;
+    // (re)allocation below: nothing queued may still use the old buffers
+    HIPCHK(hipStreamSynchronize(c->stream));
     const long long sk = c->sk_total, fh = std::max<long long>(c->nfaces, 1) * c->kp4;
     HIPCHK(c->d_srec32.alloc(sk * REC_STRIDE));
     HIPCHK(c->d_seam32.alloc(2 * c->seam_half));
@@ -1907,7 +1979,25 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
             return rc;
         HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, c->d_xr.p, c->stream));
         HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+        hipEvent_t pe0 = nullptr, pe1 = nullptr;
+        double pupd = 0.0;
+        if (c->cfg.profile) {
+            if ((rc = next_event(c, &pe0)) || (rc = next_event(c, &pe1)))
+                return rc;
+            HIPCHK(hipEventRecord(pe0, c->stream));
+            for (const auto &d : slots)
+                if (d.live)
+                    pupd += (double)c->inst[d.inst].nfluid * c->K;
+        }
         HIPCHK(launch_sweep<double>(sweep_args(c, 0, false), (int)c->items.size(), c->V, c->G, mode, c->stream));
+        if (c->cfg.profile) {
+            HIPCHK(hipEventRecord(pe1, c->stream));
+            c->ev_prec = 0;
+            c->ev_sweep.emplace_back(pe0, pe1);
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if ((rc = collect_profile(c, 1, pupd)))
+                return rc;
+        }
         HIPCHK(launch_moments(mom_args(c), c->max_cells, c->n_inst, c->stream));
         HIPCHK(launch_gather(kw.gseg.p, (int)gseg.size(), sb, c->d_rr.p, c->d_xr.p, c->stream));
         if ((rc = upload(c->d_st.p, st)))
@@ -2329,6 +2419,7 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
 {
     if (!c)
         return fail(DVM_EINVAL, "context is NULL");
+    AllocScope scope(&c->dalloc);
     if (instance < -1 || instance >= c->n_inst)
         return fail(DVM_EINVAL, "instance index out of range");
     if (!delta)
@@ -2493,6 +2584,12 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
             return do_solve(c, instance, delta, delta_is_field, alpha, info, true, depth + 1);
         }
     }
+    // flow rate of Sec. III of every instance with a state, reduced on the
+    // device in a fixed order; kept for dvm_flow_rate
+    HIPCHK(launch_flow(c->d_inst.p, c->d_codes.p, c->d_mom.p, c->d_rows.p, c->d_q.p, c->n_inst, c->stream));
+    HIPCHK(hipMemcpyAsync(c->qcache.data(), c->d_q.p, c->n_inst * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     int rc = DVM_OK;
     for (int i = i0; i < i1; ++i) {
         const SolveState &s = st[i];
@@ -2520,6 +2617,8 @@ static int ensure_adjoint(dvm_ctx *c)
 {
     if (c->adj_ready)
         return DVM_OK;
+    // (re)allocation below: nothing queued may still use the old buffers
+    HIPCHK(hipStreamSynchronize(c->stream));
     const long long sk = c->sk_total, cell = c->ncell, nf = std::max<long long>(c->nfaces, 1);
     HIPCHK(c->d_scode_adj.alloc(sk));
     HIPCHK(c->d_sface_adj.alloc(sk));
@@ -2691,11 +2790,14 @@ const char *dvm_last_error(void) { return g_err.c_str(); }
 
 const char *dvm_version(void) { return "dvm-gfx950 0.1"; }
 
-int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, void *hip_stream)
+int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, void *hip_stream,
+               dvm_alloc_fn alloc, dvm_free_fn free_, void *alloc_ud)
 {
     if (!out)
         return fail(DVM_EINVAL, "out is NULL");
     *out = nullptr;
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return fail(DVM_EINVAL, "alloc and free_ must both be given or both be NULL");
     if (nv < 4 || nv > 128 || (nv % 2) != 0)
         return fail(DVM_EINVAL, "nv must be even and in [4, 128]");
     if (n_instances < 1 || n_instances > 65535)
@@ -2749,6 +2851,9 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->driving.assign(n_instances, dvm_ctx::Driving{});
     ctx->sweeps64_wasted.assign(n_instances, 0);
     ctx->stream = (hipStream_t)hip_stream;   // NULL: a stream is made on first use
+    ctx->dalloc.alloc = alloc;
+    ctx->dalloc.free = free_;
+    ctx->dalloc.ud = alloc_ud;
     build_quadrature(ctx);
     *out = ctx;
     return DVM_OK;
@@ -2848,27 +2953,17 @@ int dvm_flow_rate(const dvm_ctx *cc, int instance, double *Q, double *k_a)
     if (!Q)
         return fail(DVM_EINVAL, "Q is NULL");
     const HostInst &h = ctx->inst[instance];
-    if (!ctx->layout_ok || !h.has_state)
+    if (!ctx->layout_ok || !h.has_state || (size_t)instance >= ctx->qcache.size())
         return fail(DVM_ESTATE, "instance has not been solved");
-    const InstDev &d = ctx->idev[instance];
-    size_t n = (size_t)d.nx * d.ny;
-    std::vector<double> mom(n * MOM_STRIDE);
-    HIPCHK(hipMemcpyAsync(mom.data(), ctx->d_mom.p + d.cell_off * MOM_STRIDE, mom.size() * sizeof(double),
-                          hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    double s = 0.0;
-    for (size_t k = 0; k < n; ++k)
-        if (!h.solid[k])
-            s += h.rows.empty() ? mom[k * MOM_STRIDE + MOM_U1] : mom[k * MOM_STRIDE + MOM_U1] * h.rows[k / h.nx];
-    // (1/L) sum u1 dA, L = nx / cells_per_H, dA = dx dy
-    *Q = h.rows.empty() ? s / (h.cph * h.nx) : s / h.nx;
+    // reduced on the device at the end of the last solve
+    *Q = ctx->qcache[instance];
     if (k_a)
         *k_a = h.field ? NAN : *Q / h.delta;
     return DVM_OK;
 }
 
 int dvm_permeability(int n, const double *delta, const double *Q, double phi, double *k_inf, double *H_star,
-                     double *Kn_star, double *ka_ratio)
+                     double *Kn_star, double *ka_ratio, double *Kn, double *k_a)
 {
     if (n < 3 || !delta || !Q)
         return fail(DVM_EINVAL, "need n >= 3 samples (delta, Q)");
@@ -2910,6 +3005,10 @@ int dvm_permeability(int n, const double *delta, const double *Q, double phi, do
             Kn_star[i] = kn[i] / hs;
         if (ka_ratio)
             ka_ratio[i] = ka[i] / k0;
+        if (Kn)
+            Kn[i] = kn[i];
+        if (k_a)
+            k_a[i] = ka[i];
     }
     return DVM_OK;
 }
@@ -2921,6 +3020,7 @@ int dvm_get_moments(const dvm_ctx *cc, int instance, double *rho, double *u1, do
     int rc = check_instance(ctx, instance);
     if (rc)
         return rc;
+    AllocScope scope(&ctx->dalloc);
     const HostInst &h = ctx->inst[instance];
     if (!ctx->layout_ok || !h.has_state)
         return fail(DVM_ESTATE, "instance has not been solved");
@@ -2984,21 +3084,16 @@ int dvm_grad(dvm_ctx *ctx, int instance, double *dQ_ddelta, double *dQ_dalpha)
     const HostInst &h = ctx->inst[instance];
     if (!ctx->layout_ok || !h.has_state || !h.converged)
         return fail(DVM_ESTATE, "instance has no converged solution (call dvm_solve first)");
+    AllocScope scope(&ctx->dalloc);
     return grad_instance(ctx, instance, dQ_ddelta, dQ_dalpha);
 }
 
-int dvm_profile(dvm_ctx *ctx, double *sweep_ms, long *n_sweeps, double *other_ms)
+int dvm_profile(dvm_ctx *ctx, dvm_prof *out)
 {
-    if (!ctx)
-        return fail(DVM_EINVAL, "context is NULL");
-    if (sweep_ms)
-        *sweep_ms = ctx->prof_sweep_ms;
-    if (n_sweeps)
-        *n_sweeps = ctx->prof_sweeps;
-    if (other_ms)
-        *other_ms = ctx->prof_other_ms;
-    ctx->prof_sweep_ms = ctx->prof_other_ms = 0.0;
-    ctx->prof_sweeps = 0;
+    if (!ctx || !out)
+        return fail(DVM_EINVAL, "context or out is NULL");
+    *out = ctx->prof;
+    ctx->prof = dvm_prof{};
     return DVM_OK;
 }
 
@@ -3025,7 +3120,7 @@ void dvm_destroy(dvm_ctx *ctx)
         return;
     if (ctx->stream)
         (void)hipStreamSynchronize(ctx->stream);
-    delete ctx;
+    delete ctx;   // every buffer goes back through the hooks it came from
 }
 
 } // extern "C"

@@ -195,6 +195,9 @@ struct GradArgs {
     const double *rows;       // row heights in units of H, [row_off + row]
 };
 hipError_t launch_grad(const GradArgs &a, int instance, int ncells, hipStream_t s);
+// q[i] = flow rate of instance i (Sec. III): sum over fluid cells of u1 dy / nx
+hipError_t launch_flow(const InstDev *inst, const uint8_t *codes, const double *mom, const double *rows,
+                       double *q, int n_inst, hipStream_t s);
 template <typename T>
 hipError_t launch_record(const RecArgs<T> &a, int max_cells, int n_inst, hipStream_t s);
 hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, hipStream_t s);

@@ -651,6 +651,36 @@ __global__ void __launch_bounds__(256) k_sum1(MomArgs a, const double *part5, do
     out[cg] = scale * s;
 }
 
+// ------------------------------------------------------------- flow rate
+// Q of Sec. III per instance: (1/L) sum over fluid cells of u1 dx dy, with
+// L = nx dx, i.e. sum u1 dy / nx.  One workgroup per instance: each thread
+// adds its cells (stride 256) in order, then a fixed tree over the threads.
+__global__ void __launch_bounds__(256) k_flow(const InstDev *inst, const uint8_t *codes, const double *mom,
+                                              const double *rows, double *q)
+{
+    __shared__ double red[256];
+    const InstDev in = inst[blockIdx.x];
+    const long long n = (long long)in.nx * in.ny;
+    const double dy0 = 1.0 / in.inv_dx;
+    double s = 0.0;
+    for (long long c = threadIdx.x; c < n; c += 256) {
+        const long long cg = in.cell_off + c;
+        if (codes[cg] == 0xFF)
+            continue;
+        const double dy = in.nonuniform ? rows[in.row_off + c / in.nx] : dy0;
+        s += mom[cg * MOM_STRIDE + MOM_U1] * dy;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        q[blockIdx.x] = red[0] / (double)in.nx;
+}
+
 // ------------------------------------------------------------------ record
 template <typename T>
 __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
@@ -1066,6 +1096,13 @@ hipError_t launch_sum1(const MomArgs &a, const double *part5, double *out, doubl
                        int n_inst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sum1, dim3((max_cells + 255) / 256, n_inst), dim3(256), 0, s, a, part5, out, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow(const InstDev *inst, const uint8_t *codes, const double *mom, const double *rows,
+                       double *q, int n_inst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flow, dim3(n_inst), dim3(256), 0, s, inst, codes, mom, rows, q);
     return hipGetLastError();
 }
 

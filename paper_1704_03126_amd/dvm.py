@@ -55,13 +55,58 @@ class dvm_config(ctypes.Structure):
                 ("accel", ctypes.c_int), ("krylov_dim", ctypes.c_int)]
 
 
+class dvm_prof(ctypes.Structure):
+    _fields_ = [("sweep_ms", ctypes.c_double), ("n_sweeps", ctypes.c_long),
+                ("updates", ctypes.c_double), ("other_ms", ctypes.c_double),
+                ("sweep32_ms", ctypes.c_double), ("n_sweeps32", ctypes.c_long),
+                ("updates32", ctypes.c_double)]
+
+
 class dvm_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_long), ("sweeps_fp64", ctypes.c_long),
                 ("rel_change", ctypes.c_double), ("est_error", ctypes.c_double),
                 ("status", ctypes.c_int), ("schedule", ctypes.c_int)]
 
 
+# allocator hooks of dvm_create: alloc(bytes, ud) -> device pointer, free(ptr, ud)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _lib = None
+
+
+class TorchAllocator:
+    """Allocator hooks that take a context's device buffers from torch's
+    caching allocator (on the given device and stream, by default the current
+    ones).  Keeps count of the bytes it holds for the library."""
+
+    def __init__(self, device=None, stream=None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        self.live = {}
+        self.calls = 0
+
+        def _alloc(nbytes, _ud):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except RuntimeError:
+                return None          # the library reports DVM_ENOMEM
+            self.live[ptr] = int(nbytes)
+            self.calls += 1
+            return ptr
+
+        def _free(ptr, _ud):
+            if ptr:
+                torch.cuda.caching_allocator_delete(ptr)
+                self.live.pop(ptr, None)
+
+        self.alloc_fn = _ALLOC_FN(_alloc)
+        self.free_fn = _FREE_FN(_free)
+
+    @property
+    def bytes_held(self) -> int:
+        return sum(self.live.values())
 
 
 def load_library(path: str = LIB_PATH):
@@ -74,7 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     lib.dvm_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_int,
-                               ctypes.POINTER(dvm_config), P]
+                               ctypes.POINTER(dvm_config), P, _ALLOC_FN, _FREE_FN, P]
     lib.dvm_set_geometry.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
                                      ctypes.c_int, ctypes.c_double]
     lib.dvm_solve.argtypes = [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_double,
@@ -84,13 +129,12 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(ctypes.c_double)]
     lib.dvm_get_moments.argtypes = [P, ctypes.c_int, P, P, P, P, P]
     lib.dvm_grad.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double)]
-    lib.dvm_profile.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long),
-                                ctypes.POINTER(ctypes.c_double)]
+    lib.dvm_profile.argtypes = [P, ctypes.POINTER(dvm_prof)]
     IP = ctypes.POINTER(ctypes.c_int)
     lib.dvm_launch_shape.argtypes = [P, IP, IP, IP, IP]
     lib.dvm_set_row_heights.argtypes = [P, ctypes.c_int, P]
     lib.dvm_set_driving.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
-    lib.dvm_permeability.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P]
+    lib.dvm_permeability.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P, P, P]
     lib.dvm_destroy.argtypes = [P]
     lib.dvm_destroy.restype = None
     lib.dvm_last_error.restype = ctypes.c_char_p
@@ -139,11 +183,11 @@ def permeability(delta, Q, porosity: float) -> dict:
     if d.shape != q.shape:
         raise ValueError("delta and Q must have the same length")
     k, h = ctypes.c_double(), ctypes.c_double()
-    kns, rat = np.zeros_like(d), np.zeros_like(d)
+    kns, rat, kn, ka = (np.zeros_like(d) for _ in range(4))
     _check(lib.dvm_permeability(len(d), _ptr(d), _ptr(q), float(porosity), ctypes.byref(k),
-                                ctypes.byref(h), _ptr(kns), _ptr(rat)))
+                                ctypes.byref(h), _ptr(kns), _ptr(rat), _ptr(kn), _ptr(ka)))
     return {"k_inf": k.value, "H_star": h.value, "Kn_star": kns, "ka_ratio": rat,
-            "Kn": np.sqrt(np.pi) / (2.0 * d), "k_a": q / d}
+            "Kn": kn, "k_a": ka}
 
 
 class Solver:
@@ -154,7 +198,7 @@ class Solver:
                  use_graphs: bool = True, vel_per_lane: int = 0,
                  waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_AUTO,
                  accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, tune_cache: str | None = None,
-                 stream=None):
+                 stream=None, allocator: TorchAllocator | None = None):
         lib = load_library()
         tc = tune_cache.encode() if tune_cache else None
         cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
@@ -162,7 +206,12 @@ class Solver:
                          int(accel), int(krylov_dim))
         h = ctypes.c_void_p()
         s = stream if stream is not None else _current_stream()
-        _check(lib.dvm_create(ctypes.byref(h), nv, n_instances, ctypes.byref(cfg), s))
+        self.allocator = allocator          # kept alive until dvm_destroy
+        if allocator is not None:
+            fa, ff = allocator.alloc_fn, allocator.free_fn
+        else:
+            fa, ff = _ALLOC_FN(), _FREE_FN()
+        _check(lib.dvm_create(ctypes.byref(h), nv, n_instances, ctypes.byref(cfg), s, fa, ff, None))
         self._h = h
         self._lib = lib
         self.epoch = 0              # bumped by every solve (autograd checks it)
@@ -263,11 +312,13 @@ class Solver:
             out["p12"] = p12
         return out
 
-    def profile(self):
-        """(sweep_ms_total, n_sweeps, other_ms_total) since the last call."""
-        sm, n, om = ctypes.c_double(), ctypes.c_long(), ctypes.c_double()
-        _check(self._lib.dvm_profile(self._h, ctypes.byref(sm), ctypes.byref(n), ctypes.byref(om)))
-        return sm.value, n.value, om.value
+    def profile(self) -> dict:
+        """Sweep timings since the last call (profile=True contexts): total
+        ms, launch count and fluid updates of the FP64 and of the FP32 sweeps,
+        and the ms of the other kernels of the plain FP64 iterations."""
+        p = dvm_prof()
+        _check(self._lib.dvm_profile(self._h, ctypes.byref(p)))
+        return {f: getattr(p, f) for f, _ in dvm_prof._fields_}
 
     def launch_shape(self):
         """((V, G) of the FP64 sweep, (V, G) of the FP32 sweep); zeros while

@@ -40,7 +40,8 @@ def _ctx(lib, nv=8, n=1, **kw):
                          kw.get("block_iters", 0), 1, kw.get("vel", 0), kw.get("waves", 0), None, 0,
                          kw.get("schedule", 0))
     h = ctypes.c_void_p()
-    rc = lib.dvm_create(ctypes.byref(h), nv, n, ctypes.byref(cfg), None)
+    rc = lib.dvm_create(ctypes.byref(h), nv, n, ctypes.byref(cfg), None,
+                        kw.get("alloc", dvm._ALLOC_FN()), kw.get("free", dvm._FREE_FN()), None)
     return rc, h
 
 
@@ -58,6 +59,23 @@ def test_create_validates_arguments(lib):
     assert rc == dvm.DVM_OK
     lib.dvm_destroy(h)
     lib.dvm_destroy(None)
+
+
+def test_create_allocator_hooks_come_in_pairs(lib):
+    """Allocator hooks: both or neither; a context with hooks allocates
+    nothing before its first solve (host-side set-up only)."""
+    calls = []
+    fa = dvm._ALLOC_FN(lambda n, ud: calls.append(n) or None)
+    ff = dvm._FREE_FN(lambda p, ud: calls.append(p))
+    assert _ctx(lib, alloc=fa)[0] == dvm.DVM_EINVAL
+    assert b"alloc" in lib.dvm_last_error()
+    assert _ctx(lib, free=ff)[0] == dvm.DVM_EINVAL
+    rc, h = _ctx(lib, alloc=fa, free=ff)
+    assert rc == dvm.DVM_OK
+    m = np.zeros((8, 8), dtype=np.uint8)
+    assert lib.dvm_set_geometry(h, 0, 8, 8, m.ctypes.data_as(ctypes.c_void_p), 0, 8.0) == 0
+    lib.dvm_destroy(h)
+    assert calls == []
 
 
 def _set(lib, h, inst, mask, periodic_y=0, cph=None):

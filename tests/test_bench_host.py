@@ -35,21 +35,43 @@ def test_no_gpu_is_reported():
 
 
 def test_traffic_figures_only_for_the_profiled_kernel():
+    """Profiler byte counts are reported only for the kernel source, workload,
+    precision, order and launch shape they were taken on."""
     import bench
     path = os.path.join(ROOT, "profiles", "k_sweep_traffic.json")
     with open(path) as f:
-        tr = json.load(f)
+        entries = json.load(f)
+    if isinstance(entries, dict):
+        entries = [entries]
     with open(os.path.join(ROOT, "paper_1704_03126_amd", "csrc", "dvm_kernels.hip"), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    got = bench.measured_traffic(tr["schedule"], *tr["shape"])
-    if not sha.startswith(tr["kernel_source_sha256_prefix"]):
-        # the kernel changed since the counters were taken: no figures
-        assert got is None
-        return
-    assert got is not None and got["fetch_bytes"] > 0 and got["write_bytes"] > 0
-    other = "skew" if tr["schedule"] != "skew" else "wrap"
-    assert bench.measured_traffic(other, *tr["shape"]) is None
-    assert bench.measured_traffic(tr["schedule"], tr["shape"][0] * 2, tr["shape"][1]) is None
+    for tr in entries:
+        wl, prec = tr.get("workload_key", "rough_channel"), tr.get("precision", "fp64")
+        got = bench.measured_traffic(wl, prec, *tr["shape"], schedule=tr.get("schedule"))
+        if not sha.startswith(tr["kernel_source_sha256_prefix"]):
+            # the kernel changed since the counters were taken: no figures
+            assert got is None
+            continue
+        assert got is not None and got["fetch_bytes"] > 0 and got["write_bytes"] > 0
+        other = "fp32" if prec == "fp64" else "fp64"
+        assert bench.measured_traffic(wl, other, *tr["shape"]) is None
+        assert bench.measured_traffic(wl, prec, tr["shape"][0] * 2, tr["shape"][1]) is None
+        assert bench.measured_traffic("no_such_workload", prec, *tr["shape"]) is None
+
+
+def test_batch_oracle_error():
+    import bench
+    path = os.path.join(ROOT, "tests", "golden", "batch64_subset_nv48.json")
+    if not os.path.exists(path):
+        pytest.skip("stored batch results not generated")
+    with open(path) as f:
+        ref = json.load(f)["instances"]
+    qs = [1.0] * 64
+    for k, r in enumerate(ref):
+        qs[r["index"]] = r["Q"] * (1.0 + 1e-7 * (k + 1))
+    err = bench.batch_oracle_error(qs)
+    for k, r in enumerate(ref):
+        assert abs(err[str(r["index"])] - 1e-7 * (k + 1)) < 1e-12
 
 
 def test_stored_oracle_error():

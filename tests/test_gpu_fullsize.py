@@ -1,8 +1,10 @@
 """Full-size parity: the GPU solver in the benchmark's launch configuration
 (default shape selection, sweep order and acceleration) against stored FP64
 oracle results (tests/golden/, written by make_golden.py from the oracle
-only).  Bar: flow rate within 1e-8 relative (the target is 1e-6) and u1, u2
-at 16 seeded cells within 1e-8 (target 1e-5 max-abs)."""
+only).  Bar: flow rate within 1e-8 relative (the target is 1e-6) and the
+whole fields rho, u1, u2, tau, P12 within 1e-8 max-abs (target 1e-5 for the
+velocity), where the stored fields exist; u1, u2 at 16 seeded cells
+otherwise."""
 import json
 import os
 
@@ -16,7 +18,9 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 MAKERS = {"plane_channel_64_nv32": cfg_plane_channel,
           "rough_channel_256x128_nv64": cfg_rough_channel,
-          "porous_512_nv64": cfg_porous}
+          "porous_512_nv64": cfg_porous,
+          "porous_128_nv64": lambda: cfg_porous(128)}
+MOMENTS = ("rho", "u1", "u2", "tau", "p12")
 
 
 @pytest.fixture(scope="module")
@@ -37,29 +41,100 @@ def _load(name):
         return json.load(f)
 
 
+def _fields(ref):
+    """Whole stored fields {delta index: {moment: array}}, or None."""
+    if not ref.get("fields"):
+        return None
+    path = os.path.join(GOLDEN, ref["fields"])
+    if not os.path.exists(path):
+        return None
+    out = {}
+    with np.load(path) as z:
+        for key in z.files:
+            i, m = key.split("_", 1)
+            out.setdefault(int(i[1:]), {})[m] = z[key]
+    return out
+
+
 @pytest.mark.parametrize("name,precision", [
     ("plane_channel_64_nv32", "fp64"),
     ("rough_channel_256x128_nv64", "fp64"),
     ("rough_channel_256x128_nv64", "fp32_refine"),
-    ("porous_512_nv64", "fp64")])
+    ("porous_512_nv64", "fp64"),
+    ("porous_512_nv64", "fp32_refine"),
+    ("porous_128_nv64", "fp64"),
+    ("porous_128_nv64", "fp32_refine")])
 def test_full_size_against_oracle(dvm, name, precision):
+    """One context per case, every delta of the case cold-started, default
+    launch configuration (autotuned shape, AUTO order and acceleration)."""
     ref = _load(name)
+    fields = _fields(ref)
     g = MAKERS[name]()
     assert (g.nx, g.ny) == (ref["nx"], ref["ny"])
     prec = dvm.DVM_FP32_REFINE if precision == "fp32_refine" else dvm.DVM_FP64
     s = dvm.Solver(ref["nv"], 1, tol=1e-11, precision=prec)
     s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
     cells = np.array(ref["cells"])
-    for r in ref["results"]:
+    for k, r in enumerate(ref["results"]):
+        print(f"[fullsize] {name} {precision} delta={r['delta']}", flush=True)
         info = s.solve(0, r["delta"])
         assert info.status == "converged", (r["delta"], info)
         Q, _ = s.flow_rate(0)
-        mom = s.moments(0)
+        mom = s.moments(0, shear=fields is not None)
         assert abs(Q - r["Q"]) <= 1e-8 * abs(r["Q"]), (r["delta"], Q, r["Q"])
-        u1 = mom["u1"][cells[:, 0], cells[:, 1]]
-        u2 = mom["u2"][cells[:, 0], cells[:, 1]]
-        assert np.max(np.abs(u1 - np.array(r["u1"]))) <= 1e-8, r["delta"]
-        assert np.max(np.abs(u2 - np.array(r["u2"]))) <= 1e-8, r["delta"]
+        if fields is not None:
+            for m in MOMENTS:
+                err = float(np.max(np.abs(mom[m] - fields[k][m])))
+                assert err <= 1e-8, (r["delta"], m, err)
+        else:
+            for m in ("u1", "u2"):
+                got = mom[m][cells[:, 0], cells[:, 1]]
+                assert np.max(np.abs(got - np.array(r[m]))) <= 1e-8, (r["delta"], m)
+    s.close()
+
+
+def test_uneven_batch_against_oracle(dvm):
+    """The 64-instance uneven batch (48 x 48 velocities, sides 64-384, delta
+    log-uniform on [0.01, 100]) in one context, solved as the benchmark
+    solves it (FP32 sweeps with FP64 refinement, AUTO).  Every instance
+    converges; a warm restart of every instance from its result passes the
+    stop rule at once (a fixed-point check that needs no oracle, for the
+    instances the oracle's plain iteration cannot finish in reasonable time);
+    the instances with stored oracle results (the largest porous cell and
+    rough channel, the smallest delta, a large delta) match them: Q within
+    1e-8 relative, rho, u1, u2, tau, P12 at 64 seeded cells within 1e-7."""
+    from paper_1704_03126_amd.geometry import batch_instances
+    ref = _load("batch64_subset_nv48")
+    gs = batch_instances(64)
+    nv = ref["nv"]
+    tol = 1e-10
+    s = dvm.Solver(nv, len(gs), tol=tol, precision=dvm.DVM_FP32_REFINE)
+    for i, g in enumerate(gs):
+        s.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
+    deltas = [g.meta["delta"] for g in gs]
+    print("[fullsize] batch64 FP32 refinement, tol 1e-10", flush=True)
+    infos = s.solve(-1, deltas)
+    assert all(inf.status == "converged" for inf in infos), [i.status for i in infos]
+    Qs = [s.flow_rate(i)[0] for i in range(len(gs))]
+    for r in ref["instances"]:
+        i = r["index"]
+        g = gs[i]
+        assert (g.nx, g.ny) == (r["nx"], r["ny"]) and abs(deltas[i] - r["delta"]) < 1e-15
+        assert abs(Qs[i] - r["Q"]) <= 1e-8 * abs(r["Q"]), (i, Qs[i], r["Q"])
+        mom = s.moments(i, shear=True)
+        cells = np.array(r["cells"])
+        for m in MOMENTS:
+            got = mom[m][cells[:, 0], cells[:, 1]]
+            err = float(np.max(np.abs(got - np.array(r[m]))))
+            assert err <= 1e-7, (i, m, err)
+    print("[fullsize] batch64 warm restart", flush=True)
+    again = s.solve(-1, deltas, warm=True)
+    for i, inf in enumerate(again):
+        assert inf.status == "converged", (i, inf)
+        assert inf.rel_change <= tol, (i, inf)
+        assert inf.iters <= 40, (i, inf)
+    Q2 = [s.flow_rate(i)[0] for i in range(len(gs))]
+    assert max(abs(a - b) / abs(b) for a, b in zip(Q2, Qs)) <= 1e-8
     s.close()
 
 

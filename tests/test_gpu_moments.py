@@ -1,0 +1,133 @@
+"""Every moment of Sec. II.A on the GPU against the FP64 CPU oracle, on
+geometries where all of them are far from zero: perturbed density rho (zero
+fluid mean), velocities u1 and u2, temperature tau = int |v|^2 h f_eq - rho,
+and the shear stress P12 = 2 int v1 v2 h f_eq.  Plus the free-molecular limit
+delta = 0 of Poiseuille flow against its closed form, and device buffers
+taken from torch's caching allocator.
+
+Both solves run far below the bar (GPU tol 1e-12, oracle 1e-13), so the
+fields are compared element by element at 1e-8 max-abs (the velocity target
+is 1e-5 max-abs, the flow-rate target 1e-6 relative)."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.dense as dn
+from paper_1704_03126_amd.geometry import plane_channel, porous_discs, rough_channel
+
+pytestmark = pytest.mark.gpu
+
+MOMENTS = ("rho", "u1", "u2", "tau", "p12")
+
+
+@pytest.fixture(scope="module")
+def dvm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1704_03126_amd.dvm as d
+    d.load_library()
+    return d
+
+
+def _one_wall_rough(nx, ny, rows, cols):
+    """Rough channel with blocks on the bottom wall only (no mirror symmetry)."""
+    m = rough_channel(nx, ny, rows, cols).mask.copy()
+    m[ny // 2:, :] = 0
+    return m
+
+
+CASES = {
+    # name: (mask, periodic_y, delta, nv, alpha, precision)
+    "rough_one_wall_48x24": (lambda: _one_wall_rough(48, 24, 5, 24), False, 1.0, 16, 1.0, "fp64"),
+    "rough_two_strips_40x80": (lambda: rough_channel(40, 80, 16, 20).mask, False, 0.5, 12, 1.0, "fp64"),
+    "porous_64_phi0.6": (lambda: porous_discs(64, 0.6, 77).mask, True, 2.0, 12, 1.0, "fp64"),
+    "rough_maxwell_0.8": (lambda: _one_wall_rough(48, 24, 5, 24), False, 1.0, 12, 0.8, "fp64"),
+    "porous_64_fp32_refine": (lambda: porous_discs(64, 0.6, 77).mask, True, 2.0, 12, 1.0, "fp32_refine"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_all_moments_against_oracle(dvm, name):
+    make, periodic_y, delta, nv, alpha, prec = CASES[name]
+    mask = np.ascontiguousarray(make(), dtype=np.uint8)
+    ny, nx = mask.shape
+    print(f"[moments] {name}: {nx}x{ny} nv={nv} delta={delta} alpha={alpha} {prec}", flush=True)
+    ref = oracle.si_solve(mask, delta, nv, periodic_y=periodic_y, cells_per_H=float(ny), alpha=alpha,
+                          tol=1e-13)
+    assert ref.converged
+    # the comparison means something only where the fields are not ~0
+    for m in MOMENTS:
+        assert np.max(np.abs(getattr(ref, m))) > 1e-3, m
+    s = dvm.Solver(nv, 1, tol=1e-12, precision=dvm.DVM_FP32_REFINE if prec == "fp32_refine" else dvm.DVM_FP64)
+    s.set_geometry(0, mask, periodic_y, float(ny))
+    info = s.solve(0, delta, alpha)
+    assert info.status == "converged", info
+    Q, _ = s.flow_rate(0)
+    mom = s.moments(0, shear=True)
+    s.close()
+    assert abs(Q - ref.Q) <= 1e-9 * abs(ref.Q), (Q, ref.Q)
+    for m in MOMENTS:
+        err = np.max(np.abs(mom[m] - getattr(ref, m)))
+        assert err <= 1e-8, (m, err)
+    solid = mask != 0
+    for m in MOMENTS:
+        assert np.all(mom[m][solid] == 0.0), m
+
+
+@pytest.mark.parametrize("nx,ny,nv", [(1, 64, 32), (8, 40, 16)])
+def test_free_molecular_poiseuille_closed_form(dvm, nx, ny, nv):
+    """delta = 0 in a plane channel: the discrete problem's exact solution is
+    the flat free-molecular profile S = sum_{eta>0} W xi^2 / eta plus a wall
+    layer decaying as 3^-j (second-order upwind recursion with roots 1 and
+    1/3), Q = S (1 + 1.5 dx^2 (1 - 3^-n)).  nx = 8 runs the 2-D sweep on an
+    x-invariant flow."""
+    q = dn.quad(nv)
+    pos = q["eta"] > 0
+    S = float((q["W"][pos] * q["xi"][pos] ** 2 / q["eta"][pos]).sum())
+    g = plane_channel(ny, nx)
+    print(f"[moments] free molecular {nx}x{ny} nv={nv}", flush=True)
+    s = dvm.Solver(nv, 1, tol=1e-13)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    info = s.solve(0, 0.0)
+    assert info.status == "converged", info
+    Q, ka = s.flow_rate(0)
+    mom = s.moments(0)
+    s.close()
+    dx = 1.0 / ny
+    assert abs(Q - S * (1 + 1.5 * dx * dx * (1 - 3.0 ** -ny))) <= 1e-12 * S
+    j = np.arange(ny)
+    prof = S * (1.0 + 0.5 * dx * (3.0 ** -j + 3.0 ** -(ny - 1 - j)))
+    for x in range(nx):
+        assert np.max(np.abs(mom["u1"][:, x] - prof)) <= 1e-12 * S
+    assert np.max(np.abs(mom["u2"])) <= 1e-13
+    assert np.isinf(ka) or np.isnan(ka)            # k_a = Q / delta at delta = 0
+
+
+def test_torch_caching_allocator_backs_the_context(dvm):
+    """dvm_create's allocator hooks: every device buffer of the context comes
+    from torch's caching allocator, the solve is bitwise the one with
+    hipMalloc'd buffers, and dvm_destroy gives every byte back."""
+    import torch
+    g = rough_channel(40, 24, 5, 20)
+    nv = 12
+    results = []
+    alloc = dvm.TorchAllocator()
+    for use in (None, alloc):
+        s = dvm.Solver(nv, 1, tol=1e-11, allocator=use)
+        s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+        s.solve(0, 1.0, 0.9)
+        Q, _ = s.flow_rate(0)
+        mom = s.moments(0, shear=True)
+        gd, ga = s.grad(0)
+        if use is not None:
+            assert use.calls > 10 and use.bytes_held > 0
+            assert torch.cuda.memory_allocated() >= use.bytes_held
+        s.close()
+        results.append((Q, mom, gd, ga))
+    assert alloc.bytes_held == 0 and not alloc.live
+    (q0, m0, g0, a0), (q1, m1, g1, a1) = results
+    assert q0 == q1 and a0 == a1
+    assert np.array_equal(g0, g1)
+    for m in MOMENTS:
+        assert np.array_equal(m0[m], m1[m])

@@ -296,12 +296,24 @@ def test_profile_counts_real_sweeps_and_launch_shape(dvm):
     s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
     assert s.launch_shape() == ((0, 0), (0, 0))        # autotuned, not chosen yet
     info = s.solve(0, 1.0)
-    sweep_ms, n, other_ms = s.profile()
+    p = s.profile()
     (V, G), (V32, G32) = s.launch_shape()
     s.close()
     assert info.status == "converged"
-    assert n == info.iters and sweep_ms > 0 and other_ms > 0
+    assert p["n_sweeps"] == info.iters and p["sweep_ms"] > 0 and p["other_ms"] > 0
+    assert p["updates"] == info.iters * g.n_fluid * 12 * 12
+    assert p["n_sweeps32"] == 0 and p["updates32"] == 0
     assert (V, G) in [(4, 8), (8, 4), (4, 4), (2, 8)] and V * G == V32 * G32
+    # FP32 refinement: its FP32 correction sweeps and FP64 outer steps are
+    # timed apart, and every sweep of the solve is counted once
+    s = dvm.Solver(12, 1, tol=1e-10, profile=True, precision=dvm.DVM_FP32_REFINE)
+    s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
+    info = s.solve(0, 1.0)
+    p = s.profile()
+    s.close()
+    assert info.status == "converged"
+    assert p["n_sweeps"] == info.sweeps_fp64 and p["n_sweeps32"] == info.iters - info.sweeps_fp64
+    assert p["updates32"] == p["n_sweeps32"] * g.n_fluid * 144 and p["sweep32_ms"] > 0
 
 
 def test_largest_velocity_grid_and_narrow_channel(dvm):

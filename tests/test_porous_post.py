@@ -79,6 +79,9 @@ def test_library_matches_oracle(lib):
         assert abs(got["H_star"] - ref["H_star"]) <= 1e-10 * ref["H_star"]
         assert np.allclose(got["Kn_star"], ref["Kn_star"], rtol=1e-10, atol=0)
         assert np.allclose(got["ka_ratio"], ref["ka_ratio"], rtol=1e-10, atol=0)
+        # Kn and k_a of every sample come from the library too
+        assert np.allclose(got["Kn"], ref["Kn"], rtol=1e-14, atol=0)
+        assert np.allclose(got["k_a"], Q / d, rtol=1e-14, atol=0)
 
 
 def test_library_rejects_bad_sweeps(lib):
