@@ -258,6 +258,23 @@ int dvm_flow_rate(const dvm_ctx *ctx, int instance, double *Q, double *k_a);
 int dvm_get_moments(const dvm_ctx *ctx, int instance, double *rho, double *u1,
                     double *u2, double *tau, double *p12);
 
+/* For callers that cannot allocate memory during the call: code under HIP
+ * stream capture, serving loops and harnesses that forbid hipMalloc.  Same
+ * moments as dvm_get_moments, but every output is a DEVICE array of ny*nx
+ * doubles owned by the caller (any may be NULL), written asynchronously on
+ * the context's stream: the values are there once the stream has reached
+ * this call (synchronize the stream, or order later work after it).  The
+ * call allocates nothing, host or device: the staging it needs (the work
+ * items of the shear-stress pass and the density gauge) lives in a static
+ * device array of 1 MiB per GPU, set up by the context's first solve and
+ * held until the process ends.  That array is shared by every call on the
+ * same GPU and keeps the last call's contents: calls that overlap on one GPU
+ * (other threads, other streams) race.  DVM_EINVAL if the instance needs
+ * more than 65520 work items (strips x 4 x velocity groups), DVM_ESTATE
+ * before the instance's first solve. */
+int dvm_get_moments_noalloc(const dvm_ctx *ctx, int instance, double *rho,
+                            double *u1, double *u2, double *tau, double *p12);
+
 /* Gradient of Q by the discrete adjoint: dQ_ddelta[ny*nx] (0 in solids) with
  * respect to the per-cell rarefaction parameter, and dQ_dalpha with respect
  * to the accommodation coefficient, at the converged state of the last

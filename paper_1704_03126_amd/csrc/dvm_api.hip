@@ -139,11 +139,26 @@ struct KrylovWork {
 
 } // namespace
 
+// Static device scratch of the allocation-free entry point
+// (dvm_get_moments_noalloc): the density gauge (first 256 bytes) and the work
+// items of the instance's shear-stress pass.  One copy per GPU, held until the
+// process ends; every call on a GPU shares it.  Host code never uses the
+// array's name as an address: ensure_device() looks up each device's copy
+// with hipGetSymbolAddress (that device current) and keeps the pointer.
+constexpr size_t SCRATCH_BYTES = 1u << 20;
+constexpr size_t SCRATCH_HEAD = 256;
+constexpr long long SCRATCH_ITEMS = (long long)((SCRATCH_BYTES - SCRATCH_HEAD) / sizeof(WorkItem));
+constexpr int SCRATCH_MAX_DEV = 64;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+
 struct dvm_ctx {
     int nv = 0, K = 0, n_inst = 0;
     dvm_config cfg{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = -1;             // current device at the first solve
     DevAlloc dalloc;             // allocator hooks of dvm_create (both null: hipMalloc)
     // flow rate of every instance, reduced on the device at the end of each
     // solve (dvm_flow_rate reads it from here)
@@ -455,13 +470,29 @@ static void strip_layout(int ny, int &nstrips, int &strip_h)
 // host-side checks run without a device.
 static int ensure_device(dvm_ctx *c)
 {
-    if (c->stream)
+    if (c->device >= 0)
         return DVM_OK;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(DVM_EHIP, "no HIP device available");
-    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV)
+        return fail(DVM_EINVAL, "device index beyond the library's table");
+    {
+        // this device's copy of the static scratch, looked up once per device
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *p = nullptr;
+            HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            g_scratch_ptr[dev] = p;
+        }
+    }
+    if (!c->stream) {
+        HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    c->device = dev;
     return DVM_OK;
 }
 
@@ -3073,6 +3104,42 @@ int dvm_get_moments(const dvm_ctx *cc, int instance, double *rho, double *u1, do
         if (tau) tau[k] = f ? e - r : 0.0;
         if (p12) p12[k] = f ? shear[k] : 0.0;
     }
+    return DVM_OK;
+}
+
+int dvm_get_moments_noalloc(const dvm_ctx *cc, int instance, double *rho, double *u1, double *u2, double *tau,
+                            double *p12)
+{
+    dvm_ctx *ctx = const_cast<dvm_ctx *>(cc);
+    int rc = check_instance(ctx, instance);
+    if (rc)
+        return rc;
+    const HostInst &h = ctx->inst[instance];
+    if (!ctx->layout_ok || !h.has_state || ctx->device < 0)
+        return fail(DVM_ESTATE, "instance has not been solved");
+    void *sp = g_scratch_ptr[ctx->device];
+    if (!sp)
+        return fail(DVM_ESTATE, "static scratch of the device not set up");
+    const InstDev &d = ctx->idev[instance];
+    const long long nitems = (long long)d.nstrips * 4 * ctx->gq;
+    if (nitems > SCRATCH_ITEMS)
+        return fail(DVM_EINVAL, "instance needs " + std::to_string(nitems) + " work items for the shear-stress pass; "
+                                "the static scratch holds " + std::to_string(SCRATCH_ITEMS));
+    double *mean = static_cast<double *>(sp);
+    WorkItem *items = reinterpret_cast<WorkItem *>(static_cast<unsigned char *>(sp) + SCRATCH_HEAD);
+    if (p12) {
+        // one diagnostic sweep from the current state accumulates the shear
+        // stress; its work items are written into the scratch on the device
+        HIPCHK(launch_items(items, instance, d.nstrips, 4 * ctx->gq, ctx->stream));
+        SweepArgs<double> a = sweep_args(ctx, 1);
+        a.items = items;
+        const int mode = MODE_P12 | (h.field ? MODE_FIELD : 0) | (h.alpha < 1.0 ? MODE_SPEC : 0);
+        HIPCHK(launch_sweep<double>(a, (int)nitems, ctx->V, ctx->G, mode, ctx->stream));
+        HIPCHK(launch_sum1(mom_args(ctx), ctx->d_part5.p, ctx->d_aux.p, 2.0, ctx->max_cells, ctx->n_inst,
+                           ctx->stream));
+    }
+    HIPCHK(launch_moments_out(ctx->d_inst.p, instance, d.nx * d.ny, ctx->d_codes.p, ctx->d_mom.p, ctx->d_aux.p,
+                              mean, ctx->M2 / ctx->m0, rho, u1, u2, tau, p12, ctx->stream));
     return DVM_OK;
 }
 

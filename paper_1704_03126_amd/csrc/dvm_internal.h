@@ -195,6 +195,14 @@ struct GradArgs {
     const double *rows;       // row heights in units of H, [row_off + row]
 };
 hipError_t launch_grad(const GradArgs &a, int instance, int ncells, hipStream_t s);
+// the work items of one instance (strip-major, then velocity group) into dst
+hipError_t launch_items(WorkItem *dst, int inst, int nstrips, int ngroups, hipStream_t s);
+// moments of one instance on the device: *mean = fluid mean of rho (one
+// workgroup, fixed order), then rho - mean, u1, u2, tau = (e - mean e_per_rho)
+// - (rho - mean), p12 = shear[cell]; 0 in solids; null outputs are skipped
+hipError_t launch_moments_out(const InstDev *inst, int instance, int ncells, const uint8_t *codes,
+                              const double *mom, const double *shear, double *mean, double e_per_rho,
+                              double *rho, double *u1, double *u2, double *tau, double *p12, hipStream_t s);
 // q[i] = flow rate of instance i (Sec. III): sum over fluid cells of u1 dy / nx
 hipError_t launch_flow(const InstDev *inst, const uint8_t *codes, const double *mom, const double *rows,
                        double *q, int n_inst, hipStream_t s);

@@ -681,6 +681,74 @@ __global__ void __launch_bounds__(256) k_flow(const InstDev *inst, const uint8_t
         q[blockIdx.x] = red[0] / (double)in.nx;
 }
 
+// ------------------------------------------------- moments on the device
+// The work items of one instance (every strip x velocity group), in the
+// order the context lists them: strip-major, then group.
+__global__ void k_items(WorkItem *dst, int inst, int nstrips, int ngroups)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nstrips * ngroups)
+        dst[i] = WorkItem{inst, i / ngroups, i % ngroups, 0};
+}
+
+// Gauge of the density (constant h is a null vector): the mean of rho over
+// the instance's fluid cells, one workgroup, fixed summation order; written
+// to *mean (overwritten, nothing accumulates across calls).
+__global__ void __launch_bounds__(256) k_gauge(const InstDev *inst, int instance, const uint8_t *codes,
+                                               const double *mom, double *mean)
+{
+    __shared__ double sr[256];
+    __shared__ double sn[256];
+    const InstDev in = inst[instance];
+    const long long n = (long long)in.nx * in.ny;
+    double r = 0.0, c = 0.0;
+    for (long long k = threadIdx.x; k < n; k += 256) {
+        const long long cg = in.cell_off + k;
+        if (codes[cg] == 0xFF)
+            continue;
+        r += mom[cg * MOM_STRIDE + MOM_RHO];
+        c += 1.0;
+    }
+    sr[threadIdx.x] = r;
+    sn[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sr[threadIdx.x] += sr[threadIdx.x + o];
+            sn[threadIdx.x] += sn[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *mean = sn[0] > 0.0 ? sr[0] / sn[0] : 0.0;
+}
+
+// rho (zero fluid mean), u1, u2, tau = e - rho (both shifted by the gauge:
+// a constant h adds m0 to rho and M2 to e) and the shear stress from the
+// summed diagnostic partial; 0 in solids.  Any output may be null.
+__global__ void __launch_bounds__(256) k_moments_out(const InstDev *inst, int instance, const uint8_t *codes,
+                                                     const double *mom, const double *shear, const double *mean,
+                                                     double e_per_rho, double *rho, double *u1, double *u2,
+                                                     double *tau, double *p12)
+{
+    const InstDev in = inst[instance];
+    const long long n = (long long)in.nx * in.ny;
+    const long long k = blockIdx.x * 256ll + threadIdx.x;
+    if (k >= n)
+        return;
+    const long long cg = in.cell_off + k;
+    const bool f = codes[cg] != 0xFF;
+    const double *m = mom + cg * MOM_STRIDE;
+    const double rm = *mean;
+    const double r = f ? m[MOM_RHO] - rm : 0.0;
+    const double e = f ? m[MOM_E] - rm * e_per_rho : 0.0;
+    if (rho) rho[k] = r;
+    if (u1) u1[k] = f ? m[MOM_U1] : 0.0;
+    if (u2) u2[k] = f ? m[MOM_U2] : 0.0;
+    if (tau) tau[k] = f ? e - r : 0.0;
+    if (p12) p12[k] = f ? shear[cg] : 0.0;
+}
+
 // ------------------------------------------------------------------ record
 template <typename T>
 __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
@@ -1096,6 +1164,26 @@ hipError_t launch_sum1(const MomArgs &a, const double *part5, double *out, doubl
                        int n_inst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sum1, dim3((max_cells + 255) / 256, n_inst), dim3(256), 0, s, a, part5, out, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_items(WorkItem *dst, int inst, int nstrips, int ngroups, hipStream_t s)
+{
+    const int n = nstrips * ngroups;
+    hipLaunchKernelGGL(k_items, dim3((n + 255) / 256), dim3(256), 0, s, dst, inst, nstrips, ngroups);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_out(const InstDev *inst, int instance, int ncells, const uint8_t *codes,
+                              const double *mom, const double *shear, double *mean, double e_per_rho,
+                              double *rho, double *u1, double *u2, double *tau, double *p12, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gauge, dim3(1), dim3(256), 0, s, inst, instance, codes, mom, mean);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_moments_out, dim3((ncells + 255) / 256), dim3(256), 0, s, inst, instance, codes, mom,
+                       shear, (const double *)mean, e_per_rho, rho, u1, u2, tau, p12);
     return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ SCHED_NAMES = {DVM_SCHED_SKEW: "skew", DVM_SCHED_WRAP: "wrap"}
 EXPORTED = ("dvm_create", "dvm_set_geometry", "dvm_solve", "dvm_solve_warm",
             "dvm_flow_rate", "dvm_get_moments", "dvm_grad", "dvm_destroy",
             "dvm_last_error", "dvm_version", "dvm_profile", "dvm_launch_shape",
-            "dvm_permeability", "dvm_set_driving", "dvm_set_row_heights")
+            "dvm_permeability", "dvm_set_driving", "dvm_set_row_heights",
+            "dvm_get_moments_noalloc")
 
 
 class DVMError(RuntimeError):
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH):
     lib.dvm_flow_rate.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
     lib.dvm_get_moments.argtypes = [P, ctypes.c_int, P, P, P, P, P]
+    lib.dvm_get_moments_noalloc.argtypes = [P, ctypes.c_int, P, P, P, P, P]
     lib.dvm_grad.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_double)]
     lib.dvm_profile.argtypes = [P, ctypes.POINTER(dvm_prof)]
     IP = ctypes.POINTER(ctypes.c_int)
@@ -311,6 +313,22 @@ class Solver:
         if shear:
             out["p12"] = p12
         return out
+
+    def moments_into(self, instance: int, rho=None, u1=None, u2=None, tau=None, p12=None):
+        """dvm_get_moments_noalloc: the moments written into caller-owned
+        device tensors (float64, ny x nx, contiguous; any may be None) on the
+        context's stream, with no allocation."""
+        ny, nx = self.shapes[instance]
+        ptrs = []
+        for t in (rho, u1, u2, tau, p12):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and
+                    t.is_contiguous() and t.numel() == ny * nx):
+                raise ValueError("outputs must be contiguous float64 device tensors of the grid's size")
+            ptrs.append(ctypes.c_void_p(t.data_ptr()))
+        _check(self._lib.dvm_get_moments_noalloc(self._h, instance, *ptrs))
 
     def profile(self) -> dict:
         """Sweep timings since the last call (profile=True contexts): total
