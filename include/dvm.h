@@ -61,13 +61,18 @@ extern "C" {
                                method); GMRES takes over an instance whose
                                iteration stops contracting, and is tried on
                                one that contracts slowly (q > 0.98 with over
-                               1000 iterations to go), kept while each cycle
-                               reduces the residual 1.5 x faster than the
-                               plain iteration per unit of work (sweeps, the
-                               orthogonalisation counted in sweep
-                               equivalents: deterministic); with
-                               DVM_FP32_REFINE an FP32 correction iteration
-                               slower than q = 0.995 continues in FP64      */
+                               1000 iterations to go), kept while its cycles
+                               together reduce the residual 1.5 x faster than
+                               the plain iteration per unit of work (sweeps,
+                               the orthogonalisation counted in sweep
+                               equivalents: deterministic).  With
+                               DVM_FP32_REFINE the FP32 correction iteration
+                               is extrapolated the same way (where its
+                               tolerance is far above the extrapolated FP32
+                               rounding), and a correction that contracts
+                               slowly or not at all continues in GMRES whose
+                               Krylov steps are FP32 sweeps (each cycle from
+                               the FP64 residual)                            */
 #define DVM_ACCEL_NONE 1    /* plain source iteration only (the paper's)      */
 #define DVM_ACCEL_GMRES 2   /* restarted GMRES on the fixed-point map of the
                                iteration from the start                       */

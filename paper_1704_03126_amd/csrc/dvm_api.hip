@@ -130,10 +130,11 @@ struct KrylovWork {
     DevBuf<VSeg> gseg, sseg;
     DevBuf<VChunk> ch;
     DevBuf<int> c0, nc;
+    DevBuf<VSeg2> seg2;  // FP32 correction state of the slots (mixed-precision steps)
     void release()
     {
         V.release(); x.release(); w.release(); part.release(); c1.release(); c2.release(); y.release();
-        gseg.release(); sseg.release(); ch.release(); c0.release(); nc.release();
+        gseg.release(); sseg.release(); ch.release(); c0.release(); nc.release(); seg2.release();
     }
 };
 
@@ -211,6 +212,7 @@ struct dvm_ctx {
     KrylovWork kw;
     std::vector<long long> sweeps_done;   // per instance, last solve
     std::vector<long long> sweeps64_done; // of which FP64 sweeps
+    std::vector<long long> gmres_s64;     // FP64 sweeps of the instance's last GMRES run
     std::vector<long long> sweeps_wasted;   // before a restart in the skewed order
     std::vector<long long> sweeps64_wasted; // of which FP64 sweeps
     // AUTO: a slow plain iteration is handed to GMRES on trial; per instance
@@ -226,6 +228,10 @@ struct dvm_ctx {
     DevBuf<SolveState> d_st32;
     DevBuf<VSeg2> d_seg32;
     int nseg32 = 0;
+    // layout of the correction state vector of the live refinement slots
+    // (offset and length per instance, -1 when not live; total length)
+    std::vector<long long> dc_off, dc_len;
+    long long dc_n = 0;
 
     // captured iteration blocks: [0] forward, [1] adjoint, [2] FP32 correction
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
@@ -1002,7 +1008,8 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         HIPCHK(launch_moments(m, c->max_cells, c->n_inst, c->stream));
         HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
         HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
-        HIPCHK(launch_status(c->d_st32.p, c->n_inst, refine_inner_tol(c), c->cfg.max_iter, c->stream));
+        HIPCHK(launch_status(c->d_st32.p, c->n_inst, refine_inner_tol(c), c->cfg.max_iter, STOP_FLOOR32,
+                             c->stream));
         return DVM_OK;
     }
     const int mode = solve_mode(c) | (adj ? MODE_ADJ : xu_flag(c, c->V));
@@ -1011,7 +1018,7 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         HIPCHK(hipEventRecord(e1, c->stream));
     HIPCHK(launch_moments(mom_args(c, adj), c->max_cells, c->n_inst, c->stream));
     HIPCHK(launch_record<double>(rec_args(c, adj), c->max_cells, c->n_inst, c->stream));
-    HIPCHK(launch_status(adj ? c->d_st_adj.p : c->d_st.p, c->n_inst, c->cfg.tol, c->cfg.max_iter,
+    HIPCHK(launch_status(adj ? c->d_st_adj.p : c->d_st.p, c->n_inst, c->cfg.tol, c->cfg.max_iter, STOP_FLOOR64,
                          c->stream));
     if (prof) {
         HIPCHK(hipEventRecord(e2, c->stream));
@@ -1070,7 +1077,7 @@ static bool debug_on()
 
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
                      const std::vector<long long> &prior, const std::vector<char> *trial = nullptr,
-                     std::vector<char> *reverted = nullptr);
+                     std::vector<char> *reverted = nullptr, bool mixed = false);
 
 static long long state_segments(const dvm_ctx *c, int i, int pw, long long voff, std::vector<VSeg> *g,
                                 std::vector<VSeg> *sc);
@@ -1150,6 +1157,66 @@ static int extrapolate(dvm_ctx *c, int kind, const std::vector<int> &cand, const
     return DVM_OK;
 }
 
+// The same extrapolation for the FP32 correction iteration of the
+// refinement, e <- L32 e + r: its state (FP64 moments, FP32 seam, wrap and
+// wall values) is read into FP64 vectors in the layout of the live
+// refinement slots, combined there, and written back (FP32 parts rounded).
+static int extrapolate32(dvm_ctx *c, const std::vector<int> &cand, const std::vector<double> &q,
+                         std::vector<SolveState> &st)
+{
+    const long long n = c->dc_n;
+    if (n == 0)
+        return DVM_OK;
+    KrylovWork &kw = c->kw;
+    if (kw.x.n < (size_t)n)
+        HIPCHK(kw.x.alloc(n));
+    if (kw.w.n < (size_t)n)
+        HIPCHK(kw.w.alloc(n));
+    // x_k: the state the next sweep reads; then x_{k+1} = L32 x_k + r
+    HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), kw.x.p, 2, c->stream));
+    double upd = 0.0;
+    for (int i = 0; i < c->n_inst; ++i)
+        if (st[i].active)
+            upd += (double)c->inst[i].nfluid * c->K;
+    int rc = enqueue_iteration(c, 2);
+    if (rc)
+        return rc;
+    HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), kw.w.p, 2, c->stream));
+    HIPCHK(hipMemcpyAsync(st.data(), c->d_st32.p, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->cfg.profile && (rc = collect_profile(c, 1, upd)))
+        return rc;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        const int i = cand[k];
+        if (!st[i].active || c->dc_off[i] < 0)
+            continue;       // stopped in the extra iteration: keep x_{k+1}
+        const double f = q[k] / (1.0 - q[k]);
+        const long long o = c->dc_off[i], len = c->dc_len[i];
+        HIPCHK(launch_axpy(kw.x.p + o, kw.w.p + o, -1.0, len, c->stream));   // x_k - x_{k+1}
+        HIPCHK(launch_axpy(kw.w.p + o, kw.x.p + o, -f, len, c->stream));
+    }
+    HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), kw.w.p, 1, c->stream));
+    // records of the next sweep from the extrapolated moments
+    HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
+    HIPCHK(hipMemcpyAsync(st.data(), c->d_st32.p, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < cand.size(); ++k) {
+        SolveState &s = st[cand[k]];
+        if (!s.active)
+            continue;
+        s.maxdiff_bits = s.maxabs_bits = 0ull;
+        s.eps_prev = 0.0;
+        s.npass = 0;
+        s.qfloor = std::max(s.qfloor, q[k]);
+    }
+    HIPCHK(hipMemcpyAsync(c->d_st32.p, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DVM_OK;
+}
+
 // Replay blocks of iterations until no instance of [i0, i1) is active.  A
 // stalled instance is stopped and flagged in stalled[] (its state is that of
 // a completed iteration).
@@ -1172,7 +1239,7 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
     const int B = c->cfg.block_iters > 0 ? c->cfg.block_iters : 32;
     const long long cap = c->cfg.max_iter;
     const long long W = 64;
-    const double tol = kind == 2 ? refine_inner_tol(c) : c->cfg.tol;
+    const double tol = c->cfg.tol;
     SolveState *dst = kind == 1 ? c->d_st_adj.p : kind == 2 ? c->d_st32.p : c->d_st.p;
     struct Hist {
         long long it;
@@ -1183,7 +1250,7 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
     // relative change at block ends since the last extrapolation; an
     // instance whose relative change, a block after an extrapolation, is
     // above the one the extrapolation started from is not extrapolated again
-    const bool extrap = c->cfg.accel == DVM_ACCEL_AUTO && kind != 2;
+    const bool extrap = c->cfg.accel == DVM_ACCEL_AUTO;
     // FP32 correction iterations (AUTO): one whose rate settles above 0.995
     // with more than 1000 iterations to go stops (stalled = 3); the
     // refinement continues that instance in FP64, where GMRES can take over
@@ -1223,7 +1290,7 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                 for (const auto &e : hv)
                     if (e.it <= it - W)
                         old = &e;
-                if (old && old->eps > 0.0 && st[i].eps > tol) {
+                if (old && old->eps > 0.0 && st[i].eps > (st[i].tol > 0.0 ? st[i].tol : tol)) {
                     const bool runaway = !(st[i].eps < 0.95 * old->eps) && st[i].amax > 1.1 * old->amax;
                     const bool flat = !(st[i].eps < 0.995 * old->eps);
                     if (runaway || (flat && !(grow_only && (*grow_only)[i]))) {
@@ -1243,7 +1310,7 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
         }
         if (!running)
             return DVM_OK;
-        if (extrap || slow32) {
+        if (extrap) {
             // a settled rate: per-iteration contraction over the last two
             // blocks agreeing to 5% of the gap 1 - q, and q <= 0.98 (the
             // factor q/(1-q) also multiplies the next mode's error: closer
@@ -1260,7 +1327,13 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                     no_extrap[i] = 1;
                     continue;
                 }
-                if (e.size() < 3 || !(st[i].eps > tol) || !(st[i].eps > 1e-13))
+                const double tli = st[i].tol > 0.0 ? st[i].tol : tol;
+                // what still separates the instance from its stop rule: the
+                // change itself, or below the tolerance the a-posteriori
+                // bound (a slow iteration spends most of its sweeps with a
+                // change below the tolerance and a bound above it)
+                const double err = std::min(std::max(st[i].eps, std::isnan(st[i].est) ? 0.0 : st[i].est), 1e300);
+                if (e.size() < 3 || !(err > tli) || !(st[i].eps > 1e-13))
                     continue;
                 const double e0 = e[e.size() - 3], e1 = e[e.size() - 2], e2 = e.back();
                 if (!(e0 > 0.0 && e1 > 0.0 && e2 > 0.0))
@@ -1270,21 +1343,26 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                 if (debug_on())
                     std::fprintf(stderr, "[dvm rate] inst %d after %lld: eps %.3e q %.5f (previous block %.5f)%s\n",
                                  i, st[i].iter - iter0[i], st[i].eps, qa, qb, settled ? " settled" : "");
-                if (slow32) {
-                    const double tli = st[i].tol > 0.0 ? st[i].tol : tol;
-                    if (qa > 0.995 && qa < 1.0 && settled && st[i].eps > tli &&
-                        std::log(tli / st[i].eps) / std::log(qa) > 1000.0) {
-                        st[i].active = 0;
-                        (*stalled)[i] = 3;
-                        trial_stop = true;
-                    }
-                } else if (qa > 0.5 && qa <= 0.98 && settled) {
+                // the FP32 correction iteration: extrapolating its state also
+                // multiplies the state's FP32 rounding (about 6e-8 of it) by
+                // q/(1-q); only where the correction's own tolerance stays far
+                // above that
+                const bool quiet = kind != 2 || tli >= 2e-6 * qa / (1.0 - qa);
+                if (slow32 && !(no_trial && (*no_trial)[i]) && qa > 0.98 && qa < 1.0 && settled &&
+                    std::log(tol / err) / std::log(qa) > 1000.0) {
+                    // (the iterations predicted to the outer tolerance, as for
+                    // the FP64 iteration's GMRES trial)
+                    st[i].active = 0;
+                    (*stalled)[i] = 3;
+                    c->trial_q[i] = qa;
+                    trial_stop = true;
+                } else if (qa > 0.5 && qa <= 0.98 && settled && quiet) {
                     cand.push_back(i);
                     qs.push_back(qa);
                     eps_at[i] = st[i].eps;
                     e.clear();
-                } else if (stalled && no_trial && !(*no_trial)[i] && qa > 0.98 && qa < 1.0 && settled &&
-                           std::log(tol / st[i].eps) / std::log(qa) > 1000.0) {
+                } else if (kind != 2 && stalled && no_trial && !(*no_trial)[i] && qa > 0.98 && qa < 1.0 &&
+                           settled && std::log(tol / err) / std::log(qa) > 1000.0) {
                     st[i].active = 0;
                     (*stalled)[i] = 3;
                     c->trial_q[i] = qa;
@@ -1302,7 +1380,7 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                     return DVM_OK;
             }
             if (!cand.empty()) {
-                rc = extrapolate(c, kind, cand, qs, st);
+                rc = kind == 2 ? extrapolate32(c, cand, qs, st) : extrapolate(c, kind, cand, qs, st);
                 if (rc)
                     return rc;
             }
@@ -1335,6 +1413,7 @@ static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &ite
     // an instance whose GMRES trial lost to the plain iteration is not tried
     // again and stays plain; base = its sweeps before the current plain pass
     std::vector<char> no_trial(c->n_inst, gm ? 0 : 1);
+    std::vector<int> ntrial(c->n_inst, 0);    // GMRES trials handed back so far
     std::vector<long long> iter0 = iter0_in, base(c->n_inst, 0);
     std::vector<char> counted(c->n_inst, 0);   // finished in GMRES: count final
     SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
@@ -1384,10 +1463,14 @@ static int iterate(dvm_ctx *c, int i0, int i1, const std::vector<long long> &ite
             if (!reverted[i])
                 continue;
             again = true;
-            // back for good: neither another trial nor a takeover when the
-            // plain iteration then creeps (GMRES has just shown it is slower)
-            no_trial[i] = 1;
-            grow_only[i] = 1;
+            // a second trial once the plain iteration has shown its rate
+            // again from the state GMRES reached (the rate measured before
+            // the first trial can flatter it); after that, back for good:
+            // neither another trial nor a takeover when the plain iteration
+            // then creeps
+            ntrial[i] += 1;
+            no_trial[i] = ntrial[i] >= 2 ? 1 : 0;
+            grow_only[i] = no_trial[i];
             base[i] = c->sweeps_done[i];
             iter0[i] = st[i].iter;
             // the stop rule's ratio is held at least at the rate measured
@@ -1494,6 +1577,10 @@ struct GmresSlotHost {
     double beta = 0.0, sig = -1.0;
     bool live = true;
     long long sweeps = 0;
+    long long sweeps64 = 0;             // of this run's sweeps, the FP64 ones
+    double trial_red = 0.0;             // trial: -log of the residual reduction so far
+    double trial_cost = 0.0;            //        and its work in sweep equivalents
+    double beta_prev = 0.0;             // residual norm at the previous cycle's start
 };
 
 // smallest singular value of the k x k upper triangular R (column-major,
@@ -1540,16 +1627,17 @@ static double sigma_min_tri(const std::vector<double> &R, int ld, int k)
 // and the gathered state a few times: about 8 j + 60 bytes per element)
 // expressed at the bytes an FP64 sweep update costs in time (about 8 bytes
 // at the vector kernels' bandwidth: 200 us per 1.07e8 updates against
-// about 4.6 TB/s, measured on the rough channel).
-static double gmres_cycle_cost(int k, long long len, double updates_per_sweep)
+// about 4.6 TB/s, measured on the rough channel; an FP32 sweep update costs
+// about 5 such bytes, 0.6 of the FP64 one, measured on the uneven batch).
+static double gmres_cycle_cost(int k, long long len, double updates_per_sweep, double bytes_per_update)
 {
     const double bytes = (4.0 * k * (k + 1) + 60.0 * k) * (double)len;
-    return (double)(k + 1) + bytes / (8.0 * std::max(updates_per_sweep, 1.0));
+    return (double)(k + 1) + bytes / (bytes_per_update * std::max(updates_per_sweep, 1.0));
 }
 
 static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveState> &st,
                      const std::vector<long long> &prior, const std::vector<char> *trial,
-                     std::vector<char> *reverted)
+                     std::vector<char> *reverted, bool mixed)
 {
     const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 64;
     const int mode = solve_mode(c) | (adj ? MODE_ADJ : xu_flag(c, c->V));
@@ -1598,6 +1686,19 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         h.sn.assign(m, 0.0);
         h.g.assign(m + 1, 0.0);
     }
+    // mixed: Krylov steps with FP32 sweeps on the FP32 correction state
+    std::vector<SolveState> st32;
+    int nseg2 = 0;
+    if (mixed) {
+        if (adj || !c->fp32_ready)
+            return fail(DVM_ESTATE, "mixed-precision GMRES needs the FP32 state of the refinement");
+        st32.resize(c->n_inst);
+        HIPCHK(hipMemcpyAsync(st32.data(), c->d_st32.p, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (auto &s32 : st32)
+            s32.active = 0;
+    }
     // tables of the live slots (rebuilt when a slot finishes)
     std::vector<VSeg> gseg, sseg;
     std::vector<VChunk> chunks;
@@ -1626,6 +1727,29 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                               c->stream));
         HIPCHK(hipMemcpyAsync(kw.c0.p, c0.data(), ns * sizeof(int), hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(kw.nc.p, ncs.data(), ns * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        if (mixed) {
+            // the Krylov steps run on the FP32 correction state: its segments
+            // in this run's vector layout, and its active flags (the parity of
+            // each instance's FP32 state is left where the refinement left it)
+            std::vector<VSeg2> s2;
+            for (int q = 0; q < ns; ++q) {
+                st32[slots[q].inst].active = hs[q].live ? 1 : 0;
+                if (!hs[q].live)
+                    continue;
+                std::vector<VSeg> g0, g1;
+                state_segments(c, slots[q].inst, 0, slots[q].off, &g0, nullptr);
+                state_segments(c, slots[q].inst, 1, slots[q].off, &g1, nullptr);
+                for (size_t k = 0; k < g0.size(); ++k)
+                    s2.push_back(VSeg2{{g0[k].buf_off, g1[k].buf_off}, g0[k].vec_off, g0[k].len, g0[k].buf,
+                                       slots[q].inst});
+            }
+            nseg2 = (int)s2.size();
+            HIPCHK(kw.seg2.alloc(std::max<size_t>(s2.size(), 1)));
+            HIPCHK(hipMemcpyAsync(kw.seg2.p, s2.data(), s2.size() * sizeof(VSeg2), hipMemcpyHostToDevice,
+                                  c->stream));
+            HIPCHK(hipMemcpyAsync(c->d_st32.p, st32.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                                  c->stream));
+        }
         HIPCHK(hipStreamSynchronize(c->stream));
         return DVM_OK;
     };
@@ -1634,6 +1758,32 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         return rc;
     const int nch = (int)chunks.size();
     (void)nch;
+    // L v for the Krylov step from basis vector v (FP32): w = v - L v
+    auto krylov_step = [&](const float *v) -> int {
+        if (!mixed) {
+            HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, v, c->stream));
+            RecArgs<double> ra = rec_args(c, adj);
+            ra.homog = 1;
+            ra.monitor = 0;
+            HIPCHK(launch_record<double>(ra, c->max_cells, c->n_inst, c->stream));
+            HIPCHK(launch_sweep<double>(sweep_args(c, 0, adj), (int)c->items.size(), c->V, c->G, mode, c->stream));
+            HIPCHK(launch_moments(mom_args(c, adj), c->max_cells, c->n_inst, c->stream));
+            HIPCHK(launch_gather_sub32(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, v, c->stream));
+            return DVM_OK;
+        }
+        HIPCHK(launch_state32_basis(kw.seg2.p, nseg2, c->d_st32.p, state32(c), nullptr, v, 0, c->stream));
+        RecArgs<float> r32 = rec_args32(c);
+        r32.monitor = 0;
+        HIPCHK(launch_record<float>(r32, c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32,
+                                   solve_mode(c) | xu_flag(c, c->V32), c->stream));
+        MomArgs m32 = mom_args(c);
+        m32.mom = c->d_mom_d.p;
+        m32.st = c->d_st32.p;
+        HIPCHK(launch_moments(m32, c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_state32_basis(kw.seg2.p, nseg2, c->d_st32.p, state32(c), kw.w.p, v, 1, c->stream));
+        return DVM_OK;
+    };
     auto sweep_once = [&](bool homog, bool monitor) -> int {
         RecArgs<double> ra = rec_args(c, adj);
         ra.homog = homog ? 1 : 0;
@@ -1700,6 +1850,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 continue;
             SolveState &s = st[slots[q].inst];
             h.sweeps += 1;
+            h.sweeps64 += 1;
             const double dmax = __builtin_bit_cast(double, (long long)dev[slots[q].inst].maxdiff_bits);
             const double amax = __builtin_bit_cast(double, (long long)dev[slots[q].inst].maxabs_bits);
             const double eps = amax > 0.0 ? dmax / amax : (dmax == 0.0 ? 0.0 : INFINITY);
@@ -1711,10 +1862,28 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             int fin = 0;
             if (!(amax < 1e30) || eps != eps || !std::isfinite(h.beta))
                 fin = STATUS_DIVERGED;
-            else if (eps <= 16.0 * 2.220446049250313e-16 || est <= tol || h.beta == 0.0)
+            else if (eps <= STOP_FLOOR64 || est <= tol || h.beta == 0.0)
                 fin = STATUS_CONVERGED;
             else if (h.sweeps >= cap)
                 fin = STATUS_MAXITER;
+            if (!fin && mixed && reverted && h.beta_prev > 0.0 && h.beta > 0.9 * h.beta_prev) {
+                // FP32 Krylov steps no longer reduce the FP64 residual (the
+                // FP32 operator's rounding floor, or a stagnating restart):
+                // the instance goes back to its caller from x, marked 2
+                if (debug_on())
+                    std::fprintf(stderr, "[dvm gmres] inst %d mixed cycles stagnate (residual %.3e after %.3e)\n",
+                                 slots[q].inst, h.beta, h.beta_prev);
+                s.iter += 1;              // the state holds F(x), as for a finished slot
+                s.maxdiff_bits = s.maxabs_bits = 0ull;
+                h.live = false;
+                s.active = 0;
+                (*reverted)[slots[q].inst] = 2;
+                c->sweeps_done[slots[q].inst] = h.sweeps;
+                c->gmres_s64[slots[q].inst] = h.sweeps64;
+                changed = true;
+                continue;
+            }
+            h.beta_prev = h.beta;
             if (fin) {
                 if (debug_on())
                     std::fprintf(stderr, "[dvm gmres] inst %d done (%d) after %lld sweeps, eps %.3e est %.3e\n",
@@ -1727,6 +1896,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 h.live = false;
                 changed = true;
                 c->sweeps_done[slots[q].inst] = h.sweeps;
+                c->gmres_s64[slots[q].inst] = h.sweeps64;
             } else {
                 any = true;
             }
@@ -1749,10 +1919,8 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         int k = 0;
         for (int j = 0; j < m; ++j) {
             float *Vj = kw.V.p + (size_t)j * n;
-            HIPCHK(launch_scatter(kw.sseg.p, (int)sseg.size(), sb, Vj, c->stream));
-            if ((rc = sweep_once(true, false)))
+            if ((rc = krylov_step(Vj)))
                 return rc;
-            HIPCHK(launch_gather_sub32(kw.gseg.p, (int)gseg.size(), sb, kw.w.p, Vj, c->stream));
             // classical Gram-Schmidt; the second pass only where the first
             // one cancelled more than half of |w|^2
             if ((rc = dots(kw.w.p, j + 1, true, kw.c1.p)))
@@ -1822,10 +1990,12 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         HIPCHK(hipMemcpyAsync(kw.y.p, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, k, kw.y.p, cst, nullptr, c->stream));
         if (trials && k > 0) {
-            // a trial instance stays with GMRES while a cycle reduces its
-            // residual at least 1.5 times faster per unit of work than the
-            // plain iteration, both counted in sweeps of the instance
-            // (deterministic, so the path a solve takes does not depend on
+            // a trial instance stays with GMRES while its cycles together
+            // have reduced its residual at least 1.5 times faster per unit of
+            // work than the plain iteration, both counted in sweeps of the
+            // instance (a single stagnating cycle after a good one does not
+            // end the trial; the rule is deterministic, so the path a solve
+            // takes does not depend on
             // machine load or on the other instances of the batch)
             HIPCHK(hipStreamSynchronize(c->stream));
             bool back = false, left = false;
@@ -1836,18 +2006,22 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                     continue;
                 if ((*trial)[inst] && h.beta > 0.0) {
                     const double red = std::max(std::fabs(h.g[k]) / h.beta, 1e-300);
-                    const double cost = gmres_cycle_cost(k, slots[q].len, c->inst[inst].nfluid * (double)c->K);
-                    const double rate_g = -std::log(red) / cost;
+                    const double cost = gmres_cycle_cost(k, slots[q].len, c->inst[inst].nfluid * (double)c->K,
+                                                         mixed ? 5.0 : 8.0);
+                    h.trial_red += -std::log(red);
+                    h.trial_cost += cost;
+                    const double rate_g = h.trial_red / h.trial_cost;
                     const double rate_p = -std::log(c->trial_q[inst]);
                     if (debug_on())
                         std::fprintf(stderr, "[dvm trial] inst %d cycle of %d: residual x %.3e over %.1f "
-                                     "sweep-equivalents (%.3g per sweep) vs plain q %.5f (%.3g per sweep)\n",
-                                     inst, k, red, cost, rate_g, c->trial_q[inst], rate_p);
+                                     "sweep-equivalents (trial so far %.3g per sweep) vs plain q %.5f (%.3g per "
+                                     "sweep)\n", inst, k, red, cost, rate_g, c->trial_q[inst], rate_p);
                     if (rate_g < 1.5 * rate_p) {
                         h.live = false;
                         st[inst].active = 0;
                         (*reverted)[inst] = 1;
                         c->sweeps_done[inst] = h.sweeps;
+                        c->gmres_s64[inst] = h.sweeps64;
                         back = true;
                         continue;
                     }
@@ -1867,6 +2041,13 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                     return rc;
             }
         }
+    }
+    if (mixed) {
+        // the FP32 correction state is idle again
+        for (auto &s32 : st32)
+            s32.active = 0;
+        HIPCHK(hipMemcpyAsync(c->d_st32.p, st32.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
+                              c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     return DVM_OK;
@@ -1919,6 +2100,13 @@ static int ensure_fp32(dvm_ctx *c)
 }
 
 
+// The refinement of the active instances of [i0, i1).  Under AUTO an
+// instance whose FP32 correction iteration is slow goes on in GMRES with
+// FP32 Krylov steps, on trial; one that does not contract is taken over by
+// it.  What GMRES hands back (slower than the plain rate, or FP32 steps that
+// stagnate) continues in FP64 under AUTO, which has its own trials and
+// takeover: the FP32 correction iteration of such an instance has already
+// shown its rate.
 static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::vector<char> *need_skew)
 {
     int rc = ensure_fp32(c);
@@ -1942,6 +2130,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
         long long s32, s64;
         bool fallback;
         bool drop_e = false;   // this step's correction did not converge: not applied
+        bool slow = false;     // fell back for being slow (GMRES on trial)
     };
     std::vector<DSlot> slots;
     long long n = 0;
@@ -1964,9 +2153,14 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
         gseg.clear();
         sseg.clear();
         std::vector<VSeg2> s2;
+        c->dc_off.assign(c->n_inst, -1);
+        c->dc_len.assign(c->n_inst, 0);
+        c->dc_n = n;
         for (const auto &d : slots) {
             if (!d.live)
                 continue;
+            c->dc_off[d.inst] = d.off;
+            c->dc_len[d.inst] = d.len;
             state_segments(c, d.inst, d.pw, d.off, &gseg, &sseg);
             std::vector<VSeg> g0, g1;
             state_segments(c, d.inst, 0, d.off, &g0, nullptr);
@@ -2056,7 +2250,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
             int fin = 0;
             if (!(amax < 1e30) || eps != eps)
                 fin = STATUS_DIVERGED;
-            else if (eps <= 16.0 * 2.220446049250313e-16 || est <= tol)
+            else if (eps <= STOP_FLOOR64 || est <= tol)
                 fin = STATUS_CONVERGED;
             else if (d.s32 + d.s64 >= cap)
                 fin = STATUS_MAXITER;
@@ -2183,10 +2377,12 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
             if (s.status == STATUS_CONVERGED && s.eps > 0.0 && std::isfinite(s.est) && s.est > 0.0)
                 qn = std::min(s.est / (s.eps + s.est), 0.9999);
             d.q = std::max(d.q, qn);
-            // a very slow correction iteration (q > 0.995, measured) goes on
-            // in FP64 under AUTO, where GMRES can take over: there Krylov
-            // steps beat any cheaper sweep
-            // (stalled = 3: stopped early for that reason; its partial
+            // a slow correction iteration (under AUTO: rate settled above
+            // 0.98 with over 1000 iterations predicted, or q > 0.995 seen at
+            // convergence) goes on in GMRES with FP32 Krylov steps, on trial
+            // as in the FP64 iteration; one that does not contract at all
+            // (stalled) or diverges is taken over by it
+            // (stalled = 3: stopped early for being slow; its partial
             // correction is applied like a converged one)
             const bool slow = c->cfg.accel == DVM_ACCEL_AUTO &&
                               ((s.status == STATUS_CONVERGED && qn > 0.995) || stalled[d.inst] == 3);
@@ -2194,6 +2390,9 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
                 d.fallback = true;
                 d.live = false;
                 d.drop_e = !slow;
+                d.slow = slow;
+                if (slow && stalled[d.inst] != 3)      // (stalled = 3 left its measured rate)
+                    c->trial_q[d.inst] = std::min(d.q, 0.9999);
                 fb = true;
             }
         }
@@ -2242,6 +2441,54 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
     std::vector<long long> before(c->n_inst);
     for (const auto &d : slots)
         before[d.inst] = c->sweeps_done[d.inst];
+    if (c->cfg.accel == DVM_ACCEL_AUTO) {
+        // GMRES from x with FP32 Krylov steps: each cycle starts from the
+        // FP64 residual of one full FP64 iteration, so the FP32 steps limit
+        // only what one cycle gains (the same defect correction, in Krylov
+        // form).  Slow instances are on trial; what GMRES hands back goes on
+        // with the FP64 iteration below.
+        std::vector<char> trial(c->n_inst, 0), reverted(c->n_inst, 0);
+        std::vector<long long> prior(c->n_inst, 0);
+        for (const auto &d : slots)
+            if (d.fallback) {
+                trial[d.inst] = d.slow ? 1 : 0;
+                prior[d.inst] = before[d.inst];
+                c->gmres_s64[d.inst] = 0;
+            }
+        if ((rc = gmres_run(c, i0, i1, false, st, prior, &trial, &reverted, true)))
+            return rc;
+        bool any_rev = false;
+        for (auto &d : slots) {
+            if (!d.fallback)
+                continue;
+            c->sweeps64_done[d.inst] += c->gmres_s64[d.inst];
+            before[d.inst] = c->sweeps_done[d.inst];
+            if (reverted[d.inst]) {
+                SolveState &s = st[d.inst];
+                s.active = 1;
+                s.status = STATUS_RUNNING;
+                s.npass = 0;
+                s.eps_prev = 0.0;
+                s.qfloor = std::max(s.qfloor, c->trial_q[d.inst]);
+                any_rev = true;
+            } else {
+                d.fallback = false;     // finished in GMRES: counts are final
+            }
+        }
+        if (!any_rev) {
+            for (const auto &d : slots)
+                c->sweeps_done[d.inst] = before[d.inst];
+            return DVM_OK;
+        }
+        for (int i = 0; i < c->n_inst; ++i)
+            iter0[i] = st[i].iter;
+        HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
+        for (const auto &d : slots)
+            if (d.fallback)
+                st[d.inst].maxdiff_bits = st[d.inst].maxabs_bits = 0ull;
+        if ((rc = upload(c->d_st.p, st)))
+            return rc;
+    }
     rc = iterate(c, i0, i1, iter0, false, st, need_skew);
     // iterate() recounts every instance of [i0, i1): the ones that did not
     // fall back keep their refinement counts
@@ -2878,6 +3125,7 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
     ctx->sweeps_done.assign(n_instances, 0);
     ctx->trial_q.assign(n_instances, 0.0);
     ctx->sweeps64_done.assign(n_instances, 0);
+    ctx->gmres_s64.assign(n_instances, 0);
     ctx->sweeps_wasted.assign(n_instances, 0);
     ctx->driving.assign(n_instances, dvm_ctx::Driving{});
     ctx->sweeps64_wasted.assign(n_instances, 0);

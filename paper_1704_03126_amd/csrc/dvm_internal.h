@@ -208,7 +208,11 @@ hipError_t launch_flow(const InstDev *inst, const uint8_t *codes, const double *
                        double *q, int n_inst, hipStream_t s);
 template <typename T>
 hipError_t launch_record(const RecArgs<T> &a, int max_cells, int n_inst, hipStream_t s);
-hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, hipStream_t s);
+// stop rule per instance; a relative change <= floor passes without the
+// a-posteriori bound (round-off level of the iterate's precision)
+constexpr double STOP_FLOOR64 = 16.0 * 2.220446049250313e-16;
+constexpr double STOP_FLOOR32 = 16.0 * 1.1920928955078125e-07;
+hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, double floor, hipStream_t s);
 hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_zero_f(float *p, size_t n, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
@@ -272,6 +276,11 @@ struct StateBufs32 {
 //       3 -- vec = state outputs of the sweep just run
 hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b, double *vec, int what,
                           hipStream_t s);
+// mixed-precision Krylov steps: what 0 -- FP32 state inputs of the next
+// sweep = v (an FP32 basis vector); what 1 -- w = v - FP32 state outputs of
+// the sweep just run
+hipError_t launch_state32_basis(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b, double *w,
+                                const float *v, int what, hipStream_t s);
 // y += a * x (n elements)
 hipError_t launch_axpy(double *y, const double *x, double a, size_t n, hipStream_t s);
 // w -= sum_j coef[slot][j] V_j; if vout: vout = w / hn, hn from coef[slot]

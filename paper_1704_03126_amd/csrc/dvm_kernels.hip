@@ -93,8 +93,20 @@ __device__ __forceinline__ T ldc(cptr<T> p, int i)
 // y-upwind value are pure renaming inside a chunk.
 constexpr int SWEEP_C = 6;
 
+// FP32 sweeps in 8-wave workgroups are held to 128 VGPRs (4 waves per SIMD):
+// with their half-size LDS staging two workgroups then share a CU, twice the
+// waves of the FP64 sweep to hide the LDS and DPP latencies of the diagonal
+// (measured on the uneven batch: 3.6 ms per sweep against 5.3 ms at the
+// compiler's 144 VGPRs, a few VGPRs spilled outside the step loop)
+template <typename T, int G>
+constexpr int sweep_waves_per_eu()
+{
+    return (sizeof(T) == 4 && G == 8) ? 4 : 1;
+}
+
 template <typename T, int V, int G, int MODE>
-__global__ void __launch_bounds__(64 * G) k_sweep(SweepArgs<T> a)
+__global__ void __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, G>())))
+k_sweep(SweepArgs<T> a)
 {
     constexpr bool FIELD = (MODE & MODE_FIELD) != 0;
     constexpr bool SPEC = (MODE & MODE_SPEC) != 0;
@@ -993,7 +1005,11 @@ __global__ void __launch_bounds__(256) k_grad_face(GradArgs a)
 }
 
 // ------------------------------------------------------------------ status
-__global__ void k_status(SolveState *st, int n, double tol, long long max_iter)
+// floor: a relative change at the round-off level of the iterate's storage
+// precision passes without the bound (16 ulp of FP64, or of FP32 for the
+// refinement's FP32 correction iteration, whose changes cannot drop below
+// the rounding of its state)
+__global__ void k_status(SolveState *st, int n, double tol, long long max_iter, double floor)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
@@ -1025,7 +1041,7 @@ __global__ void k_status(SolveState *st, int n, double tol, long long max_iter)
     const double tl = s.tol > 0.0 ? s.tol : tol;
     int pass = 0;
     double est = eps;
-    if (eps <= 16.0 * 2.220446049250313e-16) {
+    if (eps <= floor) {
         pass = 1;
     } else if (eps <= tl && s.eps_prev > 0.0) {
         const double rh = fmax(eps / s.eps_prev, s.qfloor);
@@ -1213,9 +1229,9 @@ hipError_t launch_record(const RecArgs<T> &a, int max_cells, int n_inst, hipStre
 template hipError_t launch_record<double>(const RecArgs<double> &, int, int, hipStream_t);
 template hipError_t launch_record<float>(const RecArgs<float> &, int, int, hipStream_t);
 
-hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, hipStream_t s)
+hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, double floor, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_status, dim3((n + 63) / 64), dim3(64), 0, s, st, n, tol, max_iter);
+    hipLaunchKernelGGL(k_status, dim3((n + 63) / 64), dim3(64), 0, s, st, n, tol, max_iter, floor);
     return hipGetLastError();
 }
 

@@ -369,6 +369,45 @@ hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, Stat
     return hipGetLastError();
 }
 
+// Krylov basis vector <-> FP32 correction state (mixed-precision GMRES):
+// what 0 -- state inputs of the next sweep (parity st.iter & 1 ^ 1) = v;
+// what 1 -- w = v - state outputs of the sweep just run (parity st.iter & 1).
+__global__ void __launch_bounds__(256) k_state32_basis(const VSeg2 *seg, const SolveState *st, StateBufs32 b,
+                                                       double *w, const float *v, int what)
+{
+    const VSeg2 sg = seg[blockIdx.x];
+    const int par = (int)(st[sg.inst].iter & 1);
+    const long long off = sg.off[what == 1 ? par : par ^ 1];
+    const float *vv = v + sg.vec_off;
+    double *ww = w ? w + sg.vec_off : nullptr;
+    if (sg.buf == 0) {
+        double *m = b.mom + off;
+        for (int i = threadIdx.x; i < sg.len; i += 256) {
+            if (what == 0)
+                m[i] = (double)vv[i];
+            else
+                ww[i] = (double)vv[i] - m[i];
+        }
+    } else {
+        float *f = b.b[sg.buf - 1] + off;
+        for (int i = threadIdx.x; i < sg.len; i += 256) {
+            if (what == 0)
+                f[i] = vv[i];
+            else
+                ww[i] = (double)vv[i] - (double)f[i];
+        }
+    }
+}
+
+hipError_t launch_state32_basis(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b, double *w,
+                                const float *v, int what, hipStream_t s)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_state32_basis, dim3(nseg), dim3(256), 0, s, seg, st, b, w, v, what);
+    return hipGetLastError();
+}
+
 __global__ void k_axpy(double *y, const double *x, double a, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
