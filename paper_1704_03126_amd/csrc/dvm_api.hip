@@ -2214,7 +2214,8 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
                 if (d.live)
                     pupd += (double)c->inst[d.inst].nfluid * c->K;
         }
-        HIPCHK(launch_sweep<double>(sweep_args(c, 0, false), (int)c->items.size(), c->V, c->G, mode, c->stream));
+        HIPCHK(launch_sweep<double>(sweep_args(c, 0, false), (int)c->items.size(), c->V, c->G,
+                                    mode | xu_flag(c, c->V), c->stream));
         if (c->cfg.profile) {
             HIPCHK(hipEventRecord(pe1, c->stream));
             c->ev_prec = 0;
