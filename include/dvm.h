@@ -141,6 +141,20 @@ typedef struct {
                                Krylov projection clamped to [1e-3, 1]         */
     int krylov_dim;         /* GMRES restart length; 0 -> 64 (max 64); at large
                                delta (Kn 0.01-0.03) a restart of 30 stagnated */
+    int persistent;         /* 1: run each block of block_iters iterations
+                               (FP64 forward and FP32 correction) as one
+                               cooperative launch that stays resident: per
+                               iteration the sweep's work items are drawn
+                               from a device counter, then moments, records
+                               and the stop rule run behind grid barriers,
+                               with per-instance stop flags and iteration
+                               counts on the device.  Results are bitwise
+                               those of the separate launches.  Applies with
+                               4 velocities per lane and 8 waves per
+                               workgroup and without per-face specular or
+                               gradient passes; other blocks (and profile =
+                               1) use the separate launches.  0 (default):
+                               separate launches, replayed as HIP graphs   */
 } dvm_config;
 
 /* Per-instance result of dvm_solve. */
@@ -321,6 +335,9 @@ typedef struct {
     double sweep32_ms;      /* FP32 sweep launches (DVM_FP32_REFINE)          */
     long n_sweeps32;
     double updates32;
+    long persistent_blocks; /* blocks run as one cooperative launch
+                               (persistent = 1; counted without profile too) */
+    long persistent_iters;  /*   the iterations those blocks held             */
 } dvm_prof;
 
 /* Totals since the previous call (then reset); out must not be NULL. */

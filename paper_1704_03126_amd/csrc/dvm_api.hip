@@ -228,6 +228,13 @@ struct dvm_ctx {
     DevBuf<SolveState> d_st32;
     DevBuf<VSeg2> d_seg32;
     int nseg32 = 0;
+
+    // persistent blocks (cfg.persistent): their arguments in device memory
+    // ([0] FP64 forward, [1] FP32 correction) with the host copy last sent,
+    // and the work counter of the sweep phase
+    DevBuf<unsigned char> d_pargs;
+    std::vector<unsigned char> pargs_sent[2];
+    DevBuf<unsigned int> d_ctr;
     // layout of the correction state vector of the live refinement slots
     // (offset and length per instance, -1 when not live; total length)
     std::vector<long long> dc_off, dc_len;
@@ -264,7 +271,7 @@ struct dvm_ctx {
         kw.release();
         d_srec32.release(); d_seam32.release(); d_wrap32.release(); d_fb32.release(); d_vt32.release();
         d_mom_d.release(); d_u1prev_d.release(); d_xr.release(); d_rr.release(); d_er.release();
-        d_st32.release(); d_seg32.release(); d_q.release();
+        d_st32.release(); d_seg32.release(); d_q.release(); d_pargs.release(); d_ctr.release();
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
     }
@@ -1028,8 +1035,107 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
     return DVM_OK;
 }
 
+// PARG_SLOT bytes of device memory per argument block of a persistent launch
+constexpr size_t PARG_SLOT = 1024;
+static_assert(sizeof(PersistArgs<double>) <= PARG_SLOT && sizeof(PersistArgs<float>) <= PARG_SLOT,
+              "persistent arguments exceed their slot");
+
+template <typename T>
+static int send_persist_args(dvm_ctx *c, int slot, const PersistArgs<T> &a, const PersistArgs<T> **dev)
+{
+    std::vector<unsigned char> &sent = c->pargs_sent[slot];
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&a);
+    if (sent.size() != sizeof(a) || std::memcmp(sent.data(), b, sizeof(a)) != 0) {
+        // a launch still queued may read the old arguments
+        if (!sent.empty())
+            HIPCHK(hipStreamSynchronize(c->stream));
+        sent.assign(b, b + sizeof(a));
+        HIPCHK(hipMemcpyAsync(c->d_pargs.p + slot * PARG_SLOT, sent.data(), sizeof(a), hipMemcpyHostToDevice,
+                              c->stream));
+    }
+    *dev = reinterpret_cast<const PersistArgs<T> *>(c->d_pargs.p + slot * PARG_SLOT);
+    return DVM_OK;
+}
+
+// A block of iterations of kind 0 (FP64 forward) or 2 (FP32 correction) as one
+// cooperative launch, where the sweep mode and shape allow it; *done false:
+// the caller runs the block as separate launches.
+static int enqueue_persist(dvm_ctx *c, int iters, int kind, bool *done)
+{
+    *done = false;
+    const bool f32 = kind == 2;
+    const int V = f32 ? c->V32 : c->V, G = f32 ? c->G32 : c->G;
+    const int mode = solve_mode(c) | xu_flag(c, V);
+    if (kind == 1 || V != 4 || G != 8 || (mode & ~(MODE_FIELD | MODE_XU)) != 0 || c->items.empty())
+        return DVM_OK;
+    if (!c->d_pargs.p) {
+        HIPCHK(c->d_pargs.alloc(2 * PARG_SLOT));
+        HIPCHK(c->d_ctr.alloc(1));
+        c->pargs_sent[0].clear();
+        c->pargs_sent[1].clear();
+    }
+    // the work counter starts every launch at 0 (these launches are never
+    // captured into a graph)
+    HIPCHK(hipMemsetAsync(c->d_ctr.p, 0, sizeof(unsigned int), c->stream));
+    hipError_t e;
+    if (f32) {
+        PersistArgs<float> a;
+        std::memset(&a, 0, sizeof(a));
+        a.sw = sweep_args32(c);
+        a.mom = mom_args(c);
+        a.mom.mom = c->d_mom_d.p;
+        a.mom.st = c->d_st32.p;
+        a.rec = rec_args32(c);
+        a.seg = c->nseg32 > 0 ? c->d_seg32.p : nullptr;
+        a.nseg = c->nseg32;
+        a.sb = state32(c);
+        a.rr = c->d_rr.p;
+        a.st = c->d_st32.p;
+        a.n_inst = c->n_inst;
+        a.nitems = (int)c->items.size();
+        a.max_iter = c->cfg.max_iter;
+        a.floor = STOP_FLOOR32;
+        a.ctr = c->d_ctr.p;
+        const PersistArgs<float> *dev = nullptr;
+        int rc = send_persist_args(c, 1, a, &dev);
+        if (rc)
+            return rc;
+        e = launch_persist<float>(dev, a.nitems, iters, refine_inner_tol(c), mode, c->stream);
+    } else {
+        PersistArgs<double> a;
+        std::memset(&a, 0, sizeof(a));
+        a.sw = sweep_args(c, 0, false);
+        a.mom = mom_args(c, false);
+        a.rec = rec_args(c, false);
+        a.st = c->d_st.p;
+        a.n_inst = c->n_inst;
+        a.nitems = (int)c->items.size();
+        a.max_iter = c->cfg.max_iter;
+        a.floor = STOP_FLOOR64;
+        a.ctr = c->d_ctr.p;
+        const PersistArgs<double> *dev = nullptr;
+        int rc = send_persist_args(c, 0, a, &dev);
+        if (rc)
+            return rc;
+        e = launch_persist<double>(dev, a.nitems, iters, c->cfg.tol, mode, c->stream);
+    }
+    if (e == hipErrorNotSupported)
+        return DVM_OK;
+    HIPCHK(e);
+    *done = true;
+    c->prof.persistent_blocks += 1;
+    c->prof.persistent_iters += iters;
+    return DVM_OK;
+}
+
 static int enqueue_block(dvm_ctx *c, int iters, int kind)
 {
+    if (c->cfg.persistent && !c->cfg.profile) {
+        bool done = false;
+        int rc = enqueue_persist(c, iters, kind, &done);
+        if (rc || done)
+            return rc;
+    }
     if (!c->cfg.use_graphs || c->cfg.profile) {
         for (int i = 0; i < iters; ++i) {
             int rc = enqueue_iteration(c, kind);
@@ -3102,6 +3208,8 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
         return fail(DVM_EINVAL, "unknown acceleration");
     if (c.krylov_dim < 0 || c.krylov_dim > 64)
         return fail(DVM_EINVAL, "krylov_dim must be in [0, 64]");
+    if (c.persistent != 0 && c.persistent != 1)
+        return fail(DVM_EINVAL, "persistent must be 0 or 1");
     int V = c.vel_per_lane ? c.vel_per_lane : 4;
     int G = c.waves_per_block ? c.waves_per_block : 8;
     bool okvg = (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) || (V == 2 && G == 8);

@@ -213,6 +213,7 @@ hipError_t launch_record(const RecArgs<T> &a, int max_cells, int n_inst, hipStre
 constexpr double STOP_FLOOR64 = 16.0 * 2.220446049250313e-16;
 constexpr double STOP_FLOOR32 = 16.0 * 1.1920928955078125e-07;
 hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, double floor, hipStream_t s);
+
 hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_zero_f(float *p, size_t n, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
@@ -269,6 +270,56 @@ struct StateBufs32 {
     double *mom;
     float *b[3];         // seams, wrap state, wall faces
 };
+// The FP32 correction's add on one segment: state outputs of the sweep just
+// run (parity par) += vec, elements i0, i0 + di, ...  FP32 values are added
+// in FP64 and rounded once.
+__device__ __forceinline__ void state32_add(const VSeg2 &sg, int par, StateBufs32 b, const double *vec, int i0,
+                                            int di)
+{
+    const double *v = vec + sg.vec_off;
+    const long long off = sg.off[par];
+    if (sg.buf == 0) {
+        double *m = b.mom + off;
+        for (int i = i0; i < sg.len; i += di)
+            m[i] += v[i];
+    } else {
+        float *f = b.b[sg.buf - 1] + off;
+        for (int i = i0; i < sg.len; i += di)
+            f[i] = (float)((double)f[i] + v[i]);
+    }
+}
+
+// Blocks of source iterations of a batch as one cooperative launch (plain
+// sweep modes: MODE_FIELD and MODE_XU only; 4 velocities per lane, 8 waves
+// per workgroup).  Per iteration: the sweep's work items taken from a device
+// counter, the moments, for the FP32 correction the add of rr (seg non-null),
+// the records with the stop statistics and the stop rule, each phase behind a
+// grid barrier; each phase computes what its separate kernel computes, in the
+// same order, so the results are those of the separate launches.
+template <typename T>
+struct PersistArgs {
+    SweepArgs<T> sw;
+    MomArgs mom;
+    RecArgs<T> rec;
+    const VSeg2 *seg;         // FP32 correction: the state add (null: none)
+    int nseg;
+    StateBufs32 sb;
+    const double *rr;
+    SolveState *st;           // the stop rule's states (those of sw, mom, rec)
+    int n_inst;
+    int nitems;
+    long long max_iter;
+    double floor;
+    unsigned int *ctr;        // work counter, 0 at entry
+};
+// iters iterations with the stop tolerance tol; dev_args in device memory,
+// unchanged until the launch has run, nitems its sw work items.
+// hipErrorNotSupported: mode outside the plain set, no cooperative launch on
+// the device, or iters * (nitems + grid) >= 2^31.
+template <typename T>
+hipError_t launch_persist(const PersistArgs<T> *dev_args, int nitems, int iters, double tol, int mode,
+                          hipStream_t s);
+
 // what: 0 -- state outputs of the sweep just run (parity st.iter & 1) += vec
 //            (instances that are not iterating are left alone)
 //       1 -- state inputs of the next sweep (parity (st.iter & 1) ^ 1) = vec

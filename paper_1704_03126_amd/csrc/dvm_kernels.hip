@@ -29,6 +29,7 @@
 //             convergence test.
 //   k_status  applies the stop rule of Sec. II.A per instance.
 #include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
 #include <stdint.h>
 
 #include "dvm_internal.h"
@@ -93,20 +94,22 @@ __device__ __forceinline__ T ldc(cptr<T> p, int i)
 // y-upwind value are pure renaming inside a chunk.
 constexpr int SWEEP_C = 6;
 
-// FP32 sweeps in 8-wave workgroups are held to 128 VGPRs (4 waves per SIMD):
-// with their half-size LDS staging two workgroups then share a CU, twice the
-// waves of the FP64 sweep to hide the LDS and DPP latencies of the diagonal
-// (measured on the uneven batch: 3.6 ms per sweep against 5.3 ms at the
-// compiler's 144 VGPRs, a few VGPRs spilled outside the step loop)
-template <typename T, int G>
+// Plain FP32 sweeps in 8-wave workgroups are held to 128 VGPRs (4 waves per
+// SIMD): with their half-size LDS staging two workgroups then share a CU,
+// twice the waves of the FP64 sweep to hide the LDS and DPP latencies of the
+// diagonal (measured on the uneven batch: 3.6 ms per sweep against 5.3 ms at
+// the compiler's 144 VGPRs).  The passes with face records (specular walls,
+// gradient) keep their registers: 128 would spill inside the step loop.
+template <typename T, int G, int MODE>
 constexpr int sweep_waves_per_eu()
 {
-    return (sizeof(T) == 4 && G == 8) ? 4 : 1;
+    return (sizeof(T) == 4 && G == 8 && (MODE & (MODE_SPEC | MODE_CKPT | MODE_GRAD)) == 0) ? 4 : 1;
 }
 
+// One work item of the sweep (instance, strip, velocity group) by the
+// calling workgroup; the body of k_sweep and of the persistent iteration.
 template <typename T, int V, int G, int MODE>
-__global__ void __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, G>())))
-k_sweep(SweepArgs<T> a)
+__device__ __forceinline__ void sweep_item(SweepArgs<T> a, int item)
 {
     constexpr bool FIELD = (MODE & MODE_FIELD) != 0;
     constexpr bool SPEC = (MODE & MODE_SPEC) != 0;
@@ -122,10 +125,14 @@ k_sweep(SweepArgs<T> a)
     constexpr int C = SWEEP_C;                 // steps per chunk
     // moments gathered: 4 (rho, u1, u2, e) and an extra one (P12 or gradient)
     constexpr int NACC = P12 ? 1 : (GRAD ? 5 : 4);
+    // moment partials: an FP64 sweep sums in FP64; an FP32 sweep (the
+    // refinement's correction, itself held in FP32) sums the V velocities of
+    // a lane in FP32 and the G waves of the group in FP64
+    using AccT = typename std::conditional<sizeof(T) == 4, float, double>::type;
     // steps per partial flush: the whole chunk unless LDS is short
-    // (FP32 sweeps and 4-wave workgroups: half the partial buffer, so two
-    // workgroups share a CU)
-    constexpr int FL = (FACES || NACC > 4 || G > 8 || G <= 4 || sizeof(T) == 4) ? C / 2 : C;
+    // (4-wave workgroups: half the partial buffer, so two workgroups share
+    // a CU)
+    constexpr int FL = (FACES || NACC > 4 || G > 8 || G <= 4) ? C / 2 : C;
     constexpr int P = G * V;                   // velocities of the group
     constexpr int UPE = 8 * sizeof(T) / 16;    // 16-byte units per record
     __shared__ __attribute__((aligned(16))) T st_rec[2][C][64][8];
@@ -133,11 +140,11 @@ k_sweep(SweepArgs<T> a)
     __shared__ int st_cell[2][C][64];
     __shared__ __attribute__((aligned(16))) T st_seam[2][C][2][P];
     __shared__ __attribute__((aligned(16))) FaceRec st_face[FACES ? 2 : 1][FACES ? C : 1][64];
-    __shared__ double lds_part[FL][G][64][NACC];
+    __shared__ AccT lds_part[FL][G][64][NACC];
     __shared__ T lds_rinv[P][NSTENCIL];
     __shared__ T lds_lut[NWPAIR][2];
 
-    const WorkItem it = a.items[blockIdx.x];
+    const WorkItem it = a.items[item];
     const InstDev in = a.inst[it.inst];
     if (!a.force && a.st[it.inst].active == 0)
         return;
@@ -289,7 +296,7 @@ k_sweep(SweepArgs<T> a)
 
     // velocity constants of this wave, for the whole pass
     T cxi[V], ceta[V], cqq[V], ccx[V], ccy[V];
-    double cw[V], cwxi[V], cweta[V], cwq[V];
+    AccT cw[V], cwxi[V], cweta[V], cwq[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int k = (kw + (XU ? 0 : v)) * VT_STRIDE;
@@ -299,12 +306,12 @@ k_sweep(SweepArgs<T> a)
         ceta[v] = ldc(vt, kv + VT_ETA);
         cqq[v] = ldc(vt, kv + VT_Q);
         ccy[v] = ldc(vt, kv + VT_CY);
-        cw[v] = (double)ldc(vt, kv + VT_W);
-        cwxi[v] = cw[v] * (double)cxi[v];
-        cweta[v] = cw[v] * (double)ceta[v];
-        cwq[v] = cw[v] * (double)cqq[v];
+        cw[v] = (AccT)ldc(vt, kv + VT_W);
+        cwxi[v] = cw[v] * (AccT)cxi[v];
+        cweta[v] = cw[v] * (AccT)ceta[v];
+        cwq[v] = cw[v] * (AccT)cqq[v];
     }
-    const double xi0 = (double)cxi[0];
+    const AccT xi0 = (AccT)cxi[0];
 
     // per-cell-delta mode also serves rows of unequal height (nonuniform
     // spacing across the channel): along y the face value extrapolated from
@@ -381,10 +388,10 @@ k_sweep(SweepArgs<T> a)
     // registers when the lane has no cell at this step (xa false)
     auto step = [&](int b, int s, int t, T *PA, T *PB, T *PX, T *HA, T *HB, bool hold, bool xa, int xr) {
         const int sl = s % FL;
-        double acc[NACC];
+        AccT acc[NACC];
 #pragma unroll
         for (int m = 0; m < NACC; ++m)
-            acc[m] = 0.0;
+            acc[m] = AccT(0);
         const T *rec = &st_rec[b][s][lane][0];
         const int code = st_code[b][s][lane];
         const int craw = st_cell[b][s][lane];
@@ -459,9 +466,9 @@ k_sweep(SweepArgs<T> a)
                 rinv = lds_rinv[wave * V + v][ci];
             }
             const T h = g * rinv;
-            const double hd = (double)h;
+            const AccT hd = (AccT)h;
             if (P12) {
-                acc[0] = fma(cwxi[v] * (double)ceta[v], hd, acc[0]);
+                acc[0] = fma(cwxi[v] * (AccT)ceta[v], hd, acc[0]);
             } else {
                 acc[0] = fma(cw[v], hd, acc[0]);
                 if (!XU)
@@ -589,39 +596,33 @@ k_sweep(SweepArgs<T> a)
     }
 }
 
+template <typename T, int V, int G, int MODE>
+__global__ void __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, G, MODE>())))
+k_sweep(SweepArgs<T> a)
+{
+    sweep_item<T, V, G, MODE>(a, blockIdx.x);
+}
+
 // ----------------------------------------------------------------- moments
 // 256 threads = 64 cells x 4 quadrants: each thread sums its quadrant's
 // groups in order, the four quadrant sums are combined in a fixed order
-__global__ void __launch_bounds__(256) k_moments(MomArgs a)
+// sum of the partials of quadrant q's velocity groups at cell cg (in order)
+__device__ __forceinline__ double4 moments_quadrant(const MomArgs &a, long long cg, int q)
 {
-    __shared__ double qs[4][64][4];
-    const int inst = blockIdx.y;
-    const InstDev in = a.inst[inst];
-    if (!a.force && a.st[inst].active == 0)
-        return;
-    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int c = blockIdx.x * 64 + l;
-    const bool valid = c < in.nx * in.ny;
-    const long long cg = in.cell_off + (valid ? c : 0);
-    const bool fluid = valid && a.codes[cg] != 0xFF;
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    if (fluid) {
-        for (int g = q * a.gq; g < (q + 1) * a.gq; ++g) {
-            const double4 p = *reinterpret_cast<const double4 *>(a.part + ((size_t)g * a.ncell + cg) * 4);
-            s0 += p.x;
-            s1 += p.y;
-            s2 += p.z;
-            s3 += p.w;
-        }
+    double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int g = q * a.gq; g < (q + 1) * a.gq; ++g) {
+        const double4 p = *reinterpret_cast<const double4 *>(a.part + ((size_t)g * a.ncell + cg) * 4);
+        s.x += p.x;
+        s.y += p.y;
+        s.z += p.z;
+        s.w += p.w;
     }
-    qs[q][l][0] = s0;
-    qs[q][l][1] = s1;
-    qs[q][l][2] = s2;
-    qs[q][l][3] = s3;
-    __syncthreads();
-    if (q != 0 || !valid)
-        return;
-    double *m = a.mom + cg * MOM_STRIDE;
+    return s;
+}
+
+// the cell's moments from its four quadrant sums, combined in quadrant order
+__device__ __forceinline__ void moments_store(double *m, const double4 (&qs)[4], bool fluid)
+{
     if (!fluid) {
         for (int i = 0; i < MOM_STRIDE; ++i)
             m[i] = 0.0;
@@ -629,12 +630,12 @@ __global__ void __launch_bounds__(256) k_moments(MomArgs a)
     }
     double r = 0, u1 = 0, u2 = 0, e = 0, fxp = 0, fxm = 0, fyp = 0, fym = 0;
     for (int qq = 0; qq < 4; ++qq) {
-        r += qs[qq][l][0];
-        u1 += qs[qq][l][1];
-        u2 += qs[qq][l][2];
-        e += qs[qq][l][3];
-        if ((qq & 1) == 0) fxp += qs[qq][l][1]; else fxm += qs[qq][l][1];
-        if ((qq & 2) == 0) fyp += qs[qq][l][2]; else fym += qs[qq][l][2];
+        r += qs[qq].x;
+        u1 += qs[qq].y;
+        u2 += qs[qq].z;
+        e += qs[qq].w;
+        if ((qq & 1) == 0) fxp += qs[qq].y; else fxm += qs[qq].y;
+        if ((qq & 2) == 0) fyp += qs[qq].z; else fym += qs[qq].z;
     }
     m[MOM_RHO] = r;
     m[MOM_U1] = u1;
@@ -644,6 +645,26 @@ __global__ void __launch_bounds__(256) k_moments(MomArgs a)
     m[MOM_FXM] = fxm;
     m[MOM_FYP] = fyp;
     m[MOM_FYM] = fym;
+}
+
+__global__ void __launch_bounds__(256) k_moments(MomArgs a)
+{
+    __shared__ double4 qs[4][64];
+    const int inst = blockIdx.y;
+    const InstDev in = a.inst[inst];
+    if (!a.force && a.st[inst].active == 0)
+        return;
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int c = blockIdx.x * 64 + l;
+    const bool valid = c < in.nx * in.ny;
+    const long long cg = in.cell_off + (valid ? c : 0);
+    const bool fluid = valid && a.codes[cg] != 0xFF;
+    qs[q][l] = fluid ? moments_quadrant(a, cg, q) : make_double4(0.0, 0.0, 0.0, 0.0);
+    __syncthreads();
+    if (q != 0 || !valid)
+        return;
+    const double4 mine[4] = {qs[0][l], qs[1][l], qs[2][l], qs[3][l]};
+    moments_store(a.mom + cg * MOM_STRIDE, mine, fluid);
 }
 
 // sum of one extra per-group partial (shear stress, gradient term) over the
@@ -762,6 +783,130 @@ __global__ void __launch_bounds__(256) k_moments_out(const InstDev *inst, int in
 }
 
 // ------------------------------------------------------------------ record
+// The record of one cell c of an instance (the body of k_record): the
+// collision gain and wall values of the next sweep, for every quadrant; diff
+// and absu receive |du1| and |u1| when the stop statistics are monitored.
+template <typename T>
+__device__ __forceinline__ void record_cell(const RecArgs<T> &a, const InstDev &in, int c, double &diff,
+                                            double &absu)
+{
+    const long long cg = in.cell_off + c;
+    const int code = a.codes[cg];
+    if (code == 0xFF)
+        return;
+    const double *m = a.mom + cg * MOM_STRIDE;
+    const double r = m[MOM_RHO], u1 = m[MOM_U1], u2 = m[MOM_U2], e = m[MOM_E];
+    const double t = (e - r * a.c2) / a.c4;
+    const double dl = in.field ? a.delta_field[cg] : in.delta;
+    T rec[8];
+    rec[0] = T(dl * (r / a.m0 - t * a.c2));
+    // drive: the pressure-gradient factor of the instance (forward); the adjoint
+    // is driven by -dQ/dh / W = -(dx / nx) xi
+    const double *rw = in.nonuniform ? a.rows + in.row_off : nullptr;
+    const double dyc = rw ? rw[c / in.nx] : 1.0 / in.inv_dx;
+    const double drive = a.homog ? 0.0 : a.adjoint ? -dyc / (double)in.nx : in.drive;
+    rec[1] = T(dl * (u1 / a.m2) + drive);
+    rec[2] = T(dl * (u2 / a.m2));
+    rec[3] = T(dl * t);
+    rec[6] = T(dl);
+    double gside[4], mside[4];
+    const int x = c % in.nx, y = c / in.nx;
+    for (int d = 0; d < 4; ++d) {
+        const int cd = (code >> (2 * d)) & 3;
+        const int od = d ^ 1;
+        const int co = (code >> (2 * od)) & 3;
+        // half-range flux moment of the velocities that cross side d
+        // outwards, and its sign as a flux through that face
+        const int hf = (d == SIDE_W) ? MOM_FXM : (d == SIDE_E) ? MOM_FXP
+                     : (d == SIDE_S) ? MOM_FYM : MOM_FYP;
+        const double sgn = (d == SIDE_W || d == SIDE_S) ? -1.0 : 1.0;
+        auto nbr = [&](int side) {
+            int nxx = x, nyy = y;
+            if (side == SIDE_W) nxx = (x + in.nx - 1) % in.nx;
+            else if (side == SIDE_E) nxx = (x + 1) % in.nx;
+            else if (side == SIDE_S) nyy = (y + in.ny - 1) % in.ny;
+            else nyy = (y + 1) % in.ny;
+            return in.cell_off + (long long)nyy * in.nx + nxx;
+        };
+        double gval = 0.0;
+        mside[d] = 0.0;
+        if (!a.adjoint) {
+            // the outer bottom / top wall of a channel may slide along
+            // x: its diffuse emission gains 2 U xi (Eq. diffuse1), a
+            // source term (left out of the homogeneous map)
+            if (cd == CODE_WALL && !in.periodic_y && !a.homog) {
+                if (d == SIDE_S && y == 0)
+                    mside[d] = 2.0 * in.alpha * in.u_bot;
+                else if (d == SIDE_N && y == in.ny - 1)
+                    mside[d] = 2.0 * in.alpha * in.u_top;
+            }
+            if (cd == CODE_WALL) {
+                // incident flux through the wall face on side d: the
+                // half-range flux of the cell, extrapolated from the
+                // neighbour on the opposite side unless that side is
+                // a wall as well (first-order face value)
+                double f = m[hf];
+                if (co != CODE_WALL && co != CODE_NONE) {
+                    // face value extrapolated across the cell through
+                    // its neighbour opposite the face
+                    double r = 0.5;
+                    if (in.nonuniform && d >= SIDE_S) {
+                        const double *rw = a.rows + in.row_off;
+                        const int yo = (int)((nbr(od) - in.cell_off) / in.nx);
+                        r = rw[y] / (rw[y] + rw[yo]);
+                    }
+                    f = (1.0 + r) * f - r * a.mom[nbr(od) * MOM_STRIDE + hf];
+                }
+                gval = in.alpha * sgn * f / a.D;
+            }
+        } else {
+            // transposed wall coupling: the diffuse wall of a face
+            // gathers the incident flux of the adjoint cell values and
+            // returns it to the two cells whose values built the
+            // face value (weights 1.5 / -0.5, or 1 next to a second
+            // wall on the opposite side)
+            // (rows of unequal height: weights 1 + r / -r of the
+            // face extrapolation, the neighbour's scaled by
+            // dy_c / dy_n as it enters the neighbour's row)
+            if (cd == CODE_WALL) {
+                double kap = 1.0;
+                if (co != CODE_WALL && co != CODE_NONE) {
+                    kap = 1.5;
+                    if (rw && d >= SIDE_S) {
+                        const double dyo = rw[(nbr(od) - in.cell_off) / in.nx];
+                        kap = 1.0 + dyc / (dyc + dyo);
+                    }
+                }
+                gval = kap * in.alpha * sgn * m[hf] / a.D;
+            } else if (cd == CODE_NEAR) {
+                double kn = -0.5;
+                if (rw && d >= SIDE_S) {
+                    const double dyn = rw[(nbr(d) - in.cell_off) / in.nx];
+                    kn = -(dyn / (dyn + dyc)) * (dyc / dyn);
+                }
+                gval = kn * in.alpha * sgn * a.mom[nbr(d) * MOM_STRIDE + hf] / a.D;
+            }
+        }
+        gside[d] = gval;
+    }
+    // one copy per quadrant, in that quadrant's sweep order
+    for (int qd = 0; qd < 4; ++qd) {
+        rec[4] = T(gside[(qd & 1) ? SIDE_E : SIDE_W]);
+        rec[5] = T(gside[(qd & 2) ? SIDE_N : SIDE_S]);
+        rec[7] = T(mside[(qd & 2) ? SIDE_N : SIDE_S]);
+        const long long pos = a.spos[cg * 4 + qd];
+        T *dst = a.srec + pos * 8;
+        for (int i = 0; i < 8; ++i)
+            dst[i] = rec[i];
+    }
+    if (a.monitor) {
+        const double up = a.u1prev[cg];
+        diff = fabs(u1 - up);
+        absu = fabs(u1);
+        a.u1prev[cg] = u1;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
 {
@@ -772,123 +917,8 @@ __global__ void __launch_bounds__(256) k_record(RecArgs<T> a)
         return;
     const int c = blockIdx.x * 256 + threadIdx.x;
     double diff = 0.0, absu = 0.0;
-    if (c < in.nx * in.ny) {
-        const long long cg = in.cell_off + c;
-        const int code = a.codes[cg];
-        if (code != 0xFF) {
-            const double *m = a.mom + cg * MOM_STRIDE;
-            const double r = m[MOM_RHO], u1 = m[MOM_U1], u2 = m[MOM_U2], e = m[MOM_E];
-            const double t = (e - r * a.c2) / a.c4;
-            const double dl = in.field ? a.delta_field[cg] : in.delta;
-            T rec[8];
-            rec[0] = T(dl * (r / a.m0 - t * a.c2));
-            // drive: the pressure-gradient factor of the instance (forward); the adjoint
-            // is driven by -dQ/dh / W = -(dx / nx) xi
-            const double *rw = in.nonuniform ? a.rows + in.row_off : nullptr;
-            const double dyc = rw ? rw[c / in.nx] : 1.0 / in.inv_dx;
-            const double drive = a.homog ? 0.0 : a.adjoint ? -dyc / (double)in.nx : in.drive;
-            rec[1] = T(dl * (u1 / a.m2) + drive);
-            rec[2] = T(dl * (u2 / a.m2));
-            rec[3] = T(dl * t);
-            rec[6] = T(dl);
-            double gside[4], mside[4];
-            const int x = c % in.nx, y = c / in.nx;
-            for (int d = 0; d < 4; ++d) {
-                const int cd = (code >> (2 * d)) & 3;
-                const int od = d ^ 1;
-                const int co = (code >> (2 * od)) & 3;
-                // half-range flux moment of the velocities that cross side d
-                // outwards, and its sign as a flux through that face
-                const int hf = (d == SIDE_W) ? MOM_FXM : (d == SIDE_E) ? MOM_FXP
-                             : (d == SIDE_S) ? MOM_FYM : MOM_FYP;
-                const double sgn = (d == SIDE_W || d == SIDE_S) ? -1.0 : 1.0;
-                auto nbr = [&](int side) {
-                    int nxx = x, nyy = y;
-                    if (side == SIDE_W) nxx = (x + in.nx - 1) % in.nx;
-                    else if (side == SIDE_E) nxx = (x + 1) % in.nx;
-                    else if (side == SIDE_S) nyy = (y + in.ny - 1) % in.ny;
-                    else nyy = (y + 1) % in.ny;
-                    return in.cell_off + (long long)nyy * in.nx + nxx;
-                };
-                double gval = 0.0;
-                mside[d] = 0.0;
-                if (!a.adjoint) {
-                    // the outer bottom / top wall of a channel may slide along
-                    // x: its diffuse emission gains 2 U xi (Eq. diffuse1), a
-                    // source term (left out of the homogeneous map)
-                    if (cd == CODE_WALL && !in.periodic_y && !a.homog) {
-                        if (d == SIDE_S && y == 0)
-                            mside[d] = 2.0 * in.alpha * in.u_bot;
-                        else if (d == SIDE_N && y == in.ny - 1)
-                            mside[d] = 2.0 * in.alpha * in.u_top;
-                    }
-                    if (cd == CODE_WALL) {
-                        // incident flux through the wall face on side d: the
-                        // half-range flux of the cell, extrapolated from the
-                        // neighbour on the opposite side unless that side is
-                        // a wall as well (first-order face value)
-                        double f = m[hf];
-                        if (co != CODE_WALL && co != CODE_NONE) {
-                            // face value extrapolated across the cell through
-                            // its neighbour opposite the face
-                            double r = 0.5;
-                            if (in.nonuniform && d >= SIDE_S) {
-                                const double *rw = a.rows + in.row_off;
-                                const int yo = (int)((nbr(od) - in.cell_off) / in.nx);
-                                r = rw[y] / (rw[y] + rw[yo]);
-                            }
-                            f = (1.0 + r) * f - r * a.mom[nbr(od) * MOM_STRIDE + hf];
-                        }
-                        gval = in.alpha * sgn * f / a.D;
-                    }
-                } else {
-                    // transposed wall coupling: the diffuse wall of a face
-                    // gathers the incident flux of the adjoint cell values and
-                    // returns it to the two cells whose values built the
-                    // face value (weights 1.5 / -0.5, or 1 next to a second
-                    // wall on the opposite side)
-                    // (rows of unequal height: weights 1 + r / -r of the
-                    // face extrapolation, the neighbour's scaled by
-                    // dy_c / dy_n as it enters the neighbour's row)
-                    if (cd == CODE_WALL) {
-                        double kap = 1.0;
-                        if (co != CODE_WALL && co != CODE_NONE) {
-                            kap = 1.5;
-                            if (rw && d >= SIDE_S) {
-                                const double dyo = rw[(nbr(od) - in.cell_off) / in.nx];
-                                kap = 1.0 + dyc / (dyc + dyo);
-                            }
-                        }
-                        gval = kap * in.alpha * sgn * m[hf] / a.D;
-                    } else if (cd == CODE_NEAR) {
-                        double kn = -0.5;
-                        if (rw && d >= SIDE_S) {
-                            const double dyn = rw[(nbr(d) - in.cell_off) / in.nx];
-                            kn = -(dyn / (dyn + dyc)) * (dyc / dyn);
-                        }
-                        gval = kn * in.alpha * sgn * a.mom[nbr(d) * MOM_STRIDE + hf] / a.D;
-                    }
-                }
-                gside[d] = gval;
-            }
-            // one copy per quadrant, in that quadrant's sweep order
-            for (int qd = 0; qd < 4; ++qd) {
-                rec[4] = T(gside[(qd & 1) ? SIDE_E : SIDE_W]);
-                rec[5] = T(gside[(qd & 2) ? SIDE_N : SIDE_S]);
-                rec[7] = T(mside[(qd & 2) ? SIDE_N : SIDE_S]);
-                const long long pos = a.spos[cg * 4 + qd];
-                T *dst = a.srec + pos * 8;
-                for (int i = 0; i < 8; ++i)
-                    dst[i] = rec[i];
-            }
-            if (a.monitor) {
-                const double up = a.u1prev[cg];
-                diff = fabs(u1 - up);
-                absu = fabs(u1);
-                a.u1prev[cg] = u1;
-            }
-        }
-    }
+    if (c < in.nx * in.ny)
+        record_cell(a, in, c, diff, absu);
     // block max, then one atomic per block (max is order independent)
     __shared__ double sd[256], sa[256];
     sd[threadIdx.x] = diff;
@@ -1009,12 +1039,8 @@ __global__ void __launch_bounds__(256) k_grad_face(GradArgs a)
 // precision passes without the bound (16 ulp of FP64, or of FP32 for the
 // refinement's FP32 correction iteration, whose changes cannot drop below
 // the rounding of its state)
-__global__ void k_status(SolveState *st, int n, double tol, long long max_iter, double floor)
+__device__ __forceinline__ void status_one(SolveState &s, double tol, long long max_iter, double floor)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    SolveState &s = st[i];
     if (s.active == 0)
         return;
     const double dmax = __builtin_bit_cast(double, (long long)s.maxdiff_bits);
@@ -1058,6 +1084,187 @@ __global__ void k_status(SolveState *st, int n, double tol, long long max_iter, 
     } else if (s.iter - s.iter0 >= max_iter) {
         s.status = STATUS_MAXITER;
         s.active = 0;
+    }
+}
+
+__global__ void k_status(SolveState *st, int n, double tol, long long max_iter, double floor)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        status_one(st[i], tol, max_iter, floor);
+}
+
+// ------------------------------------------------------------- persistent
+// instance that holds global cell cg (the cells of the instances follow one
+// another; an instance without cells holds none)
+__device__ __forceinline__ int inst_of_cell(const InstDev *inst, int n, long long cg)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (inst[mid].cell_off <= cg)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// k_moments over the grid: four consecutive lanes per cell, one quadrant
+// each, the first of them combines the four sums (the same order)
+__device__ __forceinline__ void persist_moments(const MomArgs &a, int n_inst, long long gtid, long long gthr)
+{
+    const int q = (int)(threadIdx.x & 3);
+    const int lead = (int)(threadIdx.x & 63) & ~3;
+    for (long long cg = gtid >> 2; cg < a.ncell; cg += gthr >> 2) {
+        const int inst = inst_of_cell(a.inst, n_inst, cg);
+        if (!a.force && a.st[inst].active == 0)
+            continue;
+        const bool fluid = a.codes[cg] != 0xFF;
+        const double4 s = fluid ? moments_quadrant(a, cg, q) : make_double4(0.0, 0.0, 0.0, 0.0);
+        double4 qs[4];
+        for (int k = 0; k < 4; ++k) {
+            qs[k].x = __shfl(s.x, lead + k, 64);
+            qs[k].y = __shfl(s.y, lead + k, 64);
+            qs[k].z = __shfl(s.z, lead + k, 64);
+            qs[k].w = __shfl(s.w, lead + k, 64);
+        }
+        if (q == 0)
+            moments_store(a.mom + cg * MOM_STRIDE, qs, fluid);
+    }
+}
+
+// k_record over the grid: chunks of NW * 64 consecutive cells; a chunk in one
+// instance folds its stop statistics with one atomic pair (max is order
+// independent), a chunk across instances with one pair per cell (a NaN there
+// is reported as +inf)
+template <typename T, int NW>
+__device__ __forceinline__ void persist_record(const RecArgs<T> &a, long long ncell, int n_inst,
+                                               double (&red)[2][NW])
+{
+    const int nthr = NW * 64;
+    for (long long c0 = (long long)blockIdx.x * nthr; c0 < ncell; c0 += (long long)gridDim.x * nthr) {
+        const long long cg = c0 + threadIdx.x;
+        const int i0 = inst_of_cell(a.inst, n_inst, c0);
+        const int i1 = inst_of_cell(a.inst, n_inst, (c0 + nthr < ncell ? c0 + nthr : ncell) - 1);
+        const bool valid = cg < ncell;
+        const int inst = (i0 == i1 || !valid) ? i0 : inst_of_cell(a.inst, n_inst, cg);
+        const bool act = valid && a.st[inst].active != 0;
+        double diff = 0.0, absu = 0.0;
+        if (act) {
+            const InstDev in = a.inst[inst];
+            record_cell(a, in, (int)(cg - in.cell_off), diff, absu);
+        }
+        if (!a.monitor)
+            continue;
+        if (i0 == i1) {
+            for (int o = 32; o > 0; o >>= 1) {
+                diff = fmax(diff, __shfl_xor(diff, o, 64));
+                absu = fmax(absu, __shfl_xor(absu, o, 64));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                red[0][threadIdx.x >> 6] = diff;
+                red[1][threadIdx.x >> 6] = absu;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0 && a.st[i0].active != 0) {
+                double dmax = red[0][0], amax = red[1][0];
+                for (int w = 1; w < NW; ++w) {
+                    dmax = fmax(dmax, red[0][w]);
+                    amax = fmax(amax, red[1][w]);
+                }
+                dmax = dmax != dmax ? __builtin_inf() : dmax;
+                amax = amax != amax ? __builtin_inf() : amax;
+                atomicMax(&a.st[i0].maxdiff_bits, (unsigned long long)__builtin_bit_cast(long long, dmax));
+                atomicMax(&a.st[i0].maxabs_bits, (unsigned long long)__builtin_bit_cast(long long, amax));
+            }
+            __syncthreads();
+        } else if (act) {
+            diff = diff != diff ? __builtin_inf() : diff;
+            absu = absu != absu ? __builtin_inf() : absu;
+            atomicMax(&a.st[inst].maxdiff_bits, (unsigned long long)__builtin_bit_cast(long long, diff));
+            atomicMax(&a.st[inst].maxabs_bits, (unsigned long long)__builtin_bit_cast(long long, absu));
+        }
+    }
+}
+
+// a struct of uniform values read from device memory into scalar registers
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S *p)
+{
+    static_assert(sizeof(S) % 4 == 0, "whole words");
+    S out;
+    const unsigned int *w = reinterpret_cast<const unsigned int *>(p);
+    unsigned int *o = reinterpret_cast<unsigned int *>(&out);
+    for (int i = 0; i < (int)(sizeof(S) / 4); ++i)
+        o[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    return out;
+}
+
+// The arguments stay in device memory and each phase reads its own after the
+// grid barrier before it (kept in registers across the whole loop they would
+// crowd out the sweep's).
+template <typename T, int V, int G, int MODE>
+__global__ void __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, G, MODE>())))
+k_persist(const PersistArgs<T> *pa, int iters, double tol)
+{
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    __shared__ int s_item;
+    __shared__ double red[2][G];
+    for (int j = 0; j < iters; ++j) {
+        {
+            // every workgroup claims until it draws past the end: iteration
+            // j's claims are the counter values j (nitems + grid) onwards
+            const int nitems = pa->nitems;
+            unsigned int *ctr = pa->ctr;
+            const unsigned int base = (unsigned int)j * (unsigned int)(nitems + gridDim.x);
+            for (;;) {
+                if (threadIdx.x == 0)
+                    s_item = (int)(atomicAdd(ctr, 1u) - base);
+                __syncthreads();
+                const int item = s_item;
+                __syncthreads();
+                if (item < 0 || item >= nitems)
+                    break;
+                const SweepArgs<T> sw = load_uniform(&pa->sw);
+                sweep_item<T, V, G, MODE>(sw, item);
+                __syncthreads();
+            }
+        }
+        grid.sync();
+        {
+            const MomArgs mom = load_uniform(&pa->mom);
+            persist_moments(mom, pa->n_inst, (long long)blockIdx.x * (64 * G) + threadIdx.x,
+                            (long long)gridDim.x * (64 * G));
+        }
+        grid.sync();
+        if (pa->seg) {
+            const VSeg2 *seg = pa->seg;
+            const int nseg = pa->nseg;
+            const StateBufs32 sb = pa->sb;
+            const double *rr = pa->rr;
+            const SolveState *st = pa->st;
+            for (int k = blockIdx.x; k < nseg; k += gridDim.x) {
+                const VSeg2 sg = seg[k];
+                if (st[sg.inst].active != 0)
+                    state32_add(sg, (int)(st[sg.inst].iter & 1), sb, rr, threadIdx.x, 64 * G);
+            }
+            grid.sync();
+        }
+        {
+            const RecArgs<T> rec = load_uniform(&pa->rec);
+            persist_record<T, G>(rec, pa->mom.ncell, pa->n_inst, red);
+        }
+        grid.sync();
+        if (blockIdx.x == 0) {
+            SolveState *st = pa->st;
+            const int n = pa->n_inst;
+            const long long max_iter = pa->max_iter;
+            const double floor = pa->floor;
+            for (int i = threadIdx.x; i < n; i += 64 * G)
+                status_one(st[i], tol, max_iter, floor);
+        }
+        grid.sync();
     }
 }
 
@@ -1234,6 +1441,45 @@ hipError_t launch_status(SolveState *st, int n, double tol, long long max_iter, 
     hipLaunchKernelGGL(k_status, dim3((n + 63) / 64), dim3(64), 0, s, st, n, tol, max_iter, floor);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_persist(const PersistArgs<T> *dev_args, int nitems, int iters, double tol, int mode,
+                          hipStream_t s)
+{
+    const void *fn = nullptr;
+    switch (mode) {
+    case 0: fn = reinterpret_cast<const void *>(&k_persist<T, 4, 8, 0>); break;
+    case MODE_FIELD: fn = reinterpret_cast<const void *>(&k_persist<T, 4, 8, MODE_FIELD>); break;
+    case MODE_XU: fn = reinterpret_cast<const void *>(&k_persist<T, 4, 8, MODE_XU>); break;
+    case MODE_FIELD | MODE_XU:
+        fn = reinterpret_cast<const void *>(&k_persist<T, 4, 8, MODE_FIELD | MODE_XU>);
+        break;
+    default: return hipErrorNotSupported;
+    }
+    int dev = 0, coop = 0, ncu = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * 8, 0);
+    if (e != hipSuccess)
+        return e;
+    if (!coop || ncu < 1 || nb < 1)
+        return hipErrorNotSupported;
+    // the counter's values stay below 2^31
+    if ((long long)iters * ((long long)nitems + (long long)nb * ncu) >= (1ll << 31))
+        return hipErrorNotSupported;
+    // every workgroup of the grid is resident at once (the cooperative
+    // launch refuses a grid that is not)
+    const PersistArgs<T> *pa = dev_args;
+    void *args[] = {&pa, &iters, &tol};
+    return hipLaunchCooperativeKernel(fn, dim3(nb * ncu), dim3(64 * 8), args, 0, s);
+}
+
+template hipError_t launch_persist<double>(const PersistArgs<double> *, int, int, double, int, hipStream_t);
+template hipError_t launch_persist<float>(const PersistArgs<float> *, int, int, double, int, hipStream_t);
 
 hipError_t launch_zero(double *p, size_t n, hipStream_t s)
 {

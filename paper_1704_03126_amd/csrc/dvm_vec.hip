@@ -335,14 +335,16 @@ __global__ void __launch_bounds__(256) k_state32(const VSeg2 *seg, const SolveSt
     if (what == 0 && st[sg.inst].active == 0)
         return;
     const int par = (int)(st[sg.inst].iter & 1);
-    const long long off = sg.off[(what == 0 || what == 3) ? par : par ^ 1];
+    if (what == 0) {
+        state32_add(sg, par, b, vec, threadIdx.x, 256);
+        return;
+    }
+    const long long off = sg.off[what == 3 ? par : par ^ 1];
     double *v = vec + sg.vec_off;
     if (sg.buf == 0) {
         double *m = b.mom + off;
         for (int i = threadIdx.x; i < sg.len; i += 256) {
-            if (what == 0)
-                m[i] += v[i];
-            else if (what == 1)
+            if (what == 1)
                 m[i] = v[i];
             else
                 v[i] = m[i];
@@ -350,9 +352,7 @@ __global__ void __launch_bounds__(256) k_state32(const VSeg2 *seg, const SolveSt
     } else {
         float *f = b.b[sg.buf - 1] + off;
         for (int i = threadIdx.x; i < sg.len; i += 256) {
-            if (what == 0)
-                f[i] = (float)((double)f[i] + v[i]);
-            else if (what == 1)
+            if (what == 1)
                 f[i] = (float)v[i];
             else
                 v[i] = (double)f[i];

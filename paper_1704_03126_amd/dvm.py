@@ -53,14 +53,15 @@ class dvm_config(ctypes.Structure):
                 ("use_graphs", ctypes.c_int), ("vel_per_lane", ctypes.c_int),
                 ("waves_per_block", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
                 ("profile", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("accel", ctypes.c_int), ("krylov_dim", ctypes.c_int)]
+                ("accel", ctypes.c_int), ("krylov_dim", ctypes.c_int), ("persistent", ctypes.c_int)]
 
 
 class dvm_prof(ctypes.Structure):
     _fields_ = [("sweep_ms", ctypes.c_double), ("n_sweeps", ctypes.c_long),
                 ("updates", ctypes.c_double), ("other_ms", ctypes.c_double),
                 ("sweep32_ms", ctypes.c_double), ("n_sweeps32", ctypes.c_long),
-                ("updates32", ctypes.c_double)]
+                ("updates32", ctypes.c_double), ("persistent_blocks", ctypes.c_long),
+                ("persistent_iters", ctypes.c_long)]
 
 
 class dvm_info(ctypes.Structure):
@@ -200,12 +201,12 @@ class Solver:
                  use_graphs: bool = True, vel_per_lane: int = 0,
                  waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_AUTO,
                  accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, tune_cache: str | None = None,
-                 stream=None, allocator: TorchAllocator | None = None):
+                 stream=None, allocator: TorchAllocator | None = None, persistent: bool = False):
         lib = load_library()
         tc = tune_cache.encode() if tune_cache else None
         cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
                          vel_per_lane, waves_per_block, tc, int(profile), int(schedule),
-                         int(accel), int(krylov_dim))
+                         int(accel), int(krylov_dim), int(persistent))
         h = ctypes.c_void_p()
         s = stream if stream is not None else _current_stream()
         self.allocator = allocator          # kept alive until dvm_destroy
@@ -333,7 +334,9 @@ class Solver:
     def profile(self) -> dict:
         """Sweep timings since the last call (profile=True contexts): total
         ms, launch count and fluid updates of the FP64 and of the FP32 sweeps,
-        and the ms of the other kernels of the plain FP64 iterations."""
+        and the ms of the other kernels of the plain FP64 iterations; in every
+        context, the blocks run as one persistent launch and their
+        iterations."""
         p = dvm_prof()
         _check(self._lib.dvm_profile(self._h, ctypes.byref(p)))
         return {f: getattr(p, f) for f, _ in dvm_prof._fields_}
