@@ -837,6 +837,17 @@ static MomArgs mom_args(dvm_ctx *c, bool adj = false, int force = 0)
     return a;
 }
 
+// moments of the FP32 correction iteration: the FP32 sweep's partials into
+// the correction's moments, stop states of the correction
+static MomArgs mom_args32(dvm_ctx *c, int force = 0)
+{
+    MomArgs a = mom_args(c, false, force);
+    a.part32 = reinterpret_cast<const float *>(c->d_part.p);
+    a.mom = c->d_mom_d.p;
+    a.st = c->d_st32.p;
+    return a;
+}
+
 static RecArgs<double> rec_args(dvm_ctx *c, bool adj = false)
 {
     RecArgs<double> a{};
@@ -931,7 +942,7 @@ static SweepArgs<float> sweep_args32(dvm_ctx *c)
     a.fb = c->d_fb32.p;
     a.vtab = c->d_vt32.p;
     a.delta_field = c->d_dfield.p;
-    a.part = c->d_part.p;
+    a.part = reinterpret_cast<float *>(c->d_part.p);      // FP32 partials, half the FP64 buffer
     a.part5 = c->d_part5.p;
     a.seam = c->d_seam32.p;
     a.wrap = c->d_wrap32.p;
@@ -1009,10 +1020,7 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
             HIPCHK(hipEventRecord(e1, c->stream));
             c->ev_sweep.emplace_back(e0, e1);
         }
-        MomArgs m = mom_args(c);
-        m.mom = c->d_mom_d.p;
-        m.st = c->d_st32.p;
-        HIPCHK(launch_moments(m, c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_moments(mom_args32(c), c->max_cells, c->n_inst, c->stream));
         HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
         HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
         HIPCHK(launch_status(c->d_st32.p, c->n_inst, refine_inner_tol(c), c->cfg.max_iter, STOP_FLOOR32,
@@ -1082,9 +1090,7 @@ static int enqueue_persist(dvm_ctx *c, int iters, int kind, bool *done)
         PersistArgs<float> a;
         std::memset(&a, 0, sizeof(a));
         a.sw = sweep_args32(c);
-        a.mom = mom_args(c);
-        a.mom.mom = c->d_mom_d.p;
-        a.mom.st = c->d_st32.p;
+        a.mom = mom_args32(c);
         a.rec = rec_args32(c);
         a.seg = c->nseg32 > 0 ? c->d_seg32.p : nullptr;
         a.nseg = c->nseg32;
@@ -1883,10 +1889,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         HIPCHK(launch_record<float>(r32, c->max_cells, c->n_inst, c->stream));
         HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32,
                                    solve_mode(c) | xu_flag(c, c->V32), c->stream));
-        MomArgs m32 = mom_args(c);
-        m32.mom = c->d_mom_d.p;
-        m32.st = c->d_st32.p;
-        HIPCHK(launch_moments(m32, c->max_cells, c->n_inst, c->stream));
+        HIPCHK(launch_moments(mom_args32(c), c->max_cells, c->n_inst, c->stream));
         HIPCHK(launch_state32_basis(kw.seg2.p, nseg2, c->d_st32.p, state32(c), kw.w.p, v, 1, c->stream));
         return DVM_OK;
     };
@@ -2399,10 +2402,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
             r32.monitor = 0;
             HIPCHK(launch_record<float>(r32, c->max_cells, c->n_inst, c->stream));
             HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32, mode, c->stream));
-            MomArgs m = mom_args(c);
-            m.mom = c->d_mom_d.p;
-            m.st = c->d_st32.p;
-            HIPCHK(launch_moments(m, c->max_cells, c->n_inst, c->stream));
+            HIPCHK(launch_moments(mom_args32(c), c->max_cells, c->n_inst, c->stream));
             HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_er.p, 3, c->stream));
             HIPCHK(hipMemcpyAsync(a32.data(), c->d_er.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
@@ -2709,8 +2709,12 @@ static int time_sweep(dvm_ctx *c, int V, int G, double *ms)
                 a.force = 1;
                 err = launch_sweep<float>(a, (int)c->items.size(), V, G, xu_flag(c, V), c->stream);
             }
-            if (err == hipSuccess)
-                err = launch_moments(mom_args(c, false, 1), c->max_cells, c->n_inst, c->stream);
+            if (err == hipSuccess) {
+                MomArgs m = mom_args(c, false, 1);
+                if constexpr (sizeof(T) == 4)
+                    m.part32 = reinterpret_cast<const float *>(c->d_part.p);
+                err = launch_moments(m, c->max_cells, c->n_inst, c->stream);
+            }
         }
     }
     if (err == hipSuccess)

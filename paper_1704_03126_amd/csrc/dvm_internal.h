@@ -124,7 +124,7 @@ struct SweepArgs {
     double *part5;            // extra partial [group][ncell] (P12 / gradient)
     const T *vtab;            // [inst][kp4][VT_STRIDE]
     const double *delta_field;
-    double *part;             // [group][ncell][4]   (final pass: [group][ncell])
+    T *part;                  // [group][ncell][4] moment partials (FP32 for the FP32 sweep)
     T *seam;                  // [2][seam_half]
     T *wrap;                  // [strip][3][kp4][64] per instance
     SolveState *st;
@@ -142,6 +142,7 @@ struct MomArgs {
     const InstDev *inst;
     const uint8_t *codes;
     const double *part;
+    const float *part32;      // non-null: the partials of an FP32 sweep instead
     double *mom;
     SolveState *st;
     long long ncell;

@@ -536,7 +536,7 @@ __device__ __forceinline__ void sweep_item(SweepArgs<T> a, int item)
             if (P12)
                 a.part5[cg] = sum;
             else if (m < 4)
-                a.part[cg * 4 + m] = sum;
+                a.part[cg * 4 + m] = (T)sum;
             else
                 a.part5[cg] = sum;
         }
@@ -606,10 +606,21 @@ k_sweep(SweepArgs<T> a)
 // ----------------------------------------------------------------- moments
 // 256 threads = 64 cells x 4 quadrants: each thread sums its quadrant's
 // groups in order, the four quadrant sums are combined in a fixed order
-// sum of the partials of quadrant q's velocity groups at cell cg (in order)
+// sum of the partials of quadrant q's velocity groups at cell cg (in order,
+// in FP64 also for the FP32 partials of an FP32 sweep)
 __device__ __forceinline__ double4 moments_quadrant(const MomArgs &a, long long cg, int q)
 {
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (a.part32) {
+        for (int g = q * a.gq; g < (q + 1) * a.gq; ++g) {
+            const float4 p = *reinterpret_cast<const float4 *>(a.part32 + ((size_t)g * a.ncell + cg) * 4);
+            s.x += (double)p.x;
+            s.y += (double)p.y;
+            s.z += (double)p.z;
+            s.w += (double)p.w;
+        }
+        return s;
+    }
     for (int g = q * a.gq; g < (q + 1) * a.gq; ++g) {
         const double4 p = *reinterpret_cast<const double4 *>(a.part + ((size_t)g * a.ncell + cg) * 4);
         s.x += p.x;
