@@ -225,6 +225,13 @@ struct dvm_ctx {
     bool fp32_ready = false;
     DevBuf<float> d_srec32, d_seam32, d_wrap32, d_fb32, d_vt32;
     DevBuf<double> d_mom_d, d_u1prev_d, d_xr, d_rr, d_er;
+    // the correction's constant term rr in the layout of the moments and
+    // wrap buffers: the FP32 correction iteration adds it where it writes
+    // those values (plain sweep modes); the seam part is added by a separate
+    // pass over the seam segments only (d_seg32s)
+    DevBuf<double> d_rb_mom, d_rb_wrap;
+    DevBuf<VSeg2> d_seg32s;
+    int nseg32s = 0;
     DevBuf<SolveState> d_st32;
     DevBuf<VSeg2> d_seg32;
     int nseg32 = 0;
@@ -271,6 +278,7 @@ struct dvm_ctx {
         kw.release();
         d_srec32.release(); d_seam32.release(); d_wrap32.release(); d_fb32.release(); d_vt32.release();
         d_mom_d.release(); d_u1prev_d.release(); d_xr.release(); d_rr.release(); d_er.release();
+        d_rb_mom.release(); d_rb_wrap.release(); d_seg32s.release();
         d_st32.release(); d_seg32.release(); d_q.release(); d_pargs.release(); d_ctr.release();
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
@@ -848,6 +856,16 @@ static MomArgs mom_args32(dvm_ctx *c, int force = 0)
     return a;
 }
 
+static int solve_mode(const dvm_ctx *c);
+
+// The FP32 correction iteration adds its constant term where the sweep and
+// the moments write the state (plain sweep modes); with wall-face buffers
+// (specular walls) a separate pass adds it after the moments.
+static bool fused_add32(const dvm_ctx *c)
+{
+    return (solve_mode(c) & MODE_SPEC) == 0 && c->d_rb_mom.p != nullptr;
+}
+
 static RecArgs<double> rec_args(dvm_ctx *c, bool adj = false)
 {
     RecArgs<double> a{};
@@ -958,6 +976,22 @@ static SweepArgs<float> sweep_args32(dvm_ctx *c)
     return a;
 }
 
+// the FP32 correction iteration e <- L32 e + r with r added where the sweep
+// and the moments write (fused_add32)
+static SweepArgs<float> sweep_args32r(dvm_ctx *c)
+{
+    SweepArgs<float> a = sweep_args32(c);
+    a.rwrap = c->d_rb_wrap.p;
+    return a;
+}
+
+static MomArgs mom_args32r(dvm_ctx *c)
+{
+    MomArgs a = mom_args32(c);
+    a.radd = c->d_rb_mom.p;
+    return a;
+}
+
 static RecArgs<float> rec_args32(dvm_ctx *c)
 {
     RecArgs<float> a{};
@@ -1014,14 +1048,18 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         c->ev_prec = kind == 2 ? 1 : 0;
     }
     if (kind == 2) {
-        HIPCHK(launch_sweep<float>(sweep_args32(c), (int)c->items.size(), c->V32, c->G32,
-                                   solve_mode(c) | xu_flag(c, c->V32), c->stream));
+        const bool fused = fused_add32(c);
+        HIPCHK(launch_sweep<float>(fused ? sweep_args32r(c) : sweep_args32(c), (int)c->items.size(), c->V32,
+                                   c->G32, solve_mode(c) | xu_flag(c, c->V32), c->stream));
         if (prof) {
             HIPCHK(hipEventRecord(e1, c->stream));
             c->ev_sweep.emplace_back(e0, e1);
         }
-        HIPCHK(launch_moments(mom_args32(c), c->max_cells, c->n_inst, c->stream));
-        HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
+        HIPCHK(launch_moments(fused ? mom_args32r(c) : mom_args32(c), c->max_cells, c->n_inst, c->stream));
+        if (fused)
+            HIPCHK(launch_state32(c->d_seg32s.p, c->nseg32s, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
+        else
+            HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
         HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
         HIPCHK(launch_status(c->d_st32.p, c->n_inst, refine_inner_tol(c), c->cfg.max_iter, STOP_FLOOR32,
                              c->stream));
@@ -1089,11 +1127,12 @@ static int enqueue_persist(dvm_ctx *c, int iters, int kind, bool *done)
     if (f32) {
         PersistArgs<float> a;
         std::memset(&a, 0, sizeof(a));
-        a.sw = sweep_args32(c);
-        a.mom = mom_args32(c);
+        const bool fused = fused_add32(c);
+        a.sw = fused ? sweep_args32r(c) : sweep_args32(c);
+        a.mom = fused ? mom_args32r(c) : mom_args32(c);
         a.rec = rec_args32(c);
-        a.seg = c->nseg32 > 0 ? c->d_seg32.p : nullptr;
-        a.nseg = c->nseg32;
+        a.seg = fused ? (c->nseg32s > 0 ? c->d_seg32s.p : nullptr) : (c->nseg32 > 0 ? c->d_seg32.p : nullptr);
+        a.nseg = fused ? c->nseg32s : c->nseg32;
         a.sb = state32(c);
         a.rr = c->d_rr.p;
         a.st = c->d_st32.p;
@@ -2190,6 +2229,11 @@ static int ensure_fp32(dvm_ctx *c)
     HIPCHK(c->d_mom_d.alloc(c->ncell * MOM_STRIDE));
     HIPCHK(c->d_u1prev_d.alloc(c->ncell));
     HIPCHK(c->d_st32.alloc(c->n_inst));
+    HIPCHK(c->d_rb_mom.alloc(c->ncell * MOM_STRIDE));
+    HIPCHK(c->d_rb_wrap.alloc(c->wrap_total));
+    // values outside every instance's state stay 0
+    HIPCHK(launch_zero(c->d_rb_mom.p, c->d_rb_mom.n, c->stream));
+    HIPCHK(launch_zero(c->d_rb_wrap.p, c->d_rb_wrap.n, c->stream));
     HIPCHK(launch_zero_f(c->d_srec32.p, c->d_srec32.n, c->stream));
     HIPCHK(launch_zero_f(c->d_seam32.p, c->d_seam32.n, c->stream));
     HIPCHK(launch_zero_f(c->d_wrap32.p, c->d_wrap32.n, c->stream));
@@ -2279,12 +2323,21 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
         }
         HIPCHK(kw.gseg.alloc(std::max<size_t>(gseg.size(), 1)));
         HIPCHK(kw.sseg.alloc(std::max<size_t>(sseg.size(), 1)));
+        std::vector<VSeg2> s2s;                // the seam segments alone
+        for (const VSeg2 &g : s2)
+            if (g.buf == 1)
+                s2s.push_back(g);
         HIPCHK(c->d_seg32.alloc(std::max<size_t>(s2.size(), 1)));
+        HIPCHK(c->d_seg32s.alloc(std::max<size_t>(s2s.size(), 1)));
         HIPCHK(hipMemcpyAsync(kw.gseg.p, gseg.data(), gseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(kw.sseg.p, sseg.data(), sseg.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(c->d_seg32.p, s2.data(), s2.size() * sizeof(VSeg2), hipMemcpyHostToDevice, c->stream));
+        if (!s2s.empty())
+            HIPCHK(hipMemcpyAsync(c->d_seg32s.p, s2s.data(), s2s.size() * sizeof(VSeg2), hipMemcpyHostToDevice,
+                                  c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         c->nseg32 = (int)s2.size();
+        c->nseg32s = (int)s2s.size();
         if (c->graph[2]) {                 // the captured block holds the old table
             (void)hipGraphExecDestroy(c->graph[2]);
             c->graph[2] = nullptr;
@@ -2455,6 +2508,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
         if ((rc = upload(c->d_st32.p, st32)))
             return rc;
         HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 1, c->stream));
+        HIPCHK(launch_rscatter(c->d_seg32.p, c->nseg32, c->d_rr.p, c->d_rb_mom.p, c->d_rb_wrap.p, c->stream));
         HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
         for (auto &d : slots)
             if (d.live)

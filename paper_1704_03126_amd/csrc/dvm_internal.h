@@ -136,6 +136,11 @@ struct SweepArgs {
     int kp4;                  // 4 * kq
     int force;                // run even for converged instances
     const double *rows;       // row heights in units of H, [row_off + row]
+    // FP32 correction iteration: its constant term in the layout of the wrap
+    // buffer, added to the wrap values the sweep writes (at the end of a work
+    // item); null otherwise (FP32 sweeps only).  The seam values get theirs
+    // in a separate pass: read inside the step loop it stalled the sweep.
+    const double *rwrap;
 };
 
 struct MomArgs {
@@ -143,6 +148,7 @@ struct MomArgs {
     const uint8_t *codes;
     const double *part;
     const float *part32;      // non-null: the partials of an FP32 sweep instead
+    const double *radd;       // non-null: added to every moment (FP32 correction's constant term)
     double *mom;
     SolveState *st;
     long long ncell;
@@ -328,6 +334,11 @@ hipError_t launch_persist(const PersistArgs<T> *dev_args, int nitems, int iters,
 //       3 -- vec = state outputs of the sweep just run
 hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b, double *vec, int what,
                           hipStream_t s);
+// the FP32 correction's constant term vec (segments of seg) into buffers in
+// the layout of the moments and wrap buffers; seam and wall-face segments
+// are left out
+hipError_t launch_rscatter(const VSeg2 *seg, int nseg, const double *vec, double *rmom, double *rwrap,
+                           hipStream_t s);
 // mixed-precision Krylov steps: what 0 -- FP32 state inputs of the next
 // sweep = v (an FP32 basis vector); what 1 -- w = v - FP32 state outputs of
 // the sweep just run

@@ -587,11 +587,22 @@ __device__ __forceinline__ void sweep_item(SweepArgs<T> a, int item)
         flush(b, C - FL);
     }
     if (!P12 && x_coupled) {
+        if (sizeof(T) == 4 && a.rwrap) {
+            // FP32 correction iteration: plus its constant term
+            const double *rw = a.rwrap + (wrapp - a.wrap);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            wrapp[v * 64] = rA[v];
-            wrapp[wslot + v * 64] = rB[v];
-            wrapp[2 * wslot + v * 64] = rH0[v];
+            for (int v = 0; v < V; ++v) {
+                wrapp[v * 64] = (T)((double)rA[v] + rw[v * 64]);
+                wrapp[wslot + v * 64] = (T)((double)rB[v] + rw[wslot + v * 64]);
+                wrapp[2 * wslot + v * 64] = (T)((double)rH0[v] + rw[2 * wslot + v * 64]);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                wrapp[v * 64] = rA[v];
+                wrapp[wslot + v * 64] = rB[v];
+                wrapp[2 * wslot + v * 64] = rH0[v];
+            }
         }
     }
 }
@@ -632,11 +643,12 @@ __device__ __forceinline__ double4 moments_quadrant(const MomArgs &a, long long 
 }
 
 // the cell's moments from its four quadrant sums, combined in quadrant order
-__device__ __forceinline__ void moments_store(double *m, const double4 (&qs)[4], bool fluid)
+// (plus r, the FP32 correction's constant term, where non-null)
+__device__ __forceinline__ void moments_store(double *m, const double4 (&qs)[4], bool fluid, const double *rr)
 {
     if (!fluid) {
         for (int i = 0; i < MOM_STRIDE; ++i)
-            m[i] = 0.0;
+            m[i] = rr ? 0.0 + rr[i] : 0.0;
         return;
     }
     double r = 0, u1 = 0, u2 = 0, e = 0, fxp = 0, fxm = 0, fyp = 0, fym = 0;
@@ -647,6 +659,16 @@ __device__ __forceinline__ void moments_store(double *m, const double4 (&qs)[4],
         e += qs[qq].w;
         if ((qq & 1) == 0) fxp += qs[qq].y; else fxm += qs[qq].y;
         if ((qq & 2) == 0) fyp += qs[qq].z; else fym += qs[qq].z;
+    }
+    if (rr) {
+        r += rr[MOM_RHO];
+        u1 += rr[MOM_U1];
+        u2 += rr[MOM_U2];
+        e += rr[MOM_E];
+        fxp += rr[MOM_FXP];
+        fxm += rr[MOM_FXM];
+        fyp += rr[MOM_FYP];
+        fym += rr[MOM_FYM];
     }
     m[MOM_RHO] = r;
     m[MOM_U1] = u1;
@@ -675,7 +697,7 @@ __global__ void __launch_bounds__(256) k_moments(MomArgs a)
     if (q != 0 || !valid)
         return;
     const double4 mine[4] = {qs[0][l], qs[1][l], qs[2][l], qs[3][l]};
-    moments_store(a.mom + cg * MOM_STRIDE, mine, fluid);
+    moments_store(a.mom + cg * MOM_STRIDE, mine, fluid, a.radd ? a.radd + cg * MOM_STRIDE : nullptr);
 }
 
 // sum of one extra per-group partial (shear stress, gradient term) over the
@@ -1141,7 +1163,7 @@ __device__ __forceinline__ void persist_moments(const MomArgs &a, int n_inst, lo
             qs[k].w = __shfl(s.w, lead + k, 64);
         }
         if (q == 0)
-            moments_store(a.mom + cg * MOM_STRIDE, qs, fluid);
+            moments_store(a.mom + cg * MOM_STRIDE, qs, fluid, a.radd ? a.radd + cg * MOM_STRIDE : nullptr);
     }
 }
 

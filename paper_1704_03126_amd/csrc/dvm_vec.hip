@@ -369,6 +369,28 @@ hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, Stat
     return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) k_rscatter(const VSeg2 *seg, const double *vec, double *rmom, double *rwrap)
+{
+    const VSeg2 sg = seg[blockIdx.x];
+    double *dst = sg.buf == 0 ? rmom : sg.buf == 2 ? rwrap : nullptr;
+    if (!dst)
+        return;
+    // moments and wrap state: one offset for both parities
+    dst += sg.off[0];
+    const double *v = vec + sg.vec_off;
+    for (int i = threadIdx.x; i < sg.len; i += 256)
+        dst[i] = v[i];
+}
+
+hipError_t launch_rscatter(const VSeg2 *seg, int nseg, const double *vec, double *rmom, double *rwrap,
+                           hipStream_t s)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_rscatter, dim3(nseg), dim3(256), 0, s, seg, vec, rmom, rwrap);
+    return hipGetLastError();
+}
+
 // Krylov basis vector <-> FP32 correction state (mixed-precision GMRES):
 // what 0 -- state inputs of the next sweep (parity st.iter & 1 ^ 1) = v;
 // what 1 -- w = v - state outputs of the sweep just run (parity st.iter & 1).
