@@ -201,9 +201,11 @@ struct dvm_ctx {
     bool adj_ready = false;
     std::vector<uint8_t> h_scode_adj;
     std::vector<FaceRec> h_sface_adj;
+    std::vector<int> h_wl_adj;            // wall-read lists of the adjoint sweep
     std::vector<int> h_face_cell, h_face_side, h_face_inst;
     DevBuf<uint8_t> d_scode_adj;
     DevBuf<FaceRec> d_sface_adj;
+    DevBuf<int> d_wl, d_wl_adj;
     DevBuf<int> d_face_cell, d_face_side, d_face_inst;
     DevBuf<double> d_srec_adj, d_mom_adj, d_u1prev_adj, d_seam_adj, d_wrap_adj, d_fb_adj;
     DevBuf<double> d_ckpt, d_part5, d_momg, d_dqda;
@@ -270,7 +272,7 @@ struct dvm_ctx {
         d_scode.release(); d_smap.release(); d_spos.release();
         d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release(); d_rows.release();
         d_u1prev.release(); d_seam.release(); d_wrap.release(); d_aux.release();
-        d_st.release(); d_sface.release(); d_fb.release();
+        d_st.release(); d_sface.release(); d_fb.release(); d_wl.release(); d_wl_adj.release();
         d_scode_adj.release(); d_sface_adj.release(); d_face_cell.release(); d_face_side.release();
         d_face_inst.release(); d_srec_adj.release(); d_mom_adj.release(); d_u1prev_adj.release();
         d_seam_adj.release(); d_wrap_adj.release(); d_fb_adj.release(); d_ckpt.release();
@@ -773,6 +775,49 @@ static int build_layout(dvm_ctx *c)
             }
         }
     }
+    // wall-read lists per chunk of every strip pass, and the slots in the
+    // face records (forward and adjoint records read different faces)
+    if (faces > SPEC_FACE_MASK)
+        return fail(DVM_EINVAL, "too many wall faces (more than 2^25)");
+    long long wl_total = 0;
+    for (int i = 0; i < c->n_inst; ++i) {
+        InstDev &d = c->idev[i];
+        d.wl_off = wl_total;
+        wl_total += 4ll * d.nstrips * ((d.tp + SWEEP_C - 1) / SWEEP_C) * SPEC_SLOTS;
+    }
+    std::vector<int> wl(wl_total, -1), wl_adj(wl_total, -1);
+    auto assign_slots = [&](std::vector<FaceRec> &recs, std::vector<int> &list) {
+        for (int i = 0; i < c->n_inst; ++i) {
+            const InstDev &d = c->idev[i];
+            const int nch = (d.tp + SWEEP_C - 1) / SWEEP_C;
+            for (int ps = 0; ps < 4 * d.nstrips; ++ps)
+                for (int k = 0; k < nch; ++k) {
+                    int *lst = &list[d.wl_off + ((long long)ps * nch + k) * SPEC_SLOTS];
+                    int n = 0;
+                    for (int t = k * SWEEP_C; t < std::min((k + 1) * SWEEP_C, d.tp); ++t)
+                        for (int l = 0; l < 64; ++l) {
+                            FaceRec &f = recs[d.sk_off + ((long long)ps * d.tp + t) * 64 + l];
+                            for (int axis = 0; axis < 2; ++axis) {
+                                int &rd = axis ? f.rdy : f.rdx;
+                                if (rd < 0)
+                                    continue;
+                                int slot = SPEC_SLOT_NONE;
+                                if (n < SPEC_SLOTS) {
+                                    lst[n] = 2 * rd + axis;
+                                    slot = n++;
+                                }
+                                rd |= slot << SPEC_SLOT_SHIFT;
+                            }
+                        }
+                }
+        }
+    };
+    assign_slots(sface, wl);
+    assign_slots(sface_adj, wl_adj);
+    HIPCHK(c->d_wl.alloc(std::max<long long>(wl_total, 1)));
+    if (wl_total > 0)
+        HIPCHK(hipMemcpyAsync(c->d_wl.p, wl.data(), wl_total * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    c->h_wl_adj.swap(wl_adj);
     c->h_scode_adj.swap(scode_adj);
     c->h_sface_adj.swap(sface_adj);
     HIPCHK(hipMemcpyAsync(c->d_codes.p, codes.data(), cell, hipMemcpyHostToDevice, c->stream));
@@ -811,6 +856,7 @@ static SweepArgs<double> sweep_args(dvm_ctx *c, int force, bool adj = false)
     a.scode = adj ? c->d_scode_adj.p : c->d_scode.p;
     a.smap = c->d_smap.p;
     a.sface = adj ? c->d_sface_adj.p : c->d_sface.p;
+    a.wl = adj ? c->d_wl_adj.p : c->d_wl.p;
     a.fb = adj ? c->d_fb_adj.p : c->d_fb.p;
     a.ckpt = c->d_ckpt.p;
     a.part5 = c->d_part5.p;
@@ -957,6 +1003,7 @@ static SweepArgs<float> sweep_args32(dvm_ctx *c)
     a.scode = c->d_scode.p;
     a.smap = c->d_smap.p;
     a.sface = c->d_sface.p;
+    a.wl = c->d_wl.p;
     a.fb = c->d_fb32.p;
     a.vtab = c->d_vt32.p;
     a.delta_field = c->d_dfield.p;
@@ -3081,6 +3128,10 @@ static int ensure_adjoint(dvm_ctx *c)
     HIPCHK(hipMemcpyAsync(c->d_scode_adj.p, c->h_scode_adj.data(), sk, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_sface_adj.p, c->h_sface_adj.data(), sk * sizeof(FaceRec), hipMemcpyHostToDevice,
                           c->stream));
+    HIPCHK(c->d_wl_adj.alloc(std::max<size_t>(c->h_wl_adj.size(), 1)));
+    if (!c->h_wl_adj.empty())
+        HIPCHK(hipMemcpyAsync(c->d_wl_adj.p, c->h_wl_adj.data(), c->h_wl_adj.size() * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
     if (c->nfaces > 0) {
         HIPCHK(hipMemcpyAsync(c->d_face_cell.p, c->h_face_cell.data(), c->nfaces * sizeof(int),
                               hipMemcpyHostToDevice, c->stream));

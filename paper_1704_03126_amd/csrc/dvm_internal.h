@@ -74,7 +74,21 @@ struct InstDev {
     double drive;         // coefficient of the pressure-gradient source
     double inv_dx;
     double u_bot, u_top;  // x velocities of the outer bottom / top walls
+    long long wl_off;     // first entry of this instance's wall-read lists
 };
+
+// Steps of a pass staged per chunk: a multiple of 6 so that the 3-register
+// rotation of the x-upwind values and the 2-register rotation of the
+// y-upwind value are pure renaming inside a chunk.
+enum { SWEEP_C = 6 };
+
+// Maxwell's specular share reads the previous iterate's values on the
+// upwind wall faces.  Per chunk of a strip pass the wall faces read are
+// listed (up to SPEC_SLOTS, as 2 face + axis, -1 unused) so that the sweep
+// fetches their mirrored values into LDS one chunk ahead; a face record's
+// rdx / rdy carry the face in bits 0-24 and the slot in bits 25-30
+// (SPEC_SLOT_NONE: read directly).
+enum { SPEC_SLOTS = 48, SPEC_SLOT_SHIFT = 25, SPEC_SLOT_NONE = 63, SPEC_FACE_MASK = (1 << 25) - 1 };
 
 struct WorkItem {
     int inst, strip, group, pad;
@@ -119,6 +133,7 @@ struct SweepArgs {
     const uint8_t *scode;     // skewed stencil nibbles [entry]
     const int *smap;          // skewed entry -> fluid cell of the instance, -1 none
     const FaceRec *sface;     // skewed face records [entry] (MODE_SPEC/CKPT/GRAD)
+    const int *wl;            // wall-read lists [wl_off + (pass * chunks + chunk) * SPEC_SLOTS + slot]
     T *fb;                    // wall-face values [2][fb_half]: [parity][face][kp4]
     double *ckpt;             // checkpoint h [cell][kp4] (MODE_CKPT writes, MODE_GRAD reads)
     double *part5;            // extra partial [group][ncell] (P12 / gradient)

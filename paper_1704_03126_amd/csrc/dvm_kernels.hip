@@ -89,10 +89,6 @@ __device__ __forceinline__ T ldc(cptr<T> p, int i)
     return p[i];
 }
 
-// Steps of a pass staged per chunk: a multiple of 6 so that the 3-register
-// rotation of the x-upwind values and the 2-register rotation of the
-// y-upwind value are pure renaming inside a chunk.
-constexpr int SWEEP_C = 6;
 
 // Plain FP32 sweeps in 8-wave workgroups are held to 128 VGPRs (4 waves per
 // SIMD): with their half-size LDS staging two workgroups then share a CU,
@@ -107,512 +103,25 @@ constexpr int sweep_waves_per_eu()
 }
 
 // One work item of the sweep (instance, strip, velocity group) by the
-// calling workgroup; the body of k_sweep and of the persistent iteration.
-template <typename T, int V, int G, int MODE>
-__device__ __forceinline__ void sweep_item(SweepArgs<T> a, int item)
-{
-    constexpr bool FIELD = (MODE & MODE_FIELD) != 0;
-    constexpr bool SPEC = (MODE & MODE_SPEC) != 0;
-    constexpr bool ADJ = (MODE & MODE_ADJ) != 0;
-    constexpr bool P12 = (MODE & MODE_P12) != 0;
-    constexpr bool CKPT = (MODE & MODE_CKPT) != 0;
-    constexpr bool GRAD = (MODE & MODE_GRAD) != 0;
-    // xi (and |xi|/dx) uniform over the wave's velocities: the collision gain's
-    // b0 + b1 xi and the u1 partial (xi times the density partial) once per step
-    constexpr bool XU = (MODE & MODE_XU) != 0;
-    constexpr bool FACES = SPEC || CKPT || GRAD;          // face records needed
-    constexpr bool FBWRITE = (SPEC || CKPT || GRAD) && !P12;
-    constexpr int C = SWEEP_C;                 // steps per chunk
-    // moments gathered: 4 (rho, u1, u2, e) and an extra one (P12 or gradient)
-    constexpr int NACC = P12 ? 1 : (GRAD ? 5 : 4);
-    // moment partials: an FP64 sweep sums in FP64; an FP32 sweep (the
-    // refinement's correction, itself held in FP32) sums the V velocities of
-    // a lane in FP32 and the G waves of the group in FP64
-    using AccT = typename std::conditional<sizeof(T) == 4, float, double>::type;
-    // steps per partial flush: the whole chunk unless LDS is short
-    // (4-wave workgroups: half the partial buffer, so two workgroups share
-    // a CU)
-    constexpr int FL = (FACES || NACC > 4 || G > 8 || G <= 4) ? C / 2 : C;
-    constexpr int P = G * V;                   // velocities of the group
-    constexpr int UPE = 8 * sizeof(T) / 16;    // 16-byte units per record
-    __shared__ __attribute__((aligned(16))) T st_rec[2][C][64][8];
-    __shared__ uint8_t st_code[2][C][64];
-    __shared__ int st_cell[2][C][64];
-    __shared__ __attribute__((aligned(16))) T st_seam[2][C][2][P];
-    __shared__ __attribute__((aligned(16))) FaceRec st_face[FACES ? 2 : 1][FACES ? C : 1][64];
-    __shared__ AccT lds_part[FL][G][64][NACC];
-    __shared__ T lds_rinv[P][NSTENCIL];
-    __shared__ T lds_lut[NWPAIR][2];
-
-    const WorkItem it = a.items[item];
-    const InstDev in = a.inst[it.inst];
-    if (!a.force && a.st[it.inst].active == 0)
-        return;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int q = it.group / a.gq;
-    const bool xpos = (q & 1) == 0, ypos = (q & 2) == 0;
-    const int idx0 = (it.group % a.gq) * P + wave * V;  // index in the quadrant
-    const int kq0 = q * a.kq + (it.group % a.gq) * P;   // first velocity of the group
-    const int kw = kq0 + wave * V;                      // first velocity of this wave
-    cptr<T> vt = (cptr<T>)(a.vtab + (size_t)it.inst * a.kp4 * VT_STRIDE);
-
-    const int y0 = it.strip * in.strip_h;
-    const int hs = min(in.strip_h, in.ny - y0);
-    const long long iter = a.st[it.inst].iter;
-    const int par_w = (int)(iter & 1), par_r = par_w ^ 1;
-    const int tp = in.tp, nx = in.nx;
-    const size_t ebase = (size_t)in.sk_off + ((size_t)(q * in.nstrips + it.strip) * tp) * 64;
-    const T *__restrict__ srec = a.srec + ebase * 8;
-    const uint8_t *__restrict__ scode = a.scode + ebase;
-    const int *__restrict__ smap = a.smap + ebase;
-    const FaceRec *__restrict__ sface = FACES ? a.sface + ebase : nullptr;
-
-    if (!FIELD) {
-        for (int e = tid; e < P * NSTENCIL; e += 64 * G) {
-            const int v = e / NSTENCIL, ci = e % NSTENCIL;
-            const T cx = vt[(kq0 + v) * VT_STRIDE + VT_CX], cy = vt[(kq0 + v) * VT_STRIDE + VT_CY];
-            const T w = vt[(kq0 + v) * VT_STRIDE + VT_W];
-            const T ax = (ci & 2) ? T(1) : T(1.5), ay = (ci & 1) ? T(1) : T(1.5);
-            const T den = T(in.delta) + ax * cx + ay * cy;
-            lds_rinv[v][ci] = (ci == STENCIL_SOLID || w == T(0) || den == T(0)) ? T(0) : T(1) / den;
-        }
-    }
-    if (tid < NWPAIR) {
-        // neighbour weight pairs of the stencil nibbles (bits 0-2)
-        const T w1 = tid < 2 ? T(2) : tid < 4 ? T(1.5) : T(0);
-        const T w2 = (tid & 1) == 0 && tid < 6 ? T(-0.5) : T(0);
-        lds_lut[tid][0] = w1;
-        lds_lut[tid][1] = w2;
-    }
-
-    const bool has_up = ypos ? (it.strip > 0 || in.periodic_y)
-                             : (it.strip < in.nstrips - 1 || in.periodic_y);
-    const int s_up = ypos ? (it.strip + in.nstrips - 1) % in.nstrips : (it.strip + 1) % in.nstrips;
-    const bool has_down = ypos ? (it.strip < in.nstrips - 1 || in.periodic_y)
-                               : (it.strip > 0 || in.periodic_y);
-    const size_t seam_row = (size_t)2 * a.kp4;
-    const T *seam_in = a.seam + (size_t)par_r * a.seam_half + in.seam_off + (size_t)s_up * nx * seam_row;
-    T *seam_out = a.seam + (size_t)par_w * a.seam_half + in.seam_off + (size_t)it.strip * nx * seam_row;
-    const T *fb_rd = FACES ? a.fb + (size_t)par_r * a.fb_half : nullptr;
-    T *fb_wr = FACES ? a.fb + (size_t)par_w * a.fb_half : nullptr;
-    const bool x_coupled = nx > 1;
-    const T spec = T(1.0 - in.alpha);
-    // mirrored velocities (first of this wave) across x- and y-normal faces
-    const int kmx = (q ^ 1) * a.kq + idx0, kmy = (q ^ 2) * a.kq + idx0;
-    const int krev = (q ^ 3) * a.kq + idx0;   // reversed velocity (gradient)
-
-    // ---- staging of one chunk of steps into LDS buffer b
-    constexpr int REC_UNITS = C * 64 * UPE;
-    constexpr int RU_PER_T = (REC_UNITS + 64 * G - 1) / (64 * G);
-    constexpr int SEAM_VALS = C * 2 * P;
-    constexpr int SV_PER_T = (SEAM_VALS + 64 * G - 1) / (64 * G);
-    constexpr int CC_PER_T = (C * 64 + 64 * G - 1) / (64 * G);
-    constexpr int FR_UNITS = FACES ? C * 64 * 2 : 0;     // 16-byte units
-    constexpr int FR_PER_T = FACES ? (FR_UNITS + 64 * G - 1) / (64 * G) : 1;
-    uint4 ru[RU_PER_T];
-    uint4 fu[FR_PER_T];
-    T sv[SV_PER_T];
-    int cc[CC_PER_T];
-    uint8_t cb[CC_PER_T];
-    auto issue = [&](int c) {
-        const int t0 = c * C;
-#pragma unroll
-        for (int r = 0; r < RU_PER_T; ++r) {
-            const int u = tid + r * 64 * G;
-            ru[r] = make_uint4(0, 0, 0, 0);
-            if (u < REC_UNITS && t0 + (u / UPE) / 64 < tp)
-                ru[r] = reinterpret_cast<const uint4 *>(srec + ((size_t)t0 * 64) * 8)[u];
-        }
-        if (FACES) {
-#pragma unroll
-            for (int r = 0; r < FR_PER_T; ++r) {
-                const int u = tid + r * 64 * G;
-                fu[r] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-                if (u < FR_UNITS) {
-                    if (t0 + (u / 2) / 64 < tp)
-                        fu[r] = reinterpret_cast<const uint4 *>(sface + (size_t)t0 * 64)[u];
-                    else if (u & 1)
-                        fu[r] = make_uint4(0, 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < CC_PER_T; ++r) {
-            const int e = tid + r * 64 * G;
-            cc[r] = -1;
-            cb[r] = 0xFF;
-            if (e < C * 64 && t0 + e / 64 < tp) {
-                cc[r] = smap[(size_t)t0 * 64 + e];
-                cb[r] = scode[(size_t)t0 * 64 + e];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < SV_PER_T; ++r) {
-            const int e = tid + r * 64 * G;       // (s, slot, j)
-            sv[r] = T(0);
-            if (e < SEAM_VALS && has_up) {
-                const int sidx = e / (2 * P), slot = (e / P) & 1, j = e % P;
-                const int xr = t0 + sidx;            // lane 0 treats x_r = t
-                if (xr < nx) {
-                    const int x0 = xpos ? xr : nx - 1 - xr;
-                    sv[r] = seam_in[(size_t)x0 * seam_row + (size_t)slot * a.kp4 + kq0 + j];
-                }
-            }
-        }
-    };
-    auto commit = [&](int b) {
-#pragma unroll
-        for (int r = 0; r < RU_PER_T; ++r) {
-            const int u = tid + r * 64 * G;
-            if (u < REC_UNITS)
-                reinterpret_cast<uint4 *>(&st_rec[b][0][0][0])[u] = ru[r];
-        }
-        if (FACES) {
-#pragma unroll
-            for (int r = 0; r < FR_PER_T; ++r) {
-                const int u = tid + r * 64 * G;
-                if (u < FR_UNITS)
-                    reinterpret_cast<uint4 *>(&st_face[b][0][0])[u] = fu[r];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < CC_PER_T; ++r) {
-            const int e = tid + r * 64 * G;
-            if (e < C * 64) {
-                (&st_cell[b][0][0])[e] = cc[r];
-                (&st_code[b][0][0])[e] = cb[r];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < SV_PER_T; ++r) {
-            const int e = tid + r * 64 * G;
-            if (e < SEAM_VALS)
-                (&st_seam[b][0][0][0])[e] = sv[r];
-        }
-    };
-
-    // velocity constants of this wave, for the whole pass
-    T cxi[V], ceta[V], cqq[V], ccx[V], ccy[V];
-    AccT cw[V], cwxi[V], cweta[V], cwq[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const int k = (kw + (XU ? 0 : v)) * VT_STRIDE;
-        const int kv = (kw + v) * VT_STRIDE;
-        cxi[v] = ldc(vt, k + VT_XI);
-        ccx[v] = ldc(vt, k + VT_CX);
-        ceta[v] = ldc(vt, kv + VT_ETA);
-        cqq[v] = ldc(vt, kv + VT_Q);
-        ccy[v] = ldc(vt, kv + VT_CY);
-        cw[v] = (AccT)ldc(vt, kv + VT_W);
-        cwxi[v] = cw[v] * (AccT)cxi[v];
-        cweta[v] = cw[v] * (AccT)ceta[v];
-        cwq[v] = cw[v] * (AccT)cqq[v];
-    }
-    const AccT xi0 = (AccT)cxi[0];
-
-    // per-cell-delta mode also serves rows of unequal height (nonuniform
-    // spacing across the channel): along y the face value extrapolated from
-    // the upwind cell u through uu is h_u + r (h_u - h_uu), r the ratio of
-    // the distances from the face and from uu's centre to u's centre; rc for
-    // this lane's row and its upwind neighbour (yrc), for the neighbour and
-    // the second one (yru), both 1/2 on a uniform grid; ysc = dx / dy scales
-    // |eta|/dx
-    // The transposed problem (adjoint) couples the cell to the rows of its
-    // two upwind neighbours with their own forward weights, scaled by
-    // dy_c / dy_n (the coupling enters row n divided by dy_n): first
-    // neighbour (1 + rn + rd) dy_c/dy_1 or (1 + rn) dy_c/dy_1, second
-    // -rn dy_c/dy_2, with rn = dy_1/(dy_1 + dy_c), rd = dy_c/(dy_c + dy_d)
-    // (d the downstream neighbour); diagonal 1 + rd (2, 1.5, -1/2 and 1.5
-    // on a uniform grid).
-    T ysc = T(1), yrc = T(0.5), yru = T(0.5);
-    T yA1 = T(2), yA15 = T(1.5), yB = T(-0.5), yaD = T(1.5);
-    if constexpr (FIELD) {
-        if (in.nonuniform && lane < hs) {
-            const int row = ypos ? y0 + lane : y0 + hs - 1 - lane;
-            const int stp = ypos ? -1 : 1;
-            int r1 = row + stp, r2 = row + 2 * stp, rd = row - stp;
-            if (in.periodic_y) {
-                r1 = wrap_mod(r1, in.ny);
-                r2 = wrap_mod(r2, in.ny);
-                rd = wrap_mod(rd, in.ny);
-            } else {
-                // beyond an outer wall the codes use the wall value instead
-                r1 = min(max(r1, 0), in.ny - 1);
-                r2 = min(max(r2, 0), in.ny - 1);
-                rd = min(max(rd, 0), in.ny - 1);
-            }
-            const double *rw = a.rows + in.row_off;
-            const double d0 = rw[row], d1 = rw[r1], d2 = rw[r2], dd = rw[rd];
-            ysc = T(1.0 / (d0 * in.inv_dx));
-            yrc = T(d0 / (d0 + d1));
-            yru = T(d1 / (d1 + d2));
-            if (ADJ) {
-                const double rn = d1 / (d1 + d0), rdn = d0 / (d0 + dd);
-                yA1 = T((1.0 + rn + rdn) * (d0 / d1));
-                yA15 = T((1.0 + rn) * (d0 / d1));
-                yB = T(-rn * (d0 / d2));
-                yaD = T(1.0 + rdn);
-            }
-        }
-    }
-
-    // rotating registers: x-upwind values A (prev1), B (prev2), X (free);
-    // y-upwind chain H0 (current hs1), H1 (free)
-    T rA[V], rB[V], rX[V], rH0[V], rH1[V];
-    // wrap state [strip][slot][velocity][lane]: independent of V and G
-    T *wrapp = a.wrap + in.wrap_off + ((size_t)it.strip * 3 * a.kp4 + kw) * 64 + lane;
-    const size_t wslot = (size_t)a.kp4 * 64;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        rA[v] = x_coupled ? wrapp[v * 64] : T(0);
-        rB[v] = x_coupled ? wrapp[wslot + v * 64] : T(0);
-        rH0[v] = x_coupled ? wrapp[2 * wslot + v * 64] : T(0);
-        rX[v] = T(0);
-        rH1[v] = T(0);
-    }
-
-    const long long cbase = in.cell_off;
-    const int nchunks = (tp + C - 1) / C;
-    const bool skew = tp != nx;
-    int xr0 = (tp - (lane % tp)) % tp;
-
-    issue(0);
-    commit(0);
-    __syncthreads();
-
-    // one step (s-th of the chunk in buffer b); (PA, PB, PX) and (HA, HB) are
-    // the register roles of this step in the rotation; hold: keep the
-    // registers when the lane has no cell at this step (xa false)
-    auto step = [&](int b, int s, int t, T *PA, T *PB, T *PX, T *HA, T *HB, bool hold, bool xa, int xr) {
-        const int sl = s % FL;
-        AccT acc[NACC];
-#pragma unroll
-        for (int m = 0; m < NACC; ++m)
-            acc[m] = AccT(0);
-        const T *rec = &st_rec[b][s][lane][0];
-        const int code = st_code[b][s][lane];
-        const int craw = st_cell[b][s][lane];
-        const int xn = code & 15, yn = code >> 4;
-        const bool solid = craw < 0;
-        const int cl = craw & SMAP_CELL;
-        const T b0 = rec[0], b1 = rec[1], b2 = rec[2], b3 = rec[3];
-        // wall values only where the cell has a wall term (LDS bandwidth);
-        // mw = 2 alpha U of a sliding wall on the y-upwind side (else 0)
-        T gx = T(0), gy = T(0), mw = T(0);
-        if (FIELD || (craw & SMAP_WALL) != 0) {
-            gx = rec[4];
-            gy = rec[5];
-            mw = rec[7];
-        }
-        const T px = lds_lut[xn & 7][0], qx = lds_lut[xn & 7][1];
-        T py = lds_lut[yn & 7][0], qy = lds_lut[yn & 7][1];
-        if constexpr (FIELD && !ADJ) {
-            // forward y weights from the row ratios (2, -1/2 and 3/2 when
-            // both are 1/2)
-            const int yp = yn & 7;
-            py = yp == NIB_INT ? T(1) + yrc + yru : yp == NIB_NEAR ? T(1) + yrc : T(0);
-            qy = yp == NIB_INT ? -yru : T(0);
-        }
-        if constexpr (FIELD && ADJ) {
-            // transposed y weights: pair index 2 w1 + w2 of the nibble
-            const int yp = yn & 7, w1i = yp >> 1;
-            py = w1i == 0 ? yA1 : w1i == 1 ? yA15 : T(0);
-            qy = ((yp & 1) == 0 && yp < 6) ? yB : T(0);
-        }
-        const int aox = xn >> 3, aoy = yn >> 3;
-        const int ci = solid ? STENCIL_SOLID : 2 * aox + aoy;
-        T ax = T(0), ay = T(0), dl = T(0);
-        if (FIELD) {
-            ax = aox ? T(1) : T(1.5);
-            ay = aoy ? T(1) : (ADJ ? yaD : T(1) + yrc);
-            dl = rec[6];
-        }
-        const T sbase = XU ? fma(b1, cxi[0], b0) : T(0);
-        const T gyw = XU ? fma(mw, cxi[0], gy) : T(0);
-        FaceRec fr;
-        if (FACES)
-            fr = st_face[b][s][lane];
-        T hout[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const T p1 = PA[v], p2 = PB[v], h1 = HA[v];
-            // staged as zero when the strip has no upstream neighbour
-            const T sm1 = st_seam[b][s][1][wave * V + v];
-            const T sm2 = st_seam[b][s][0][wave * V + v];
-            const T hS1 = dpp_shr1(sm1, p1);
-            const T hS2 = dpp_shr1(sm2, h1);
-            // a sliding wall emits rho_w + 2 U xi (Eq. diffuse1)
-            T gxv = gx, gyv = XU ? gyw : fma(mw, cxi[v], gy);
-            if (SPEC) {
-                // Maxwell's specular share: mirrored value of the previous iterate
-                if (fr.rdx >= 0)
-                    gxv = fma(T(fr.kx) * spec, fb_rd[(size_t)fr.rdx * a.kp4 + kmx + v], gxv);
-                if (fr.rdy >= 0)
-                    gyv = fma(T(fr.ky) * spec, fb_rd[(size_t)fr.rdy * a.kp4 + kmy + v], gyv);
-            }
-            const T S = fma(b3, cqq[v], fma(b2, ceta[v], XU ? sbase : fma(b1, cxi[v], b0)));
-            const T ux = fma(px, p1, fma(qx, p2, gxv));
-            const T uy = fma(py, hS1, fma(qy, hS2, gyv));
-            const T cyv = FIELD ? ccy[v] * ysc : ccy[v];
-            const T g = fma(ccx[v], ux, fma(cyv, uy, S));
-            T rinv;
-            if (FIELD) {
-                const T den = fma(ax, ccx[v], fma(ay, cyv, dl));
-                rinv = (solid || cw[v] == 0.0) ? T(0) : rcp_full(den);
-            } else {
-                rinv = lds_rinv[wave * V + v][ci];
-            }
-            const T h = g * rinv;
-            const AccT hd = (AccT)h;
-            if (P12) {
-                acc[0] = fma(cwxi[v] * (AccT)ceta[v], hd, acc[0]);
-            } else {
-                acc[0] = fma(cw[v], hd, acc[0]);
-                if (!XU)
-                    acc[1] = fma(cwxi[v], hd, acc[1]);
-                acc[2] = fma(cweta[v], hd, acc[2]);
-                acc[3] = fma(cwq[v], hd, acc[3]);
-                if (GRAD && !solid)
-                    acc[4] = fma(cw[v], hd * a.ckpt[((size_t)cbase + cl) * a.kp4 + krev + v], acc[4]);
-            }
-            if (FBWRITE && !solid && xa) {
-                // values this cell sends through its downstream wall faces:
-                // forward -- the reconstructed incident face value;
-                // adjoint -- the cell value
-                if (fr.wrx >= 0)
-                    fb_wr[(size_t)fr.wrx * a.kp4 + kw + v] =
-                        ADJ ? h : (aox ? h : T(1.5) * h - T(0.5) * p1);
-                if (fr.wry >= 0)
-                    fb_wr[(size_t)fr.wry * a.kp4 + kw + v] =
-                        ADJ ? h : (aoy ? h : (FIELD ? (T(1) + yrc) * h - yrc * hS1 : T(1.5) * h - T(0.5) * hS1));
-            }
-            if (CKPT && !solid && xa)
-                a.ckpt[((size_t)cbase + cl) * a.kp4 + kw + v] = hd;
-            hout[v] = h;
-            if (hold) {
-                PX[v] = xa ? h : p1;
-                PA[v] = xa ? p1 : p2;       // prev2 of the next step
-                HB[v] = xa ? hS1 : h1;
-            } else {
-                PX[v] = h;
-                HB[v] = hS1;
-            }
-        }
-        if (XU && !P12)
-            acc[1] = xi0 * acc[0];
-        // the last two rows of the strip feed the next strip next iteration
-        if (!P12 && has_down && t < tp && lane >= hs - 2 && lane < hs && xa) {
-            // x of this lane's cell from its running position on the diagonal
-            // (the seam of one strip holds < 2^31 values, checked on the host)
-            const int xx = xpos ? xr : nx - 1 - xr;
-            const int slot = lane - (hs - 2);
-            T *sp = seam_out + (xx * (2 * a.kp4) + slot * a.kp4 + kw);
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                sp[v] = hout[v];
-        }
-#pragma unroll
-        for (int m = 0; m < NACC; ++m)
-            lds_part[sl][wave][lane][m] = acc[m];
-    };
-
-    // group-wide sum of the partial moments of steps [s0, s0 + FL) of buffer b
-    auto flush = [&](int b, int s0) {
-        __syncthreads();
-        for (int e = tid; e < FL * 64 * NACC; e += 64 * G) {
-            const int sl = e / (64 * NACC), l = (e / NACC) % 64, m = e % NACC;
-            const int craw = st_cell[b][s0 + sl][l];
-            if (craw < 0)
-                continue;
-            const int cl = craw & SMAP_CELL;
-            double sum = 0.0;
-#pragma unroll
-            for (int w = 0; w < G; ++w)
-                sum += lds_part[sl][w][l][m];
-            const size_t cg = (size_t)it.group * a.ncell + cbase + cl;
-            if (P12)
-                a.part5[cg] = sum;
-            else if (m < 4)
-                a.part[cg * 4 + m] = (T)sum;
-            else
-                a.part5[cg] = sum;
-        }
-        __syncthreads();
-    };
-
-    for (int c = 0; c < nchunks; ++c) {
-        const int b = c & 1;
-        const int t0 = c * C;
-        if (c + 1 < nchunks)
-            issue(c + 1);
-        bool xa[C];
-        int xrs[C];
-        {
-            int xr = xr0;
-#pragma unroll
-            for (int s = 0; s < C; ++s) {
-                xa[s] = (t0 + s < tp) && (xr < nx);
-                xrs[s] = xr;
-                xr = (xr + 1 == tp) ? 0 : xr + 1;
-            }
-        }
-        // every lane has a cell at every step of the chunk: no register holds
-        const bool fast = skew ? (t0 >= 63 && t0 + C <= nx) : (t0 + C <= tp);
-        // register roles cycle with period 6: (A,B,X)(H0,H1) -> (X,A,B)(H1,H0) -> ...
-        if (fast) {
-            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, false, true, xrs[0]);
-            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, false, true, xrs[1]);
-            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, false, true, xrs[2]);
-            if (FL == 3)
-                flush(b, 0);
-            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, false, true, xrs[3]);
-            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, false, true, xrs[4]);
-            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, false, true, xrs[5]);
-        } else {
-            step(b, 0, t0 + 0, rA, rB, rX, rH0, rH1, true, xa[0], xrs[0]);
-            step(b, 1, t0 + 1, rX, rA, rB, rH1, rH0, true, xa[1], xrs[1]);
-            step(b, 2, t0 + 2, rB, rX, rA, rH0, rH1, true, xa[2], xrs[2]);
-            if (FL == 3)
-                flush(b, 0);
-            step(b, 3, t0 + 3, rA, rB, rX, rH1, rH0, true, xa[3], xrs[3]);
-            step(b, 4, t0 + 4, rX, rA, rB, rH0, rH1, true, xa[4], xrs[4]);
-            step(b, 5, t0 + 5, rB, rX, rA, rH1, rH0, true, xa[5], xrs[5]);
-        }
-        xr0 = (xr0 + C) % tp;
-        if (c + 1 < nchunks)
-            commit(b ^ 1);
-        flush(b, C - FL);
-    }
-    if (!P12 && x_coupled) {
-        if (sizeof(T) == 4 && a.rwrap) {
-            // FP32 correction iteration: plus its constant term
-            const double *rw = a.rwrap + (wrapp - a.wrap);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                wrapp[v * 64] = (T)((double)rA[v] + rw[v * 64]);
-                wrapp[wslot + v * 64] = (T)((double)rB[v] + rw[wslot + v * 64]);
-                wrapp[2 * wslot + v * 64] = (T)((double)rH0[v] + rw[2 * wslot + v * 64]);
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                wrapp[v * 64] = rA[v];
-                wrapp[wslot + v * 64] = rB[v];
-                wrapp[2 * wslot + v * 64] = rH0[v];
-            }
-        }
-    }
-}
-
+// calling workgroup: work item blockIdx.x in k_sweep, drawn from a counter
+// in the persistent iteration.  The body is the text of dvm_sweep_body.inc
+// in both: the kernel reads its arguments in place from the kernel argument
+// segment (a by-value copy handed to an inlined function stays live in
+// registers across the pass and spilled the specular per-cell passes).
 template <typename T, int V, int G, int MODE>
 __global__ void __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, G, MODE>())))
 k_sweep(SweepArgs<T> a)
 {
-    sweep_item<T, V, G, MODE>(a, blockIdx.x);
+    const int item = blockIdx.x;
+#include "dvm_sweep_body.inc"
 }
+
+template <typename T, int V, int G, int MODE>
+__device__ __forceinline__ void sweep_item(const SweepArgs<T> &a, int item)
+{
+#include "dvm_sweep_body.inc"
+}
+
 
 // ----------------------------------------------------------------- moments
 // 256 threads = 64 cells x 4 quadrants: each thread sums its quadrant's
