@@ -100,6 +100,8 @@ def parse():
                         "a-posteriori error bound)")
     p.add_argument("--block-iters", type=int, default=32,
                    help="iterations per captured block (the stop and rate checks run between blocks)")
+    p.add_argument("--alpha", type=float, default=0.9,
+                   help="accommodation coefficient of the gradient workload (adjoint)")
     p.add_argument("--persistent", action="store_true",
                    help="run blocks of iterations as one cooperative launch (untimed sweeps only: "
                         "the roofline's timed steps use separate launches)")
@@ -571,12 +573,13 @@ def bench_porous(args, torch, dvm):
 def bench_adjoint(args, torch, dvm):
     """The gradient workload: a 256 x 256 periodic porous cell (porosity
     0.55, seed 3005), log-normal delta(x) of mean 1 smoothed over 8 cells
-    (seed 3006), accommodation 0.9, 48 x 48 velocities, FP64.  One step = the
+    (seed 3006), accommodation --alpha (default 0.9), 48 x 48 velocities,
+    FP64.  One step = the
     forward solve to the stop rule and the gradient (dQ/d delta per cell and
     dQ/d alpha: checkpoint sweep, adjoint solve, gradient sweep), timed
     apart."""
     from paper_1704_03126_amd.geometry import delta_field, porous_discs
-    nv, alpha = 48, 0.9
+    nv, alpha = 48, args.alpha
     g = porous_discs(256, 0.55, 3005)
     base = np.where(g.mask == 0, delta_field(g.mask.shape, 3006), 0.0)
     s = dvm.Solver(nv, 1, tol=args.tol, **solver_options(args, dvm))
@@ -609,7 +612,7 @@ def bench_adjoint(args, torch, dvm):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "adjoint_porous_256x256_phi0.55_seed3005_deltafield_alpha0.9_nv48",
+           "config": {"workload": f"adjoint_porous_256x256_phi0.55_seed3005_deltafield_alpha{alpha:g}_nv48",
                       "nx": g.nx, "ny": g.ny, "fluid_cells": g.n_fluid, "velocities": nv * nv,
                       "alpha": alpha, "tol": args.tol, "schedule": args.schedule, "accel": args.accel,
                       "parallelism": "single_gpu"},
