@@ -624,21 +624,35 @@ def bench_adjoint(args, torch, dvm):
     print(json.dumps(out))
 
 
+KERNEL_SOURCES = ("dvm_kernels.hip", "dvm_sweep_body.inc", "dvm_internal.h")
+
+
+def kernel_source_sha256():
+    """sha256 over the sweep kernel's source files, in a fixed order (None if
+    one is missing)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        src = os.path.join(ROOT, "paper_1704_03126_amd", "csrc", name)
+        if not os.path.exists(src):
+            return None
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, precision, vel, waves, schedule=None):
     """Profiler-measured HBM bytes per sweep launch (profiles/), valid only
     while the kernel source, the workload, the sweep precision, order and
     launch shape are the ones that were profiled."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "k_sweep_traffic.json")
-    src = os.path.join(ROOT, "paper_1704_03126_amd", "csrc", "dvm_kernels.hip")
-    if not (os.path.exists(path) and os.path.exists(src)):
+    sha = kernel_source_sha256()
+    if not (os.path.exists(path) and sha):
         return None
     with open(path) as f:
         entries = json.load(f)
     if isinstance(entries, dict):
         entries = [entries]
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
     for tr in entries:
         if not sha.startswith(tr.get("kernel_source_sha256_prefix", "-")):
             continue

@@ -201,10 +201,12 @@ struct dvm_ctx {
     bool adj_ready = false;
     std::vector<uint8_t> h_scode_adj;
     std::vector<FaceRec> h_sface_adj;
+    std::vector<FaceK> h_sfacek_adj;
     std::vector<int> h_wl_adj;            // wall-read lists of the adjoint sweep
     std::vector<int> h_face_cell, h_face_side, h_face_inst;
     DevBuf<uint8_t> d_scode_adj;
     DevBuf<FaceRec> d_sface_adj;
+    DevBuf<FaceK> d_sfacek_adj;
     DevBuf<int> d_wl, d_wl_adj;
     DevBuf<int> d_face_cell, d_face_side, d_face_inst;
     DevBuf<double> d_srec_adj, d_mom_adj, d_u1prev_adj, d_seam_adj, d_wrap_adj, d_fb_adj;
@@ -273,7 +275,8 @@ struct dvm_ctx {
         d_vt.release(); d_dfield.release(); d_part.release(); d_mom.release(); d_rows.release();
         d_u1prev.release(); d_seam.release(); d_wrap.release(); d_aux.release();
         d_st.release(); d_sface.release(); d_fb.release(); d_wl.release(); d_wl_adj.release();
-        d_scode_adj.release(); d_sface_adj.release(); d_face_cell.release(); d_face_side.release();
+        d_scode_adj.release(); d_sface_adj.release(); d_sfacek_adj.release(); d_face_cell.release();
+        d_face_side.release();
         d_face_inst.release(); d_srec_adj.release(); d_mom_adj.release(); d_u1prev_adj.release();
         d_seam_adj.release(); d_wrap_adj.release(); d_fb_adj.release(); d_ckpt.release();
         d_part5.release(); d_momg.release(); d_dqda.release(); d_st_adj.release();
@@ -584,10 +587,13 @@ static int build_layout(dvm_ctx *c)
     std::stable_sort(c->items.begin(), c->items.end(), [&](const WorkItem &a, const WorkItem &b) {
         return c->idev[a.inst].tp > c->idev[b.inst].tp;
     });
-    for (int i = 0; i < c->n_inst; ++i)
+    for (int i = 0; i < c->n_inst; ++i) {
         if ((long long)c->inst[i].nx * 2 * c->kp4 >= (1ll << 31))
             return fail(DVM_EINVAL, "instance " + std::to_string(i) +
                                         ": nx too large for the velocity grid (nx * 2 * padded velocities >= 2^31)");
+        if ((long long)c->inst[i].nx * c->inst[i].ny > SMAP_CELL)
+            return fail(DVM_EINVAL, "instance " + std::to_string(i) + ": more than 2^29 - 1 cells");
+    }
     // The solution state (moments, seam, wrap and wall-face buffers, delta
     // field) survives a new layout that keeps every instance's state where it
     // was: same velocity padding, same offsets -- only the sweep order of
@@ -678,11 +684,12 @@ static int build_layout(dvm_ctx *c)
     // Per entry: the fluid cell (-1 for none or solid), the x / y stencil
     // nibbles of the forward and the adjoint problem, and the wall faces each
     // problem reads and writes.
-    const FaceRec none{-1, -1, -1, -1, 0.0, 0.0};
+    const FaceRec none{-1, -1, -1, -1};
     std::vector<uint8_t> scode(sk, NIB_ZERO * 17), scode_adj(sk, NIB_ZERO * 17);
     std::vector<int> smap(sk, -1);
     std::vector<long long> spos(cell * 4, -1);
     std::vector<FaceRec> sface(sk, none), sface_adj(sk, none);
+    std::vector<FaceK> sfacek_adj(sk, FaceK{0.0, 0.0});
     c->h_face_cell.assign(faces, 0);
     c->h_face_side.assign(faces, 0);
     c->h_face_inst.assign(faces, 0);
@@ -738,7 +745,6 @@ static int build_layout(dvm_ctx *c)
                         fr.rdy = cyu == CODE_WALL ? gface(cl, dys) : -1;
                         fr.wrx = cxd == CODE_WALL ? gface(cl, dxd) : -1;
                         fr.wry = cyd == CODE_WALL ? gface(cl, dyd) : -1;
-                        fr.kx = fr.ky = 1.0;
                         // adjoint: the upwind wall face of the cell (weight
                         // 1.5, or 1 with a wall on the far side too) or of its
                         // upwind neighbour (weight -0.5)
@@ -767,10 +773,12 @@ static int build_layout(dvm_ctx *c)
                                 }
                             }
                         };
-                        adj_face(cxu, cxd, dxs, fa.rdx, fa.kx);
-                        adj_face(cyu, cyd, dys, fa.rdy, fa.ky);
+                        adj_face(cxu, cxd, dxs, fa.rdx, sfacek_adj[e].kx);
+                        adj_face(cyu, cyd, dys, fa.rdy, sfacek_adj[e].ky);
                         fa.wrx = fr.wrx;
                         fa.wry = fr.wry;
+                        if (fr.rdx >= 0 || fr.rdy >= 0 || fr.wrx >= 0 || fr.wry >= 0 || fa.rdx >= 0 || fa.rdy >= 0)
+                            smap[e] |= SMAP_FACE;
                     }
             }
         }
@@ -820,6 +828,7 @@ static int build_layout(dvm_ctx *c)
     c->h_wl_adj.swap(wl_adj);
     c->h_scode_adj.swap(scode_adj);
     c->h_sface_adj.swap(sface_adj);
+    c->h_sfacek_adj.swap(sfacek_adj);
     HIPCHK(hipMemcpyAsync(c->d_codes.p, codes.data(), cell, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_scode.p, scode.data(), sk, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_smap.p, smap.data(), sk * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -856,6 +865,7 @@ static SweepArgs<double> sweep_args(dvm_ctx *c, int force, bool adj = false)
     a.scode = adj ? c->d_scode_adj.p : c->d_scode.p;
     a.smap = c->d_smap.p;
     a.sface = adj ? c->d_sface_adj.p : c->d_sface.p;
+    a.sfacek = adj ? c->d_sfacek_adj.p : nullptr;
     a.wl = adj ? c->d_wl_adj.p : c->d_wl.p;
     a.fb = adj ? c->d_fb_adj.p : c->d_fb.p;
     a.ckpt = c->d_ckpt.p;
@@ -3112,6 +3122,7 @@ static int ensure_adjoint(dvm_ctx *c)
     const long long sk = c->sk_total, cell = c->ncell, nf = std::max<long long>(c->nfaces, 1);
     HIPCHK(c->d_scode_adj.alloc(sk));
     HIPCHK(c->d_sface_adj.alloc(sk));
+    HIPCHK(c->d_sfacek_adj.alloc(sk));
     HIPCHK(c->d_face_cell.alloc(nf));
     HIPCHK(c->d_face_side.alloc(nf));
     HIPCHK(c->d_face_inst.alloc(nf));
@@ -3127,6 +3138,8 @@ static int ensure_adjoint(dvm_ctx *c)
     HIPCHK(c->d_st_adj.alloc(c->n_inst));
     HIPCHK(hipMemcpyAsync(c->d_scode_adj.p, c->h_scode_adj.data(), sk, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->d_sface_adj.p, c->h_sface_adj.data(), sk * sizeof(FaceRec), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_sfacek_adj.p, c->h_sfacek_adj.data(), sk * sizeof(FaceK), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(c->d_wl_adj.alloc(std::max<size_t>(c->h_wl_adj.size(), 1)));
     if (!c->h_wl_adj.empty())

@@ -94,10 +94,11 @@ struct WorkItem {
     int inst, strip, group, pad;
 };
 
-// skewed cell map entries: fluid cell index, with this bit set when the
+// skewed cell map entries: fluid cell index, with SMAP_WALL set when the
 // cell has a wall term on an upwind side (the record's wall values are read
-// only then); -1 for no cell
-enum { SMAP_WALL = 1 << 30, SMAP_CELL = (1 << 30) - 1 };
+// only then) and SMAP_FACE when its face record (forward or adjoint) names a
+// wall face (the record is read only then); -1 for no cell
+enum { SMAP_WALL = 1 << 30, SMAP_FACE = 1 << 29, SMAP_CELL = (1 << 29) - 1 };
 
 // grids at least this wide use the wrap-around diagonal schedule
 enum { WRAP_MIN = 8 };
@@ -118,10 +119,14 @@ struct SolveState {
 };
 
 // face record of a sweep entry (alpha < 1 and the gradient): faces whose
-// buffer is read on the x / y upwind side (with weight kx / ky), and the
-// cell's own faces on the x / y downstream side that receive values
+// buffer is read on the x / y upwind side, and the cell's own faces on the
+// x / y downstream side that receive values (-1: none)
 struct FaceRec {
     int rdx, rdy, wrx, wry;
+};
+// weights of the faces read by the adjoint sweep's entries (the forward
+// sweep reads its faces with weight 1)
+struct FaceK {
     double kx, ky;
 };
 
@@ -133,6 +138,7 @@ struct SweepArgs {
     const uint8_t *scode;     // skewed stencil nibbles [entry]
     const int *smap;          // skewed entry -> fluid cell of the instance, -1 none
     const FaceRec *sface;     // skewed face records [entry] (MODE_SPEC/CKPT/GRAD)
+    const FaceK *sfacek;      // their read weights [entry] (adjoint with MODE_SPEC)
     const int *wl;            // wall-read lists [wl_off + (pass * chunks + chunk) * SPEC_SLOTS + slot]
     T *fb;                    // wall-face values [2][fb_half]: [parity][face][kp4]
     double *ckpt;             // checkpoint h [cell][kp4] (MODE_CKPT writes, MODE_GRAD reads)

@@ -43,8 +43,12 @@ def test_traffic_figures_only_for_the_profiled_kernel():
         entries = json.load(f)
     if isinstance(entries, dict):
         entries = [entries]
-    with open(os.path.join(ROOT, "paper_1704_03126_amd", "csrc", "dvm_kernels.hip"), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("dvm_kernels.hip", "dvm_sweep_body.inc", "dvm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1704_03126_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
+    assert sha == bench.kernel_source_sha256()
     for tr in entries:
         wl, prec = tr.get("workload_key", "rough_channel"), tr.get("precision", "fp64")
         got = bench.measured_traffic(wl, prec, *tr["shape"], schedule=tr.get("schedule"))
