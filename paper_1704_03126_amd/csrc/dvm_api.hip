@@ -234,6 +234,7 @@ struct dvm_ctx {
     // those values (plain sweep modes); the seam part is added by a separate
     // pass over the seam segments only (d_seg32s)
     DevBuf<double> d_rb_mom, d_rb_wrap;
+    DevBuf<float> d_rr32;       // the seam part of rr in FP32 (positions of rr)
     DevBuf<VSeg2> d_seg32s;
     int nseg32s = 0;
     DevBuf<SolveState> d_st32;
@@ -283,7 +284,7 @@ struct dvm_ctx {
         kw.release();
         d_srec32.release(); d_seam32.release(); d_wrap32.release(); d_fb32.release(); d_vt32.release();
         d_mom_d.release(); d_u1prev_d.release(); d_xr.release(); d_rr.release(); d_er.release();
-        d_rb_mom.release(); d_rb_wrap.release(); d_seg32s.release();
+        d_rb_mom.release(); d_rb_wrap.release(); d_seg32s.release(); d_rr32.release();
         d_st32.release(); d_seg32.release(); d_q.release(); d_pargs.release(); d_ctr.release();
         if (own_stream && stream)
             (void)hipStreamDestroy(stream);
@@ -1114,7 +1115,8 @@ static int enqueue_iteration(dvm_ctx *c, int kind)
         }
         HIPCHK(launch_moments(fused ? mom_args32r(c) : mom_args32(c), c->max_cells, c->n_inst, c->stream));
         if (fused)
-            HIPCHK(launch_state32(c->d_seg32s.p, c->nseg32s, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
+            HIPCHK(launch_state32_add32(c->d_seg32s.p, c->nseg32s, c->d_st32.p, state32(c), c->d_rr32.p,
+                                        c->stream));
         else
             HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 0, c->stream));
         HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
@@ -1192,6 +1194,7 @@ static int enqueue_persist(dvm_ctx *c, int iters, int kind, bool *done)
         a.nseg = fused ? c->nseg32s : c->nseg32;
         a.sb = state32(c);
         a.rr = c->d_rr.p;
+        a.rr32 = fused ? c->d_rr32.p : nullptr;
         a.st = c->d_st32.p;
         a.n_inst = c->n_inst;
         a.nitems = (int)c->items.size();
@@ -2356,6 +2359,7 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
         return DVM_OK;
     HIPCHK(c->d_xr.alloc(n));
     HIPCHK(c->d_rr.alloc(n));
+    HIPCHK(c->d_rr32.alloc(n));
     HIPCHK(c->d_er.alloc(n));
     KrylovWork &kw = c->kw;
     std::vector<VSeg> gseg, sseg;
@@ -2565,7 +2569,8 @@ static int dc_run(dvm_ctx *c, int i0, int i1, std::vector<SolveState> &st, std::
         if ((rc = upload(c->d_st32.p, st32)))
             return rc;
         HIPCHK(launch_state32(c->d_seg32.p, c->nseg32, c->d_st32.p, state32(c), c->d_rr.p, 1, c->stream));
-        HIPCHK(launch_rscatter(c->d_seg32.p, c->nseg32, c->d_rr.p, c->d_rb_mom.p, c->d_rb_wrap.p, c->stream));
+        HIPCHK(launch_rscatter(c->d_seg32.p, c->nseg32, c->d_rr.p, c->d_rb_mom.p, c->d_rb_wrap.p, c->d_rr32.p,
+                               c->stream));
         HIPCHK(launch_record<float>(rec_args32(c), c->max_cells, c->n_inst, c->stream));
         for (auto &d : slots)
             if (d.live)

@@ -317,6 +317,17 @@ __device__ __forceinline__ void state32_add(const VSeg2 &sg, int par, StateBufs3
     }
 }
 
+// The same with the term in FP32 (the seam values of the FP32 correction
+// iteration): an FP32 add.
+__device__ __forceinline__ void state32_add(const VSeg2 &sg, int par, StateBufs32 b, const float *vec, int i0,
+                                            int di)
+{
+    const float *v = vec + sg.vec_off;
+    float *f = b.b[sg.buf - 1] + sg.off[par];
+    for (int i = i0; i < sg.len; i += di)
+        f[i] = f[i] + v[i];
+}
+
 // Blocks of source iterations of a batch as one cooperative launch (plain
 // sweep modes: MODE_FIELD and MODE_XU only; 4 velocities per lane, 8 waves
 // per workgroup).  Per iteration: the sweep's work items taken from a device
@@ -333,6 +344,7 @@ struct PersistArgs {
     int nseg;
     StateBufs32 sb;
     const double *rr;
+    const float *rr32;        // non-null: the add takes this FP32 term (FP32 segments only)
     SolveState *st;           // the stop rule's states (those of sw, mom, rec)
     int n_inst;
     int nitems;
@@ -356,10 +368,15 @@ hipError_t launch_persist(const PersistArgs<T> *dev_args, int nitems, int iters,
 hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b, double *vec, int what,
                           hipStream_t s);
 // the FP32 correction's constant term vec (segments of seg) into buffers in
-// the layout of the moments and wrap buffers; seam and wall-face segments
-// are left out
+// the layout of the moments and wrap buffers, and its seam part rounded to
+// FP32 into rseam32 (same positions as in vec); wall-face segments are left
+// out
 hipError_t launch_rscatter(const VSeg2 *seg, int nseg, const double *vec, double *rmom, double *rwrap,
-                           hipStream_t s);
+                           float *rseam32, hipStream_t s);
+// FP32 state outputs of the sweep just run (parity st.iter & 1) += vec32, for
+// the FP32 segments of seg (instances not iterating are left alone)
+hipError_t launch_state32_add32(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b,
+                                const float *vec32, hipStream_t s);
 // mixed-precision Krylov steps: what 0 -- FP32 state inputs of the next
 // sweep = v (an FP32 basis vector); what 1 -- w = v - FP32 state outputs of
 // the sweep just run

@@ -785,11 +785,16 @@ k_persist(const PersistArgs<T> *pa, int iters, double tol)
             const int nseg = pa->nseg;
             const StateBufs32 sb = pa->sb;
             const double *rr = pa->rr;
+            const float *rr32 = pa->rr32;
             const SolveState *st = pa->st;
             for (int k = blockIdx.x; k < nseg; k += gridDim.x) {
                 const VSeg2 sg = seg[k];
-                if (st[sg.inst].active != 0)
-                    state32_add(sg, (int)(st[sg.inst].iter & 1), sb, rr, threadIdx.x, 64 * G);
+                if (st[sg.inst].active != 0) {
+                    if (rr32)
+                        state32_add(sg, (int)(st[sg.inst].iter & 1), sb, rr32, threadIdx.x, 64 * G);
+                    else
+                        state32_add(sg, (int)(st[sg.inst].iter & 1), sb, rr, threadIdx.x, 64 * G);
+                }
             }
             grid.sync();
         }

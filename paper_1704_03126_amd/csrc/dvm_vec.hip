@@ -369,25 +369,52 @@ hipError_t launch_state32(const VSeg2 *seg, int nseg, const SolveState *st, Stat
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_rscatter(const VSeg2 *seg, const double *vec, double *rmom, double *rwrap)
+__global__ void __launch_bounds__(256) k_rscatter(const VSeg2 *seg, const double *vec, double *rmom, double *rwrap,
+                                                  float *rseam32)
 {
     const VSeg2 sg = seg[blockIdx.x];
+    const double *v = vec + sg.vec_off;
+    if (sg.buf == 1) {
+        float *r = rseam32 + sg.vec_off;
+        for (int i = threadIdx.x; i < sg.len; i += 256)
+            r[i] = (float)v[i];
+        return;
+    }
     double *dst = sg.buf == 0 ? rmom : sg.buf == 2 ? rwrap : nullptr;
     if (!dst)
         return;
     // moments and wrap state: one offset for both parities
     dst += sg.off[0];
-    const double *v = vec + sg.vec_off;
     for (int i = threadIdx.x; i < sg.len; i += 256)
         dst[i] = v[i];
 }
 
 hipError_t launch_rscatter(const VSeg2 *seg, int nseg, const double *vec, double *rmom, double *rwrap,
-                           hipStream_t s)
+                           float *rseam32, hipStream_t s)
 {
     if (nseg == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_rscatter, dim3(nseg), dim3(256), 0, s, seg, vec, rmom, rwrap);
+    hipLaunchKernelGGL(k_rscatter, dim3(nseg), dim3(256), 0, s, seg, vec, rmom, rwrap, rseam32);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_state32_add32(const VSeg2 *seg, const SolveState *st, StateBufs32 b,
+                                                       const float *vec32)
+{
+    const VSeg2 sg = seg[blockIdx.x];
+    // the add runs inside captured blocks of iterations: an instance that
+    // has stopped iterating keeps its state
+    if (sg.buf == 0 || st[sg.inst].active == 0)
+        return;
+    state32_add(sg, (int)(st[sg.inst].iter & 1), b, vec32, threadIdx.x, 256);
+}
+
+hipError_t launch_state32_add32(const VSeg2 *seg, int nseg, const SolveState *st, StateBufs32 b,
+                                const float *vec32, hipStream_t s)
+{
+    if (nseg == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_state32_add32, dim3(nseg), dim3(256), 0, s, seg, st, b, vec32);
     return hipGetLastError();
 }
 
