@@ -47,6 +47,8 @@ NV = 64
 TOL = 1e-8
 HBM_PEAK = 8.0e12                 # MI355X HBM3E bytes/s
 FP64_VALU_PEAK = 78.6e12          # MI355X FP64 vector FLOP/s
+VALU_SIMDS = 256 * 4               # MI355X: 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9                   # MI355X peak engine clock
 # arithmetic the sweep performs per fluid cell x velocity update (FMA = 2):
 # collision gain 3 FMA, upwind terms 2 x 2 FMA, combination 2 FMA,
 # reciprocal-diagonal scaling 1 MUL, quadrature moments 1 MUL + 1 ADD + 3 FMA
@@ -392,14 +394,23 @@ def batch_roofline(prof, vel, waves, args):
     tr = measured_traffic("batch64", dom, vel, waves)
     traffic = None
     detail = None
+    valu = None
     if tr is not None:
         traffic = tr["fetch_bytes"] + tr["write_bytes"]
         detail = {"fetch_bytes_per_launch": tr["fetch_bytes"], "write_bytes_per_launch": tr["write_bytes"],
                   "measured_over_algorithmic": traffic / d["algorithmic_bytes_per_launch"],
                   "source": tr.get("source", "")}
+        if tr.get("sq_insts_valu_per_launch"):
+            # VALU issue: a wave64 VALU instruction holds a 16-lane SIMD for
+            # 4 cycles; the profiled instruction count against the SIMD
+            # cycles of this run's average launch
+            cycles = VALU_SIMDS * CLOCK_HZ * d["avg_launch_ms"] / 1e3
+            busy = 4.0 * tr["sq_insts_valu_per_launch"] / cycles
+            valu = {"insts_per_launch": tr["sq_insts_valu_per_launch"], "simd_cycles_per_launch": cycles,
+                    "issue_busy": busy, "source": "SQ_INSTS_VALU of the profiled run (profiles/)"}
     return {"bound": "hbm", "achieved": d["achieved_GBps"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": d["achieved_GBps"] * 1e9 / HBM_PEAK, "traffic": traffic, "traffic_detail": detail,
-            "kernel": f"k_sweep<{'float' if dom == 'fp32' else 'double'},{vel},{waves}>",
+            "valu": valu, "kernel": f"k_sweep<{'float' if dom == 'fp32' else 'double'},{vel},{waves}>",
             "bytes_per_update": BYTES_PER_UPDATE[dom], "legs": legs,
             "timing": "HIP events around every sweep launch on the solver's stream, timed steps only"}
 
