@@ -155,6 +155,18 @@ typedef struct {
                                gradient passes; other blocks (and profile =
                                1) use the separate launches.  0 (default):
                                separate launches, replayed as HIP graphs   */
+    int krylov_deflate;     /* GMRES restarts with deflation (Morgan's
+                               GMRES-DR): each cycle hands this many harmonic
+                               Ritz vectors of its smallest harmonic Ritz
+                               values, with its residual, to the next cycle,
+                               whose Arnoldi steps extend that basis instead
+                               of starting from the residual alone (the
+                               slowest modes of the source iteration stay in
+                               the Krylov space across restarts).  0 -> 16;
+                               negative -> plain restarts; at most 31 and
+                               krylov_dim/2 - 1; a complex pair is kept
+                               whole (one more).  A cycle whose kept basis
+                               cannot be formed to rounding restarts plainly */
 } dvm_config;
 
 /* Per-instance result of dvm_solve. */

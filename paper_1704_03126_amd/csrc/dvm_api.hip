@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -20,7 +21,9 @@
 #include <vector>
 
 #include "../../include/dvm.h"
+#include "dvm_eig.h"
 #include "dvm_internal.h"
+#include "dvm_krylov.h"
 
 using namespace dvm;
 
@@ -131,10 +134,13 @@ struct KrylovWork {
     DevBuf<VChunk> ch;
     DevBuf<int> c0, nc;
     DevBuf<VSeg2> seg2;  // FP32 correction state of the slots (mixed-precision steps)
+    DevBuf<float> T;     // deflated restart: the next cycle's first basis vectors
+    DevBuf<double> pc;   //                   and their combination coefficients
     void release()
     {
         V.release(); x.release(); w.release(); part.release(); c1.release(); c2.release(); y.release();
         gseg.release(); sseg.release(); ch.release(); c0.release(); nc.release(); seg2.release();
+        T.release(); pc.release();
     }
 };
 
@@ -1784,7 +1790,11 @@ static long long state_segments(const dvm_ctx *c, int i, int pw, long long voff,
 }
 
 struct GmresSlotHost {
-    std::vector<double> H, cs, sn, g;   // H: (m+1) x m column-major
+    std::vector<double> H, cs, sn, g;   // H: (m+1) x m column-major, rotated to R
+    std::vector<double> Hr;             // the same unrotated (the cycle's Hessenberg Hb)
+    std::vector<double> c;              // right-hand side of the cycle in its basis
+    std::vector<double> Q0;             // deflated restart: orthogonal factor of the kept block
+    std::vector<double> P, Hn;          //                   next cycle's basis map and block
     double beta = 0.0, sig = -1.0;
     bool live = true;
     long long sweeps = 0;
@@ -1831,6 +1841,10 @@ static double sigma_min_tri(const std::vector<double> &R, int ld, int k)
     return 1.0 / std::sqrt(lam);
 }
 
+// Harmonic Ritz vectors a GMRES cycle hands to the next (deflated restarts;
+// dvm_config.krylov_deflate = 0)
+constexpr int KRYLOV_DEFLATE_DEFAULT = 16;
+
 // Work of one GMRES cycle of k Arnoldi steps on one instance, in sweeps of
 // that instance: the cycle's k + 1 sweeps, plus the HBM traffic of the
 // orthogonalisation over its state vector of len elements (step j reads the
@@ -1851,6 +1865,12 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                      std::vector<char> *reverted, bool mixed)
 {
     const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 64;
+    // deflated restarts: harmonic Ritz vectors a cycle hands to the next
+    const int want = c->cfg.krylov_deflate < 0
+                         ? 0
+                         : std::min(c->cfg.krylov_deflate > 0 ? c->cfg.krylov_deflate : KRYLOV_DEFLATE_DEFAULT,
+                                    m / 2 - 1);
+    int kd = 0;   // kept vectors the current cycle starts from (the same for every slot)
     const int mode = solve_mode(c) | (adj ? MODE_ADJ : xu_flag(c, c->V));
     SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
     StateBufs sb;
@@ -1887,12 +1907,20 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
     HIPCHK(grow(kw.c2, (size_t)ns * (m + 2)));
     HIPCHK(grow(kw.y, (size_t)ns * (m + 2)));
     const int cst = m + 2;
+    const int pstr = VCOMB_IN * VCOMB_OUT;
+    if (want > 0) {
+        HIPCHK(grow(kw.T, (size_t)(want + 2) * n));
+        HIPCHK(grow(kw.pc, (size_t)ns * pstr));
+    }
+    std::vector<double> hpc(want > 0 ? (size_t)ns * pstr : 0);
 
     std::vector<GmresSlotHost> hs(ns);
     for (int q = 0; q < ns; ++q)
         hs[q].sweeps = prior.empty() ? 0 : prior[slots[q].inst];
     for (auto &h : hs) {
         h.H.assign((size_t)(m + 1) * m, 0.0);
+        h.Hr.assign((size_t)(m + 1) * m, 0.0);
+        h.c.assign(m + 1, 0.0);
         h.cs.assign(m, 0.0);
         h.sn.assign(m, 0.0);
         h.g.assign(m + 1, 0.0);
@@ -2045,7 +2073,9 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             RecArgs<double> ra = rec_args(c, adj);
             HIPCHK(launch_record<double>(ra, c->max_cells, c->n_inst, c->stream));
         }
-        if ((rc = dots(kw.w.p, 0, true, kw.c1.p)))
+        // with a deflated restart also the residual's coordinates in the kept basis
+        const int nkept = kd > 0 ? kd + 1 : 0;
+        if ((rc = dots(kw.w.p, nkept, true, kw.c1.p)))
             return rc;
         std::vector<SolveState> dev(c->n_inst);
         HIPCHK(hipMemcpyAsync(dev.data(), dst, c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, c->stream));
@@ -2066,7 +2096,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             const double est = sig > 0.0 ? eps / sig : INFINITY;
             s.eps = eps;
             s.est = est;
-            h.beta = std::sqrt(std::max(hc1[(size_t)q * cst], 0.0));
+            h.beta = std::sqrt(std::max(hc1[(size_t)q * cst + nkept], 0.0));
             int fin = 0;
             if (!(amax < 1e30) || eps != eps || !std::isfinite(h.beta))
                 fin = STATUS_DIVERGED;
@@ -2116,16 +2146,68 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         if (changed && (rc = rebuild()))
             return rc;
         // ---- GMRES cycle
-        for (int q = 0; q < ns; ++q) {
-            std::fill(hs[q].H.begin(), hs[q].H.end(), 0.0);
-            std::fill(hs[q].g.begin(), hs[q].g.end(), 0.0);
-            hs[q].g[0] = hs[q].beta;
+        if (kd > 0) {
+            // a deflated start needs the residual inside the kept span (it is,
+            // up to the FP32 basis and, in the mixed steps, the FP32
+            // operator); otherwise every slot restarts plainly from w
+            for (int q = 0; q < ns; ++q) {
+                if (!hs[q].live)
+                    continue;
+                double in = 0.0;
+                for (int i = 0; i <= kd; ++i)
+                    in += hc1[(size_t)q * cst + i] * hc1[(size_t)q * cst + i];
+                const double lost = hs[q].beta * hs[q].beta - in;
+                if (!(lost <= 1e-4 * hs[q].beta * hs[q].beta)) {
+                    if (debug_on())
+                        std::fprintf(stderr, "[dvm gmres] inst %d: %.2e of the residual outside the kept basis, "
+                                     "plain restart\n", slots[q].inst, std::sqrt(std::max(lost, 0.0)) / hs[q].beta);
+                    kd = 0;
+                }
+            }
+            if (kd == 0) {
+                // |w|^2 in the first coefficient row for the plain start below
+                for (int q = 0; q < ns; ++q)
+                    hc1[(size_t)q * cst] = hs[q].beta * hs[q].beta;
+                HIPCHK(hipMemcpyAsync(kw.c1.p, hc1.data(), hc1.size() * sizeof(double), hipMemcpyHostToDevice,
+                                      c->stream));
+            }
         }
-        // V_0 = w / beta (coefficient row holds |w|^2 with no vectors)
-        HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, 0, kw.c1.p, cst, kw.V.p,
-                              c->stream));
-        int k = 0;
-        for (int j = 0; j < m; ++j) {
+        for (int q = 0; q < ns; ++q) {
+            GmresSlotHost &h = hs[q];
+            std::fill(h.H.begin(), h.H.end(), 0.0);
+            std::fill(h.Hr.begin(), h.Hr.end(), 0.0);
+            std::fill(h.g.begin(), h.g.end(), 0.0);
+            std::fill(h.c.begin(), h.c.end(), 0.0);
+            if (kd == 0 || !h.live) {
+                h.g[0] = h.beta;
+                h.c[0] = h.beta;
+                continue;
+            }
+            // kept block Hn = Q0 R: R opens the rotated matrix, Q0^T acts on
+            // rows 0..kd of every later column and on c
+            std::vector<double> R;
+            dvm_eig::qr_small(h.Hn, kd + 1, kd, h.Q0, R);
+            for (int j = 0; j < kd; ++j)
+                for (int i = 0; i <= kd; ++i) {
+                    h.Hr[(size_t)j * (m + 1) + i] = h.Hn[i + (size_t)j * (kd + 1)];
+                    h.H[(size_t)j * (m + 1) + i] = R[i + (size_t)j * (kd + 1)];
+                }
+            for (int i = 0; i <= kd; ++i)
+                h.c[i] = hc1[(size_t)q * cst + i];
+            for (int i = 0; i <= kd; ++i) {
+                double a = 0.0;
+                for (int r = 0; r <= kd; ++r)
+                    a += h.Q0[r + (size_t)i * (kd + 1)] * h.c[r];
+                h.g[i] = a;
+            }
+        }
+        if (kd == 0) {
+            // V_0 = w / beta (coefficient row holds |w|^2 with no vectors)
+            HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, 0, kw.c1.p, cst, kw.V.p,
+                                  c->stream));
+        }
+        int k = kd;
+        for (int j = kd; j < m; ++j) {
             float *Vj = kw.V.p + (size_t)j * n;
             if ((rc = krylov_step(Vj)))
                 return rc;
@@ -2158,7 +2240,20 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                     n2 -= hc2[(size_t)q * cst + i] * hc2[(size_t)q * cst + i];
                 }
                 col[j + 1] = std::sqrt(std::max(n2, 0.0));
-                for (int i = 0; i < j; ++i) {
+                std::copy(col, col + j + 2, &h.Hr[(size_t)j * (m + 1)]);
+                int i0 = 0;
+                if (kd > 0) {
+                    double t[VCOMB_OUT];
+                    for (int i = 0; i <= kd; ++i) {
+                        double a = 0.0;
+                        for (int r = 0; r <= kd; ++r)
+                            a += h.Q0[r + (size_t)i * (kd + 1)] * col[r];
+                        t[i] = a;
+                    }
+                    std::copy(t, t + kd + 1, col);
+                    i0 = kd;
+                }
+                for (int i = i0; i < j; ++i) {
                     const double a = h.cs[i] * col[i] + h.sn[i] * col[i + 1];
                     col[i + 1] = -h.sn[i] * col[i] + h.cs[i] * col[i + 1];
                     col[i] = a;
@@ -2215,7 +2310,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 if ((*trial)[inst] && h.beta > 0.0) {
                     const double red = std::max(std::fabs(h.g[k]) / h.beta, 1e-300);
                     const double cost = gmres_cycle_cost(k, slots[q].len, c->inst[inst].nfluid * (double)c->K,
-                                                         mixed ? 5.0 : 8.0);
+                                                         mixed ? 5.0 : 8.0) - kd;
                     h.trial_red += -std::log(red);
                     h.trial_cost += cost;
                     const double rate_g = h.trial_red / h.trial_cost;
@@ -2248,6 +2343,60 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 if ((rc = rebuild()))
                     return rc;
             }
+        }
+        // ---- deflated restart: the next cycle starts from the harmonic
+        // Ritz vectors of the smallest harmonic Ritz values and the cycle's
+        // residual (csrc/dvm_eig.h), the same number for every live slot
+        const int kd_prev = kd;
+        kd = 0;
+        if (want > 0 && k >= want + 2) {
+            std::vector<int> dq(ns, 0);
+            int target = want;
+            for (int pass = 0; pass < 3 && kd == 0; ++pass) {
+                int dmin = INT_MAX, dmax = -1;
+                for (int q = 0; q < ns; ++q) {
+                    GmresSlotHost &h = hs[q];
+                    if (!h.live)
+                        continue;
+                    std::vector<double> rho(h.c.begin(), h.c.begin() + k + 1);
+                    for (int j = 0; j < k; ++j) {
+                        const double yj = hy[(size_t)q * cst + j];
+                        for (int i = 0; i <= k; ++i)
+                            rho[i] -= h.Hr[(size_t)j * (m + 1) + i] * yj;
+                    }
+                    dq[q] = dvm_eig::deflate(h.Hr, m + 1, k, rho, target, h.P, h.Hn);
+                    dmin = std::min(dmin, dq[q]);
+                    dmax = std::max(dmax, dq[q]);
+                }
+                if (dmax < 0 || dmin <= 0)
+                    break;
+                if (dmin == dmax)
+                    kd = dmin;
+                else
+                    target = pass == 0 ? dmin : dmin - 1;
+                if (target <= 0)
+                    break;
+            }
+            if (kd > 0) {
+                for (int q = 0; q < ns; ++q) {
+                    if (!hs[q].live)
+                        continue;
+                    double *pq = hpc.data() + (size_t)q * pstr;
+                    for (int j = 0; j <= k; ++j)
+                        for (int o = 0; o <= kd; ++o)
+                            pq[j * (kd + 1) + o] = hs[q].P[j + (size_t)o * (k + 1)];
+                }
+                HIPCHK(hipMemcpyAsync(kw.pc.p, hpc.data(), hpc.size() * sizeof(double), hipMemcpyHostToDevice,
+                                      c->stream));
+                HIPCHK(launch_vcombine(kw.ch.p, (int)chunks.size(), kw.V.p, n, k + 1, kd + 1, kw.pc.p, pstr,
+                                       kw.T.p, c->stream));
+                HIPCHK(hipMemcpyAsync(kw.V.p, kw.T.p, (size_t)(kd + 1) * n * sizeof(float),
+                                      hipMemcpyDeviceToDevice, c->stream));
+                // hpc is rewritten only after the next cycle's synchronisations
+            }
+            if (debug_on())
+                std::fprintf(stderr, "[dvm gmres] cycle of %d steps (from %d kept): next cycle keeps %d\n", k,
+                             kd_prev, kd);
         }
     }
     if (mixed) {
@@ -3337,6 +3486,8 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
         return fail(DVM_EINVAL, "krylov_dim must be in [0, 64]");
     if (c.persistent != 0 && c.persistent != 1)
         return fail(DVM_EINVAL, "persistent must be 0 or 1");
+    if (c.krylov_deflate > VCOMB_OUT - 2)
+        return fail(DVM_EINVAL, "krylov_deflate must be at most 31");
     int V = c.vel_per_lane ? c.vel_per_lane : 4;
     int G = c.waves_per_block ? c.waves_per_block : 8;
     bool okvg = (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) || (V == 2 && G == 8);

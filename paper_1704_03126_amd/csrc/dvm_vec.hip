@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "dvm_internal.h"
+#include "dvm_krylov.h"
 
 namespace dvm {
 
@@ -326,6 +327,39 @@ __global__ void __launch_bounds__(256) k_vupdate4(const VChunk *ch, double *w, c
     }
 }
 
+// Deflated GMRES restart: out_o = sum_j P[slot][j][o] V_j for o < nout, j <
+// nin (the slot's combination coefficients staged in LDS; FP64 sums of the
+// FP32 basis, stored in FP32).
+__global__ void __launch_bounds__(256) k_vcombine(const VChunk *ch, const float *V, long long ldv, int nin,
+                                                  int nout, const double *P, int pstride, float *out)
+{
+    __shared__ double sp[VCOMB_IN * VCOMB_OUT];
+    const VChunk c = ch[blockIdx.x];
+    const double *pp = P + (size_t)c.slot * pstride;
+    for (int i = threadIdx.x; i < nin * nout; i += 256)
+        sp[i] = pp[i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < c.len; e += 256) {
+        const size_t g = (size_t)c.start + e;
+        double acc[VCOMB_OUT];
+#pragma unroll
+        for (int o = 0; o < VCOMB_OUT; ++o)
+            acc[o] = 0.0;
+        for (int j = 0; j < nin; ++j) {
+            const double v = (double)V[(size_t)j * ldv + g];
+            const double *pj = sp + j * nout;
+#pragma unroll
+            for (int o = 0; o < VCOMB_OUT; ++o)
+                if (o < nout)
+                    acc[o] = fma(pj[o], v, acc[o]);
+        }
+#pragma unroll
+        for (int o = 0; o < VCOMB_OUT; ++o)
+            if (o < nout)
+                out[(size_t)o * ldv + g] = (float)acc[o];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_state32(const VSeg2 *seg, const SolveState *st, StateBufs32 b,
                                                  double *vec, int what)
 {
@@ -570,6 +604,17 @@ hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const float *V, 
                           const double *coef, int cstride, float *vout, hipStream_t s)
 {
     hipLaunchKernelGGL((k_vupdate<float>), dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout);
+    return hipGetLastError();
+}
+
+hipError_t launch_vcombine(const VChunk *ch, int nch, const float *V, long long ldv, int nin, int nout,
+                           const double *P, int pstride, float *out, hipStream_t s)
+{
+    if (nch == 0)
+        return hipSuccess;
+    if (nin < 1 || nin > VCOMB_IN || nout < 1 || nout > VCOMB_OUT || pstride < nin * nout)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vcombine, dim3(nch), dim3(256), 0, s, ch, V, ldv, nin, nout, P, pstride, out);
     return hipGetLastError();
 }
 

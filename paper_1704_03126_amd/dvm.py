@@ -53,7 +53,8 @@ class dvm_config(ctypes.Structure):
                 ("use_graphs", ctypes.c_int), ("vel_per_lane", ctypes.c_int),
                 ("waves_per_block", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
                 ("profile", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("accel", ctypes.c_int), ("krylov_dim", ctypes.c_int), ("persistent", ctypes.c_int)]
+                ("accel", ctypes.c_int), ("krylov_dim", ctypes.c_int), ("persistent", ctypes.c_int),
+                ("krylov_deflate", ctypes.c_int)]
 
 
 class dvm_prof(ctypes.Structure):
@@ -201,12 +202,13 @@ class Solver:
                  use_graphs: bool = True, vel_per_lane: int = 0,
                  waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_AUTO,
                  accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, tune_cache: str | None = None,
-                 stream=None, allocator: TorchAllocator | None = None, persistent: bool = False):
+                 stream=None, allocator: TorchAllocator | None = None, persistent: bool = False,
+                 krylov_deflate: int = 0):
         lib = load_library()
         tc = tune_cache.encode() if tune_cache else None
         cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
                          vel_per_lane, waves_per_block, tc, int(profile), int(schedule),
-                         int(accel), int(krylov_dim), int(persistent))
+                         int(accel), int(krylov_dim), int(persistent), int(krylov_deflate))
         h = ctypes.c_void_p()
         s = stream if stream is not None else _current_stream()
         self.allocator = allocator          # kept alive until dvm_destroy

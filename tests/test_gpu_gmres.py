@@ -88,15 +88,20 @@ def test_gmres_adjoint_multi_strip(dvm):
     qp = s.flow_rate(0)[0]
     s.solve(0, 1.0 - eps, 0.9)
     qm = s.flow_rate(0)[0]
-    ea = 1e-4
-    s.solve(0, 1.0, 0.9 + ea)
-    qap = s.flow_rate(0)[0]
-    s.solve(0, 1.0, 0.9 - ea)
-    qam = s.flow_rate(0)[0]
+    # dQ/d alpha is small (about 1e-5 of Q): a fourth-order central
+    # difference at step 1e-2 keeps both its truncation error and the solves'
+    # own error (tol 1e-12 on u1) well below 1e-6 of the derivative, which a
+    # second-order one at step 1e-4 could not (its solve-error term alone
+    # is about 1e-3 of it unless the errors of neighbouring solves cancel)
+    ea = 1e-2
+    qa = {}
+    for k in (-2, -1, 1, 2):
+        s.solve(0, 1.0, 0.9 + k * ea)
+        qa[k] = s.flow_rate(0)[0]
     s.close()
     fd = (qp - qm) / (2 * eps)
     assert abs(gd.sum() - fd) <= 1e-6 * abs(fd), (gd.sum(), fd)
-    fda = (qap - qam) / (2 * ea)
+    fda = (8.0 * (qa[1] - qa[-1]) - (qa[2] - qa[-2])) / (12.0 * ea)
     assert abs(ga - fda) <= 1e-6 * abs(fda), (ga, fda)
 
 
@@ -184,3 +189,35 @@ def test_auto_gmres_trial_on_slow_iteration(dvm):
     s.solve(0, 1.0)
     assert abs(s.flow_rate(0)[0] - q1) <= 1e-9 * abs(q1)
     s.close()
+
+
+def test_gmres_deflated_restarts(dvm):
+    """Deflated restarts (harmonic Ritz vectors kept from cycle to cycle)
+    against plain restarts on a periodic porous cell at large delta, where
+    restarted GMRES(64) stagnates: both reach the oracle's fixed point, the
+    deflated one in fewer sweeps."""
+    g = porous_discs(48, 0.6, 1003)
+    nv = 8
+    ref = oracle.si_solve(g.mask, 40.0, nv, periodic_y=True, cells_per_H=48.0, tol=1e-12)
+    res = {}
+    for name, kd in (("plain", -1), ("deflated", 0), ("deflated8", 8)):
+        s, info, Q, mom = solve(dvm, g, 40.0, nv, krylov_deflate=kd)
+        s.close()
+        assert info.status == "converged", (name, info)
+        assert abs(Q - ref.Q) <= 1e-8 * abs(ref.Q), (name, Q, ref.Q)
+        assert np.max(np.abs(mom["u1"] - ref.u1)) <= 1e-8, name
+        res[name] = info.iters
+    assert res["deflated"] < res["plain"], res
+    assert res["deflated8"] < res["plain"], res
+    # deeper in the slow regime (no oracle run: the plain iteration would
+    # need tens of thousands of sweeps): the same fixed point, far fewer sweeps
+    out = {}
+    for name, kd in (("plain", -1), ("deflated", 0)):
+        s, info, Q, mom = solve(dvm, g, 150.0, nv, krylov_deflate=kd)
+        s.close()
+        assert info.status == "converged", (name, info)
+        out[name] = (Q, info.iters, mom["u1"])
+    (qp, ip, up), (qd, idf, ud) = out["plain"], out["deflated"]
+    assert abs(qd - qp) <= 1e-8 * abs(qp), (qd, qp)
+    assert np.max(np.abs(ud - up)) <= 1e-8
+    assert idf < 0.8 * ip, (idf, ip)
