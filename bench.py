@@ -107,6 +107,8 @@ def parse():
     p.add_argument("--persistent", action="store_true",
                    help="run blocks of iterations as one cooperative launch (untimed sweeps only: "
                         "the roofline's timed steps use separate launches)")
+    p.add_argument("--krylov-dim", type=int, default=0,
+                   help="GMRES restart length (0: the library's default, 64)")
     p.add_argument("--krylov-deflate", type=int, default=0,
                    help="harmonic Ritz vectors a GMRES cycle hands to the next (0: the library's "
                         "default, negative: plain restarts)")
@@ -289,7 +291,7 @@ def solver_options(args, dvm):
             "accel": {"auto": dvm.DVM_ACCEL_AUTO, "none": dvm.DVM_ACCEL_NONE,
                       "gmres": dvm.DVM_ACCEL_GMRES}[args.accel],
             "block_iters": args.block_iters, "persistent": args.persistent,
-            "krylov_deflate": args.krylov_deflate}
+            "krylov_dim": args.krylov_dim, "krylov_deflate": args.krylov_deflate}
 
 
 def stored_oracle_error(g, Qs):
@@ -442,7 +444,8 @@ def batch_time_to_solution(args, torch, dvm, gs, deltas, vel, waves):
                               ("fp64_plain_iteration", dvm.DVM_FP64, dvm.DVM_ACCEL_NONE)):
         s = dvm.Solver(BATCH_NV, len(gs), tol=args.tts_tol, max_iter=200000, precision=prec, accel=accel,
                        vel_per_lane=vel, waves_per_block=waves, block_iters=args.block_iters,
-                       persistent=args.persistent, krylov_deflate=args.krylov_deflate)
+                       persistent=args.persistent, krylov_dim=args.krylov_dim,
+                       krylov_deflate=args.krylov_deflate)
         for i, g in enumerate(gs):
             s.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
         s.solve(1, deltas[1])             # layout, buffers and captured blocks, outside the timing

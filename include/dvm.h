@@ -139,8 +139,10 @@ typedef struct {
                                by eps (relative) with eps / sigma <= tol,
                                sigma the smallest singular value of the last
                                Krylov projection clamped to [1e-3, 1]         */
-    int krylov_dim;         /* GMRES restart length; 0 -> 64 (max 64); at large
-                               delta (Kn 0.01-0.03) a restart of 30 stagnated */
+    int krylov_dim;         /* GMRES restart length; 0 -> 40 with deflated
+                               restarts, 64 with plain ones (max 64); at large
+                               delta (Kn 0.01-0.03) a plain restart of 30
+                               stagnated                                     */
     int persistent;         /* 1: run each block of block_iters iterations
                                (FP64 forward and FP32 correction) as one
                                cooperative launch that stays resident: per
@@ -162,7 +164,8 @@ typedef struct {
                                whose Arnoldi steps extend that basis instead
                                of starting from the residual alone (the
                                slowest modes of the source iteration stay in
-                               the Krylov space across restarts).  0 -> 16;
+                               the Krylov space across restarts).  0 -> a
+                               quarter of the restart length (10 of 40);
                                negative -> plain restarts; at most 31 and
                                krylov_dim/2 - 1; a complex pair is kept
                                whole (one more).  A cycle whose kept basis

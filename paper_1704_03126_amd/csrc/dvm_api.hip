@@ -136,11 +136,12 @@ struct KrylovWork {
     DevBuf<VSeg2> seg2;  // FP32 correction state of the slots (mixed-precision steps)
     DevBuf<float> T;     // deflated restart: the next cycle's first basis vectors
     DevBuf<double> pc;   //                   and their combination coefficients
+    DevBuf<int> vw;      // per slot: whether the Arnoldi step writes its next basis vector
     void release()
     {
         V.release(); x.release(); w.release(); part.release(); c1.release(); c2.release(); y.release();
         gseg.release(); sseg.release(); ch.release(); c0.release(); nc.release(); seg2.release();
-        T.release(); pc.release();
+        T.release(); pc.release(); vw.release();
     }
 };
 
@@ -1795,6 +1796,9 @@ struct GmresSlotHost {
     std::vector<double> c;              // right-hand side of the cycle in its basis
     std::vector<double> Q0;             // deflated restart: orthogonal factor of the kept block
     std::vector<double> P, Hn;          //                   next cycle's basis map and block
+    int kd = 0;                         // kept vectors this cycle starts from
+    int kq = 0;                         // columns of this cycle so far
+    bool done = false;                  // its Arnoldi process has stopped
     double beta = 0.0, sig = -1.0;
     bool live = true;
     long long sweeps = 0;
@@ -1841,9 +1845,11 @@ static double sigma_min_tri(const std::vector<double> &R, int ld, int k)
     return 1.0 / std::sqrt(lam);
 }
 
-// Harmonic Ritz vectors a GMRES cycle hands to the next (deflated restarts;
-// dvm_config.krylov_deflate = 0)
-constexpr int KRYLOV_DEFLATE_DEFAULT = 16;
+// GMRES restart length with deflated restarts (dvm_config.krylov_dim = 0);
+// a cycle then keeps a quarter of it (krylov_deflate = 0).  Time to solution
+// of the uneven batch at 1e-6 (FP32 + refinement): 7.83 s at (64, 16), 6.73 s
+// at (40, 10), 6.82 s at (48, 12), 6.87 s at (32, 8).
+constexpr int KRYLOV_DIM_DEFLATED = 40;
 
 // Work of one GMRES cycle of k Arnoldi steps on one instance, in sweeps of
 // that instance: the cycle's k + 1 sweeps, plus the HBM traffic of the
@@ -1864,13 +1870,13 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                      const std::vector<long long> &prior, const std::vector<char> *trial,
                      std::vector<char> *reverted, bool mixed)
 {
-    const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64) : 64;
-    // deflated restarts: harmonic Ritz vectors a cycle hands to the next
-    const int want = c->cfg.krylov_deflate < 0
-                         ? 0
-                         : std::min(c->cfg.krylov_deflate > 0 ? c->cfg.krylov_deflate : KRYLOV_DEFLATE_DEFAULT,
-                                    m / 2 - 1);
-    int kd = 0;   // kept vectors the current cycle starts from (the same for every slot)
+    // restart length and the harmonic Ritz vectors a cycle hands to the next
+    // (deflated restarts; defaults measured on the uneven batch, the porous
+    // rarefaction sweep and the Couette channels)
+    const bool deflate = c->cfg.krylov_deflate >= 0;
+    const int m = c->cfg.krylov_dim > 0 ? std::min(c->cfg.krylov_dim, 64)
+                                        : (deflate ? KRYLOV_DIM_DEFLATED : 64);
+    const int want = !deflate ? 0 : std::min(c->cfg.krylov_deflate > 0 ? c->cfg.krylov_deflate : m / 4, m / 2 - 1);
     const int mode = solve_mode(c) | (adj ? MODE_ADJ : xu_flag(c, c->V));
     SolveState *dst = adj ? c->d_st_adj.p : c->d_st.p;
     StateBufs sb;
@@ -1899,7 +1905,13 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
         return b.n >= cnt ? hipSuccess : b.alloc(cnt);
     };
     const long long nchmax = n / VCHUNK + ns + 1;
-    HIPCHK(grow(kw.V, (size_t)(m + 1) * n));
+    if (kw.V.n < (size_t)(m + 1) * n) {
+        // zeroed once: an instance whose Arnoldi process has stopped still
+        // has the later basis columns scattered into its state (and its
+        // results ignored), which must hold finite values
+        HIPCHK(kw.V.alloc((size_t)(m + 1) * n));
+        HIPCHK(launch_zero_f(kw.V.p, kw.V.n, c->stream));
+    }
     HIPCHK(grow(kw.x, n));
     HIPCHK(grow(kw.w, n));
     HIPCHK(grow(kw.part, (size_t)(m + 2) * nchmax));
@@ -2048,7 +2060,9 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
     const long long cap = c->cfg.max_iter;
     HIPCHK(launch_gather(kw.sseg.p, (int)sseg.size(), sb, kw.x.p, nullptr, c->stream));
 
-    std::vector<double> hc1((size_t)ns * cst), hc2((size_t)ns * cst), hy((size_t)ns * cst);
+    std::vector<double> hc1((size_t)ns * cst), hc2((size_t)ns * cst), hy((size_t)ns * cst), hz((size_t)ns * cst);
+    std::vector<int> hvw(ns, 0);
+    HIPCHK(grow(kw.vw, (size_t)ns));
     bool trials = false;
     for (int q = 0; q < ns; ++q)
         trials = trials || (trial && (*trial)[slots[q].inst]);
@@ -2073,8 +2087,11 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             RecArgs<double> ra = rec_args(c, adj);
             HIPCHK(launch_record<double>(ra, c->max_cells, c->n_inst, c->stream));
         }
-        // with a deflated restart also the residual's coordinates in the kept basis
-        const int nkept = kd > 0 ? kd + 1 : 0;
+        // with deflated restarts also the residual's coordinates in the kept bases
+        int nkept = 0;
+        for (int q = 0; q < ns; ++q)
+            if (hs[q].live && hs[q].kd > 0)
+                nkept = std::max(nkept, hs[q].kd + 1);
         if ((rc = dots(kw.w.p, nkept, true, kw.c1.p)))
             return rc;
         std::vector<SolveState> dev(c->n_inst);
@@ -2145,46 +2162,53 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             break;
         if (changed && (rc = rebuild()))
             return rc;
-        // ---- GMRES cycle
-        if (kd > 0) {
-            // a deflated start needs the residual inside the kept span (it is,
-            // up to the FP32 basis and, in the mixed steps, the FP32
-            // operator); otherwise every slot restarts plainly from w
-            for (int q = 0; q < ns; ++q) {
-                if (!hs[q].live)
-                    continue;
+        // ---- GMRES cycle.  Every instance runs its own Arnoldi process: it
+        // starts from its kept basis (deflated restart, kd > 0) or from w
+        // (kd = 0) and stops at its own column; the global step j only
+        // shares the sweeps, so a batch gives each instance the arithmetic
+        // of its own solve.
+        bool plain_any = false;
+        for (int q = 0; q < ns; ++q) {
+            GmresSlotHost &h = hs[q];
+            if (!h.live)
+                continue;
+            if (h.kd > 0) {
+                // a deflated start needs the residual inside the kept span
+                // (it is, up to the FP32 basis and, in the mixed steps, the
+                // FP32 operator); otherwise this instance restarts plainly
                 double in = 0.0;
-                for (int i = 0; i <= kd; ++i)
+                for (int i = 0; i <= h.kd; ++i)
                     in += hc1[(size_t)q * cst + i] * hc1[(size_t)q * cst + i];
-                const double lost = hs[q].beta * hs[q].beta - in;
-                if (!(lost <= 1e-4 * hs[q].beta * hs[q].beta)) {
+                const double lost = h.beta * h.beta - in;
+                if (!(lost <= 1e-4 * h.beta * h.beta)) {
                     if (debug_on())
                         std::fprintf(stderr, "[dvm gmres] inst %d: %.2e of the residual outside the kept basis, "
-                                     "plain restart\n", slots[q].inst, std::sqrt(std::max(lost, 0.0)) / hs[q].beta);
-                    kd = 0;
+                                     "plain restart\n", slots[q].inst, std::sqrt(std::max(lost, 0.0)) / h.beta);
+                    h.kd = 0;
                 }
             }
-            if (kd == 0) {
-                // |w|^2 in the first coefficient row for the plain start below
-                for (int q = 0; q < ns; ++q)
-                    hc1[(size_t)q * cst] = hs[q].beta * hs[q].beta;
-                HIPCHK(hipMemcpyAsync(kw.c1.p, hc1.data(), hc1.size() * sizeof(double), hipMemcpyHostToDevice,
-                                      c->stream));
-            }
+            plain_any = plain_any || h.kd == 0;
         }
+        int jmin = m;
         for (int q = 0; q < ns; ++q) {
             GmresSlotHost &h = hs[q];
             std::fill(h.H.begin(), h.H.end(), 0.0);
             std::fill(h.Hr.begin(), h.Hr.end(), 0.0);
             std::fill(h.g.begin(), h.g.end(), 0.0);
             std::fill(h.c.begin(), h.c.end(), 0.0);
-            if (kd == 0 || !h.live) {
+            h.done = false;
+            h.kq = 0;
+            if (!h.live)
+                continue;
+            jmin = std::min(jmin, h.kd);
+            if (h.kd == 0) {
                 h.g[0] = h.beta;
                 h.c[0] = h.beta;
                 continue;
             }
             // kept block Hn = Q0 R: R opens the rotated matrix, Q0^T acts on
             // rows 0..kd of every later column and on c
+            const int kd = h.kd;
             std::vector<double> R;
             dvm_eig::qr_small(h.Hn, kd + 1, kd, h.Q0, R);
             for (int j = 0; j < kd; ++j)
@@ -2201,13 +2225,38 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 h.g[i] = a;
             }
         }
-        if (kd == 0) {
-            // V_0 = w / beta (coefficient row holds |w|^2 with no vectors)
-            HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, 0, kw.c1.p, cst, kw.V.p,
+        if (plain_any) {
+            // V_0 = w / beta for the instances that start plainly (coefficient
+            // row |w|^2 with no vectors); the others keep their V_0
+            std::fill(hz.begin(), hz.end(), 0.0);
+            for (int q = 0; q < ns; ++q) {
+                hvw[q] = hs[q].live && hs[q].kd == 0 ? 1 : 0;
+                if (hvw[q])
+                    hz[(size_t)q * cst] = hs[q].beta * hs[q].beta;
+            }
+            HIPCHK(hipMemcpyAsync(kw.c2.p, hz.data(), hz.size() * sizeof(double), hipMemcpyHostToDevice,
                                   c->stream));
+            HIPCHK(hipMemcpyAsync(kw.vw.p, hvw.data(), ns * sizeof(int), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(launch_vupdate4_masked(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, 0, kw.c2.p, cst, kw.V.p,
+                                          kw.vw.p, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
         }
-        int k = kd;
-        for (int j = kd; j < m; ++j) {
+        int k = jmin;
+        for (int j = jmin; j < m; ++j) {
+            // the instances that take this step: live, not yet stopped, and
+            // past their kept vectors
+            bool pending = false, step = false;
+            for (int q = 0; q < ns; ++q) {
+                const GmresSlotHost &h = hs[q];
+                pending = pending || (h.live && !h.done);
+                hvw[q] = h.live && !h.done && j >= h.kd ? 1 : 0;
+                step = step || hvw[q];
+            }
+            if (!pending)
+                break;
+            if (!step)
+                continue;
+            HIPCHK(hipMemcpyAsync(kw.vw.p, hvw.data(), ns * sizeof(int), hipMemcpyHostToDevice, c->stream));
             float *Vj = kw.V.p + (size_t)j * n;
             if ((rc = krylov_step(Vj)))
                 return rc;
@@ -2219,18 +2268,17 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                                   c->stream));
             if ((rc = dots(kw.w.p, j + 1, true, kw.c2.p, kw.c1.p)))
                 return rc;
-            HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c2.p, cst,
-                                  kw.V.p + (size_t)(j + 1) * n, c->stream));
+            HIPCHK(launch_vupdate4_masked(kw.ch.p, (int)chunks.size(), kw.w.p, kw.V.p, n, j + 1, kw.c2.p, cst,
+                                          kw.V.p + (size_t)(j + 1) * n, kw.vw.p, c->stream));
             HIPCHK(hipMemcpyAsync(hc1.data(), kw.c1.p, hc1.size() * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
             HIPCHK(hipMemcpyAsync(hc2.data(), kw.c2.p, hc2.size() * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
             k = j + 1;
-            bool all_done = true;
             for (int q = 0; q < ns; ++q) {
                 GmresSlotHost &h = hs[q];
-                if (!h.live)
+                if (!hvw[q])
                     continue;
                 h.sweeps += 1;
                 double *col = &h.H[(size_t)j * (m + 1)];
@@ -2241,7 +2289,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 }
                 col[j + 1] = std::sqrt(std::max(n2, 0.0));
                 std::copy(col, col + j + 2, &h.Hr[(size_t)j * (m + 1)]);
-                int i0 = 0;
+                const int kd = h.kd;
                 if (kd > 0) {
                     double t[VCOMB_OUT];
                     for (int i = 0; i <= kd; ++i) {
@@ -2251,9 +2299,8 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                         t[i] = a;
                     }
                     std::copy(t, t + kd + 1, col);
-                    i0 = kd;
                 }
-                for (int i = i0; i < j; ++i) {
+                for (int i = kd; i < j; ++i) {
                     const double a = h.cs[i] * col[i] + h.sn[i] * col[i + 1];
                     col[i + 1] = -h.sn[i] * col[i] + h.cs[i] * col[i + 1];
                     col[i] = a;
@@ -2265,34 +2312,38 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 col[j + 1] = 0.0;
                 h.g[j + 1] = -h.sn[j] * h.g[j];
                 h.g[j] = h.cs[j] * h.g[j];
+                h.kq = j + 1;
                 const double res = std::fabs(h.g[j + 1]);
-                if (!(res <= 1e-3 * h.beta) && h.sweeps < cap)
-                    all_done = false;
+                if (res <= 1e-3 * h.beta || h.sweeps >= cap)
+                    h.done = true;
             }
-            if (all_done)
-                break;
         }
-        // x -= V y per slot, y from the triangular system of the cycle
+        // x -= V y per slot, y from the triangular system of its cycle
         std::fill(hy.begin(), hy.end(), 0.0);
+        int kmax = 0;
         for (int q = 0; q < ns; ++q) {
             GmresSlotHost &h = hs[q];
             if (!h.live)
                 continue;
-            std::vector<double> y(k, 0.0);
-            for (int i = k - 1; i >= 0; --i) {
+            const int kq = h.kq;
+            kmax = std::max(kmax, kq);
+            std::vector<double> y(kq, 0.0);
+            for (int i = kq - 1; i >= 0; --i) {
                 double a = h.g[i];
-                for (int jj = i + 1; jj < k; ++jj)
+                for (int jj = i + 1; jj < kq; ++jj)
                     a -= h.H[(size_t)jj * (m + 1) + i] * y[jj];
                 const double dg = h.H[(size_t)i * (m + 1) + i];
                 y[i] = dg != 0.0 ? a / dg : 0.0;
             }
-            for (int i = 0; i < k; ++i)
+            for (int i = 0; i < kq; ++i)
                 hy[(size_t)q * cst + i] = y[i];
-            h.sig = sigma_min_tri(h.H, m + 1, k);
+            h.sig = sigma_min_tri(h.H, m + 1, kq);
         }
+        (void)k;
         HIPCHK(hipMemcpyAsync(kw.y.p, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, k, kw.y.p, cst, nullptr, c->stream));
-        if (trials && k > 0) {
+        HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, kmax, kw.y.p, cst, nullptr,
+                              c->stream));
+        if (trials && kmax > 0) {
             // a trial instance stays with GMRES while its cycles together
             // have reduced its residual at least 1.5 times faster per unit of
             // work than the plain iteration, both counted in sweeps of the
@@ -2307,10 +2358,10 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 const int inst = slots[q].inst;
                 if (!h.live)
                     continue;
-                if ((*trial)[inst] && h.beta > 0.0) {
-                    const double red = std::max(std::fabs(h.g[k]) / h.beta, 1e-300);
-                    const double cost = gmres_cycle_cost(k, slots[q].len, c->inst[inst].nfluid * (double)c->K,
-                                                         mixed ? 5.0 : 8.0) - kd;
+                if ((*trial)[inst] && h.beta > 0.0 && h.kq > 0) {
+                    const double red = std::max(std::fabs(h.g[h.kq]) / h.beta, 1e-300);
+                    const double cost = gmres_cycle_cost(h.kq, slots[q].len, c->inst[inst].nfluid * (double)c->K,
+                                                         mixed ? 5.0 : 8.0) - h.kd;
                     h.trial_red += -std::log(red);
                     h.trial_cost += cost;
                     const double rate_g = h.trial_red / h.trial_cost;
@@ -2318,7 +2369,7 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                     if (debug_on())
                         std::fprintf(stderr, "[dvm trial] inst %d cycle of %d: residual x %.3e over %.1f "
                                      "sweep-equivalents (trial so far %.3g per sweep) vs plain q %.5f (%.3g per "
-                                     "sweep)\n", inst, k, red, cost, rate_g, c->trial_q[inst], rate_p);
+                                     "sweep)\n", inst, h.kq, red, cost, rate_g, c->trial_q[inst], rate_p);
                     if (rate_g < 1.5 * rate_p) {
                         h.live = false;
                         st[inst].active = 0;
@@ -2344,59 +2395,52 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                     return rc;
             }
         }
-        // ---- deflated restart: the next cycle starts from the harmonic
-        // Ritz vectors of the smallest harmonic Ritz values and the cycle's
-        // residual (csrc/dvm_eig.h), the same number for every live slot
-        const int kd_prev = kd;
-        kd = 0;
-        if (want > 0 && k >= want + 2) {
-            std::vector<int> dq(ns, 0);
-            int target = want;
-            for (int pass = 0; pass < 3 && kd == 0; ++pass) {
-                int dmin = INT_MAX, dmax = -1;
-                for (int q = 0; q < ns; ++q) {
-                    GmresSlotHost &h = hs[q];
-                    if (!h.live)
-                        continue;
-                    std::vector<double> rho(h.c.begin(), h.c.begin() + k + 1);
-                    for (int j = 0; j < k; ++j) {
-                        const double yj = hy[(size_t)q * cst + j];
-                        for (int i = 0; i <= k; ++i)
-                            rho[i] -= h.Hr[(size_t)j * (m + 1) + i] * yj;
-                    }
-                    dq[q] = dvm_eig::deflate(h.Hr, m + 1, k, rho, target, h.P, h.Hn);
-                    dmin = std::min(dmin, dq[q]);
-                    dmax = std::max(dmax, dq[q]);
-                }
-                if (dmax < 0 || dmin <= 0)
-                    break;
-                if (dmin == dmax)
-                    kd = dmin;
-                else
-                    target = pass == 0 ? dmin : dmin - 1;
-                if (target <= 0)
-                    break;
+        // ---- deflated restart: each instance's next cycle starts from the
+        // harmonic Ritz vectors of its smallest harmonic Ritz values and its
+        // cycle's residual (csrc/dvm_eig.h)
+        int dmax = 0, kin = 0;
+        for (int q = 0; q < ns; ++q) {
+            GmresSlotHost &h = hs[q];
+            const int kd_prev = h.kd;
+            h.kd = 0;
+            if (!h.live || want <= 0 || h.kq < want + 2)
+                continue;
+            const int kq = h.kq;
+            std::vector<double> rho(h.c.begin(), h.c.begin() + kq + 1);
+            for (int j = 0; j < kq; ++j) {
+                const double yj = hy[(size_t)q * cst + j];
+                for (int i = 0; i <= kq; ++i)
+                    rho[i] -= h.Hr[(size_t)j * (m + 1) + i] * yj;
             }
-            if (kd > 0) {
-                for (int q = 0; q < ns; ++q) {
-                    if (!hs[q].live)
-                        continue;
-                    double *pq = hpc.data() + (size_t)q * pstr;
-                    for (int j = 0; j <= k; ++j)
-                        for (int o = 0; o <= kd; ++o)
-                            pq[j * (kd + 1) + o] = hs[q].P[j + (size_t)o * (k + 1)];
-                }
-                HIPCHK(hipMemcpyAsync(kw.pc.p, hpc.data(), hpc.size() * sizeof(double), hipMemcpyHostToDevice,
-                                      c->stream));
-                HIPCHK(launch_vcombine(kw.ch.p, (int)chunks.size(), kw.V.p, n, k + 1, kd + 1, kw.pc.p, pstr,
-                                       kw.T.p, c->stream));
-                HIPCHK(hipMemcpyAsync(kw.V.p, kw.T.p, (size_t)(kd + 1) * n * sizeof(float),
-                                      hipMemcpyDeviceToDevice, c->stream));
-                // hpc is rewritten only after the next cycle's synchronisations
+            h.kd = std::max(dvm_eig::deflate(h.Hr, m + 1, kq, rho, want, h.P, h.Hn), 0);
+            if (h.kd > 0) {
+                dmax = std::max(dmax, h.kd);
+                kin = std::max(kin, kq + 1);
             }
             if (debug_on())
-                std::fprintf(stderr, "[dvm gmres] cycle of %d steps (from %d kept): next cycle keeps %d\n", k,
-                             kd_prev, kd);
+                std::fprintf(stderr, "[dvm gmres] inst %d: cycle of %d columns (%d kept): next cycle keeps %d\n",
+                             slots[q].inst, kq, kd_prev, h.kd);
+        }
+        if (dmax > 0) {
+            // V_0..V_dmax <- V P per slot (zero columns past a slot's own
+            // count: its Arnoldi steps rewrite them)
+            std::fill(hpc.begin(), hpc.end(), 0.0);
+            for (int q = 0; q < ns; ++q) {
+                const GmresSlotHost &h = hs[q];
+                if (!h.live || h.kd == 0)
+                    continue;
+                double *pq = hpc.data() + (size_t)q * pstr;
+                for (int j = 0; j <= h.kq; ++j)
+                    for (int o = 0; o <= h.kd; ++o)
+                        pq[j * (dmax + 1) + o] = h.P[j + (size_t)o * (h.kq + 1)];
+            }
+            HIPCHK(hipMemcpyAsync(kw.pc.p, hpc.data(), hpc.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream));
+            HIPCHK(launch_vcombine(kw.ch.p, (int)chunks.size(), kw.V.p, n, kin, dmax + 1, kw.pc.p, pstr, kw.T.p,
+                                   c->stream));
+            HIPCHK(hipMemcpyAsync(kw.V.p, kw.T.p, (size_t)(dmax + 1) * n * sizeof(float), hipMemcpyDeviceToDevice,
+                                  c->stream));
+            // hpc is rewritten only after the next cycle's synchronisations
         }
     }
     if (mixed) {

@@ -1,5 +1,5 @@
-// dvm_krylov.h -- the basis recombination of the deflated GMRES restart
-// (device kernel in dvm_vec.hip, called from the solver in dvm_api.hip).
+// dvm_krylov.h -- Krylov-vector kernels of the deflated GMRES restart (device
+// kernels in dvm_vec.hip, called from the solver in dvm_api.hip).
 #pragma once
 
 #include "dvm_internal.h"
@@ -14,5 +14,11 @@ namespace dvm {
 enum { VCOMB_IN = 65, VCOMB_OUT = 33 };
 hipError_t launch_vcombine(const VChunk *ch, int nch, const float *V, long long ldv, int nin, int nout,
                            const double *P, int pstride, float *out, hipStream_t s);
+
+// launch_vupdate4 with a per-slot switch for vout: vwrite[slot] == 0 leaves
+// that slot's part of vout as it is (its own Arnoldi process is not at this
+// column)
+hipError_t launch_vupdate4_masked(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
+                                  const double *coef, int cstride, float *vout, const int *vwrite, hipStream_t s);
 
 } // namespace dvm

@@ -257,9 +257,13 @@ __global__ void __launch_bounds__(256) k_vdots4(const VChunk *ch, const double *
 }
 
 __global__ void __launch_bounds__(256) k_vupdate4(const VChunk *ch, double *w, const float *V, long long ldv,
-                                                  int nvec, const double *coef, int cstride, float *vout)
+                                                  int nvec, const double *coef, int cstride, float *vout_all,
+                                                  const int *vwrite)
 {
     const VChunk c = ch[blockIdx.x];
+    // vwrite (optional): per slot, whether vout is written (an instance whose
+    // Arnoldi process is not at this column keeps its basis vector)
+    float *vout = vout_all && (!vwrite || vwrite[c.slot]) ? vout_all : nullptr;
     const double *cf = coef + (size_t)c.slot * cstride;
     double inv = 0.0;
     if (vout) {
@@ -597,7 +601,19 @@ hipError_t launch_vupdate4(const VChunk *ch, int nch, double *w, const float *V,
     if (ldv % 4 != 0 || reinterpret_cast<uintptr_t>(V) % 16 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0 ||
         reinterpret_cast<uintptr_t>(vout) % 16 != 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_vupdate4, dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout);
+    hipLaunchKernelGGL(k_vupdate4, dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout,
+                       static_cast<const int *>(nullptr));
+    return hipGetLastError();
+}
+hipError_t launch_vupdate4_masked(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
+                                  const double *coef, int cstride, float *vout, const int *vwrite, hipStream_t s)
+{
+    if (nch == 0)
+        return hipSuccess;
+    if (ldv % 4 != 0 || reinterpret_cast<uintptr_t>(V) % 16 != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(vout) % 16 != 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vupdate4, dim3(nch), dim3(256), 0, s, ch, w, V, ldv, nvec, coef, cstride, vout, vwrite);
     return hipGetLastError();
 }
 hipError_t launch_vupdate(const VChunk *ch, int nch, double *w, const float *V, long long ldv, int nvec,
