@@ -87,6 +87,9 @@ def parse():
                         "to the stop rule")
     p.add_argument("--no-tts", action="store_true",
                    help="batch64: skip the time-to-solution runs (for profiler runs)")
+    p.add_argument("--tts-solvers", default="fp32_refine,fp64,fp64_plain_iteration",
+                   help="batch64: which time-to-solution runs to make (comma list of fp32_refine, "
+                        "fp64, fp64_plain_iteration; for profiler runs)")
     p.add_argument("--tts-tol", type=float, default=BATCH_TTS_TOL,
                    help="batch64: stop-rule tolerance of the time-to-solution runs")
     p.add_argument("--schedule", choices=["auto", "skew", "wrap"], default="auto",
@@ -442,6 +445,8 @@ def batch_time_to_solution(args, torch, dvm, gs, deltas, vel, waves):
     for name, prec, accel in (("fp32_refine", dvm.DVM_FP32_REFINE, dvm.DVM_ACCEL_AUTO),
                               ("fp64", dvm.DVM_FP64, dvm.DVM_ACCEL_AUTO),
                               ("fp64_plain_iteration", dvm.DVM_FP64, dvm.DVM_ACCEL_NONE)):
+        if name not in args.tts_solvers.split(","):
+            continue
         s = dvm.Solver(BATCH_NV, len(gs), tol=args.tts_tol, max_iter=200000, precision=prec, accel=accel,
                        vel_per_lane=vel, waves_per_block=waves, block_iters=args.block_iters,
                        persistent=args.persistent, krylov_dim=args.krylov_dim,
@@ -469,7 +474,8 @@ def batch_time_to_solution(args, torch, dvm, gs, deltas, vel, waves):
                 abs(a - b) / abs(b) for a, b, ok in zip(Qref, Qs, conv) if ok)
         runs[name] = r
     runs["tol"] = args.tts_tol
-    runs["speedup_fp32_refine_vs_fp64"] = runs["fp64"]["seconds"] / runs["fp32_refine"]["seconds"]
+    if "fp64" in runs and "fp32_refine" in runs:
+        runs["speedup_fp32_refine_vs_fp64"] = runs["fp64"]["seconds"] / runs["fp32_refine"]["seconds"]
     return runs
 
 
