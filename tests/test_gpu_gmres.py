@@ -106,20 +106,32 @@ def test_gmres_adjoint_multi_strip(dvm):
 
 
 def test_gmres_batched_equals_single(dvm):
-    gs = [rough_channel(48, 24, 4, 24), porous_discs(40, 0.6, 1010), plane_channel(16)]
-    deltas = [0.5, 2.0, 1.0]
+    """A batch solved by GMRES matches the oracle, and every instance's
+    result is bitwise that of its own single-instance solve: each instance
+    runs its own Arnoldi process (own restart columns, own stop, own kept
+    harmonic Ritz vectors); the batch only shares the sweeps.  The last
+    instance (delta 40) restarts many times with deflation."""
+    gs = [rough_channel(48, 24, 4, 24), porous_discs(40, 0.6, 1010), plane_channel(16),
+          porous_discs(48, 0.6, 1003)]
+    deltas = [0.5, 2.0, 1.0, 40.0]
     nv = 8
-    b = dvm.Solver(nv, len(gs), tol=1e-10, accel=dvm.DVM_ACCEL_GMRES)
+    shape = dict(vel_per_lane=4, waves_per_block=8)   # the same sweep layout in both contexts
+    b = dvm.Solver(nv, len(gs), tol=1e-10, accel=dvm.DVM_ACCEL_GMRES, **shape)
     for i, g in enumerate(gs):
         b.set_geometry(i, g.mask, g.periodic_y, g.cells_per_H)
     infos = b.solve(-1, deltas)
     Qb = [b.flow_rate(i)[0] for i in range(len(gs))]
+    ub = [b.moments(i)["u1"] for i in range(len(gs))]
     b.close()
     for i, g in enumerate(gs):
         assert infos[i].status == "converged"
         ref = oracle.si_solve(g.mask, deltas[i], nv, periodic_y=g.periodic_y,
                               cells_per_H=g.cells_per_H, tol=1e-12)
         assert abs(Qb[i] - ref.Q) <= 1e-8 * abs(ref.Q), (i, Qb[i], ref.Q)
+        s, info, Q1, mom1 = solve(dvm, g, deltas[i], nv, **shape)
+        s.close()
+        assert Q1 == Qb[i], (i, Q1, Qb[i])
+        assert np.array_equal(mom1["u1"], ub[i]), i
 
 
 def test_auto_hands_diverging_instances_to_gmres(dvm):
