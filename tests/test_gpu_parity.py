@@ -189,6 +189,33 @@ def test_max_iter_then_resume(dvm):
     s3.close()
 
 
+@pytest.mark.parametrize("graphs", [True, False])
+def test_resume_is_bitwise(dvm, graphs):
+    """A solve stopped at max_iter and resumed warm continues the same
+    iteration: 40 iterations in slices of 8 give bitwise the moments of 40
+    uninterrupted ones (plain iteration, so nothing but the state carries
+    over; a tolerance no iterate reaches)."""
+    g = rough_channel(32, 16, 3, 16)
+    kw = dict(tol=1e-300, block_iters=4, accel=dvm.DVM_ACCEL_NONE, use_graphs=graphs,
+              vel_per_lane=4, waves_per_block=8)
+    a = dvm.Solver(8, 1, max_iter=40, **kw)
+    a.set_geometry(0, g.mask, False, 16.0)
+    ia = a.solve(0, 5.0, raise_on_noconv=False)
+    assert ia.status == "max_iter" and ia.iters == 40
+    b = dvm.Solver(8, 1, max_iter=8, **kw)
+    b.set_geometry(0, g.mask, False, 16.0)
+    ib = b.solve(0, 5.0, raise_on_noconv=False)
+    for _ in range(4):
+        ib = b.solve(0, 5.0, warm=True, raise_on_noconv=False)
+    assert ib.status == "max_iter"
+    ma, mb = a.moments(0), b.moments(0)
+    for k in ("rho", "u1", "u2", "tau"):
+        assert np.array_equal(ma[k], mb[k]), k
+    assert a.flow_rate(0)[0] == b.flow_rate(0)[0]
+    a.close()
+    b.close()
+
+
 def test_warm_start_delta_sweep(dvm):
     g = rough_channel(48, 24, 5, 24)
     s = dvm.Solver(8, 1, tol=1e-11)
