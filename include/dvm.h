@@ -61,7 +61,7 @@ extern "C" {
                                method); GMRES takes over an instance whose
                                iteration stops contracting, and is tried on
                                one that contracts slowly (q > 0.98 with over
-                               1000 iterations to go), kept while its cycles
+                               300 iterations to go), kept while its cycles
                                together reduce the residual 1.5 x faster than
                                the plain iteration per unit of work (sweeps,
                                the orthogonalisation counted in sweep
@@ -70,12 +70,18 @@ extern "C" {
                                is extrapolated the same way (where its
                                tolerance is far above the extrapolated FP32
                                rounding), and a correction that contracts
-                               slowly or not at all continues in GMRES whose
+                               slowly (q > 0.98 with over 1000 iterations to
+                               go) or not at all continues in GMRES whose
                                Krylov steps are FP32 sweeps (each cycle from
                                the FP64 residual)                            */
 #define DVM_ACCEL_NONE 1    /* plain source iteration only (the paper's)      */
 #define DVM_ACCEL_GMRES 2   /* restarted GMRES on the fixed-point map of the
-                               iteration from the start                       */
+                               iteration from the start.  Restarts are
+                               deflated (see krylov_deflate); the instances of
+                               a batch share the sweeps of each Arnoldi step
+                               but each runs its own Arnoldi process, so a
+                               batch gives every instance bitwise the result
+                               of its own solve                               */
 
 #define DVM_STATUS_RUNNING 0
 #define DVM_STATUS_CONVERGED 1
