@@ -233,3 +233,31 @@ def test_gmres_deflated_restarts(dvm):
     assert abs(qd - qp) <= 1e-8 * abs(qp), (qd, qp)
     assert np.max(np.abs(ud - up)) <= 1e-8
     assert idf < 0.8 * ip, (idf, ip)
+
+
+@pytest.mark.parametrize("m,kd", [(8, 1), (12, 0), (16, 7), (64, 31), (40, -1)])
+def test_gmres_restart_shapes(dvm, m, kd):
+    """Restart lengths and kept counts at the edges of their ranges (one
+    kept vector, a kept count one short of half the restart, the largest
+    kept count) reach the oracle's fixed point on the large-delta porous
+    cell; kd = 0 keeps a quarter of the restart, kd < 0 restarts plainly.
+    (Much shorter restarts do not stop here: the stop rule divides the
+    change by the smallest singular value of the cycle's projection, which
+    a four-step cycle underestimates.)"""
+    g = porous_discs(48, 0.6, 1003)
+    nv = 8
+    ref = _ref48(g)
+    s, info, Q, mom = solve(dvm, g, 40.0, nv, krylov_dim=m, krylov_deflate=kd, max_iter=40000)
+    s.close()
+    assert info.status == "converged", info
+    assert abs(Q - ref.Q) <= 1e-8 * abs(ref.Q), (Q, ref.Q)
+    assert np.max(np.abs(mom["u1"] - ref.u1)) <= 1e-8
+
+
+_REF48 = {}
+
+
+def _ref48(g):
+    if "r" not in _REF48:
+        _REF48["r"] = oracle.si_solve(g.mask, 40.0, 8, periodic_y=True, cells_per_H=48.0, tol=1e-12)
+    return _REF48["r"]
