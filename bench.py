@@ -111,7 +111,7 @@ def parse():
                    help="run blocks of iterations as one cooperative launch (untimed sweeps only: "
                         "the roofline's timed steps use separate launches)")
     p.add_argument("--krylov-dim", type=int, default=0,
-                   help="GMRES restart length (0: the library's default, 64)")
+                   help="GMRES restart length (0: the library's default, 40 with deflated restarts)")
     p.add_argument("--krylov-deflate", type=int, default=0,
                    help="harmonic Ritz vectors a GMRES cycle hands to the next (0: the library's "
                         "default, negative: plain restarts)")

@@ -2252,7 +2252,6 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                                           kw.vw.p, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
         }
-        int k = jmin;
         for (int j = jmin; j < m; ++j) {
             // the instances that take this step: live, not yet stopped, and
             // past their kept vectors
@@ -2286,7 +2285,6 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
             HIPCHK(hipMemcpyAsync(hc2.data(), kw.c2.p, hc2.size() * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            k = j + 1;
             for (int q = 0; q < ns; ++q) {
                 GmresSlotHost &h = hs[q];
                 if (!hvw[q])
@@ -2350,7 +2348,6 @@ static int gmres_run(dvm_ctx *c, int i0, int i1, bool adj, std::vector<SolveStat
                 hy[(size_t)q * cst + i] = y[i];
             h.sig = sigma_min_tri(h.H, m + 1, kq);
         }
-        (void)k;
         HIPCHK(hipMemcpyAsync(kw.y.p, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(launch_vupdate4(kw.ch.p, (int)chunks.size(), kw.x.p, kw.V.p, n, kmax, kw.y.p, cst, nullptr,
                               c->stream));
