@@ -271,7 +271,7 @@ def main():
         "config": {"workload": "rough_channel_256x128_blocks26x128_nv64_delta0.1_1_10",
                    "nx": g.nx, "ny": g.ny, "fluid_cells": nf, "velocities": K,
                    "deltas": list(DELTAS), "tol": args.tol, "precision": args.precision,
-                   "schedule": args.schedule, "accel": args.accel, "block_iters": args.block_iters,
+                   "schedule": args.schedule, "accel": args.accel, "krylov": krylov_config(args), "block_iters": args.block_iters,
                    "parallelism": "single_gpu"},
         "iterations_per_delta": all_its[-1],
         "schedule_per_delta": scheds,
@@ -295,6 +295,17 @@ def solver_options(args, dvm):
                       "gmres": dvm.DVM_ACCEL_GMRES}[args.accel],
             "block_iters": args.block_iters, "persistent": args.persistent,
             "krylov_dim": args.krylov_dim, "krylov_deflate": args.krylov_deflate}
+
+
+def krylov_config(args):
+    """GMRES restart length and kept harmonic Ritz vectors as the library
+    applies them (0 selects its defaults: 40 and 10 with deflated restarts,
+    64 with plain ones)."""
+    deflate = args.krylov_deflate >= 0
+    m = args.krylov_dim if args.krylov_dim > 0 else (40 if deflate else 64)
+    m = min(m, 64)
+    kept = 0 if not deflate else min(args.krylov_deflate if args.krylov_deflate > 0 else m // 4, m // 2 - 1)
+    return {"restart": m, "kept": max(kept, 0)}
 
 
 def stored_oracle_error(g, Qs):
@@ -370,7 +381,7 @@ def bench_batch(args, torch, dvm):
                       "fluid_cells": int(sum(nfl)), "velocities": K,
                       "iterations_per_step": "to the stop rule" if to_conv else args.batch_iters,
                       "tol": args.tol if to_conv else None, "precision": prec_name,
-                      "launch_shape": [vel, waves], "schedule": args.schedule, "accel": args.accel,
+                      "launch_shape": [vel, waves], "schedule": args.schedule, "accel": args.accel, "krylov": krylov_config(args),
                       "parallelism": "single_gpu"},
            "sweeps_per_step": {"fp32": sweeps32 // max(args.steps, 1), "fp64": sweeps64 // max(args.steps, 1)},
            "roofline": roofline, "time_to_solution": tts, "cpu_baseline": cpu}
@@ -528,7 +539,7 @@ def bench_couette(args, torch, dvm):
            "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
            "config": {"workload": "couette_wm_D1.5_eps0.02_aspect5_graded60+100rows_64perH_nv32",
                       "rough_cells": [rough.ny, rough.nx], "Kn": kns, "tol": args.tol,
-                      "precision": args.precision, "schedule": args.schedule, "accel": args.accel,
+                      "precision": args.precision, "schedule": args.schedule, "accel": args.accel, "krylov": krylov_config(args),
                       "parallelism": "single_gpu"},
            "Q_rough": [float(q) for q in qr], "Q_smooth": [float(q) for q in qs],
            "Q_star": [float(a / b) for a, b in zip(qr, qs)],
@@ -584,7 +595,7 @@ def bench_porous(args, torch, dvm):
            "config": {"workload": "porous_discs_512x512_phi0.6_seed1003_nv64_delta0.01-100x8",
                       "nx": g.nx, "ny": g.ny, "fluid_cells": g.n_fluid, "porosity": phi,
                       "velocities": nv * nv, "deltas": deltas, "tol": args.tol,
-                      "precision": args.precision, "schedule": args.schedule, "accel": args.accel,
+                      "precision": args.precision, "schedule": args.schedule, "accel": args.accel, "krylov": krylov_config(args),
                       "parallelism": "single_gpu"},
            "iterations_per_delta": its, "time_to_solution_s": tts, "Q": Qs,
            "k_inf": perm["k_inf"], "H_star": perm["H_star"],
@@ -638,7 +649,7 @@ def bench_adjoint(args, torch, dvm):
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"adjoint_porous_256x256_phi0.55_seed3005_deltafield_alpha{alpha:g}_nv48",
                       "nx": g.nx, "ny": g.ny, "fluid_cells": g.n_fluid, "velocities": nv * nv,
-                      "alpha": alpha, "tol": args.tol, "schedule": args.schedule, "accel": args.accel,
+                      "alpha": alpha, "tol": args.tol, "schedule": args.schedule, "accel": args.accel, "krylov": krylov_config(args),
                       "parallelism": "single_gpu"},
            "value_is": "forward-solve updates/s", "forward_iterations": info.iters,
            "forward_s": float(np.mean(fwd)), "gradient_s": float(np.mean(adj)),
