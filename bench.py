@@ -115,6 +115,9 @@ def parse():
     p.add_argument("--krylov-deflate", type=int, default=0,
                    help="harmonic Ritz vectors a GMRES cycle hands to the next (0: the library's "
                         "default, negative: plain restarts)")
+    p.add_argument("--continuation", action="store_true",
+                   help="porous: warm starts from the state extrapolated in log(delta) through the "
+                        "last two solutions (warm_extrapolate) instead of the last solution as it is")
     p.add_argument("--vel", type=int, default=0)
     p.add_argument("--waves", type=int, default=0)
     p.add_argument("--no-roofline", action="store_true",
@@ -552,7 +555,9 @@ def bench_porous(args, torch, dvm):
     cells, seeded overlapping discs (radius 0.03-0.08 of the side) to
     porosity 0.6 with non-percolating pores filled, 64 x 64 velocities,
     delta log-spaced over [0.01, 100] (8 values), each solve warm-started
-    from the previous one (rarefied end first).  Reports per-delta sweeps,
+    from the previous one (rarefied end first; with --continuation from the
+    third delta on from the state extrapolated in log(delta)).
+    Reports per-delta sweeps,
     time and Q, and the post-processing: k_inf, H*, Kn*, k_a/k_inf."""
     from paper_1704_03126_amd.geometry import cfg_porous
     nv = 64
@@ -560,7 +565,7 @@ def bench_porous(args, torch, dvm):
     deltas = [float(d) for d in np.logspace(-2, 2, 8)]
     phi = float(np.mean(g.mask == 0))
     s = dvm.Solver(nv, 1, tol=args.tol, precision=dvm.DVM_FP32_REFINE if args.precision == "fp32_refine"
-                   else dvm.DVM_FP64, **solver_options(args, dvm))
+                   else dvm.DVM_FP64, warm_extrapolate=args.continuation, **solver_options(args, dvm))
     s.set_geometry(0, g.mask, g.periodic_y, g.cells_per_H)
 
     def step():
@@ -596,7 +601,7 @@ def bench_porous(args, torch, dvm):
                       "nx": g.nx, "ny": g.ny, "fluid_cells": g.n_fluid, "porosity": phi,
                       "velocities": nv * nv, "deltas": deltas, "tol": args.tol,
                       "precision": args.precision, "schedule": args.schedule, "accel": args.accel, "krylov": krylov_config(args),
-                      "parallelism": "single_gpu"},
+                      "continuation": args.continuation, "parallelism": "single_gpu"},
            "iterations_per_delta": its, "time_to_solution_s": tts, "Q": Qs,
            "k_inf": perm["k_inf"], "H_star": perm["H_star"],
            "Kn_star": [float(x) for x in perm["Kn_star"]],

@@ -176,6 +176,18 @@ typedef struct {
                                krylov_dim/2 - 1; a complex pair is kept
                                whole (one more).  A cycle whose kept basis
                                cannot be formed to rounding restarts plainly */
+    int warm_extrapolate;   /* 1: continuation for sweeps in delta.  After
+                               each converged solve at a uniform delta the
+                               library keeps the instance's state (two per
+                               instance, device memory of two GMRES state
+                               vectors); a warm solve (dvm_solve_warm) at a
+                               new delta, same alpha, drive and walls, then
+                               starts from the state extrapolated linearly in
+                               log(delta) through the last two solutions, if
+                               the step goes on in the same direction and at
+                               most doubles.  Same fixed point, fewer
+                               iterations.  0 (default): warm solves start
+                               from the last state as it is                  */
 } dvm_config;
 
 /* Per-instance result of dvm_solve. */

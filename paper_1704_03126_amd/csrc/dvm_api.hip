@@ -221,6 +221,16 @@ struct dvm_ctx {
     DevBuf<SolveState> d_st_adj;
 
     KrylovWork kw;
+    // warm-start continuation (cfg.warm_extrapolate): per instance the state
+    // vectors of its last two converged solves at a uniform delta, in the
+    // layout generation they were taken in
+    DevBuf<double> whist[2];
+    DevBuf<VSeg> wseg;
+    DevBuf<double> wvec;
+    std::vector<long long> whist_off, whist_len;
+    std::vector<double> whist_d0, whist_d1, whist_par;   // deltas; alpha, drive, walls of the last one
+    std::vector<int> whist_n;
+    long long layout_gen = 0, whist_gen = -1;
     std::vector<long long> sweeps_done;   // per instance, last solve
     std::vector<long long> sweeps64_done; // of which FP64 sweeps
     std::vector<long long> gmres_s64;     // FP64 sweeps of the instance's last GMRES run
@@ -289,6 +299,7 @@ struct dvm_ctx {
         d_seam_adj.release(); d_wrap_adj.release(); d_fb_adj.release(); d_ckpt.release();
         d_part5.release(); d_momg.release(); d_dqda.release(); d_st_adj.release();
         kw.release();
+        whist[0].release(); whist[1].release(); wseg.release(); wvec.release();
         d_srec32.release(); d_seam32.release(); d_wrap32.release(); d_fb32.release(); d_vt32.release();
         d_mom_d.release(); d_u1prev_d.release(); d_xr.release(); d_rr.release(); d_er.release();
         d_rb_mom.release(); d_rb_wrap.release(); d_seg32s.release(); d_rr32.release();
@@ -860,6 +871,7 @@ static int build_layout(dvm_ctx *c)
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     c->layout_ok = true;
+    c->layout_gen += 1;
     return DVM_OK;
 }
 
@@ -3120,6 +3132,136 @@ static int check_instance(const dvm_ctx *c, int instance)
     return DVM_OK;
 }
 
+// ------------------------------------------------ warm-start continuation
+// cfg.warm_extrapolate: a warm solve at a new uniform delta starts from the
+// state extrapolated linearly in log(delta) through the instance's last two
+// converged solves (same alpha, drive and walls, same layout):
+//   x0 = x + theta (x_1 - x_2),  theta = log(delta / d_1) / log(d_1 / d_2),
+// x the current state (normally x_1, the last solution), for
+// 0 < theta <= 2 (forward along the sweep, at most twice its last step).
+// The fixed point is the plain warm start's; only the start is closer.  The
+// state vector is the GMRES one: moments, lagged seam, wrap and wall values.
+
+static StateBufs fwd_state_bufs(dvm_ctx *c)
+{
+    StateBufs sb;
+    sb.b[0] = c->d_mom.p;
+    sb.b[1] = c->d_seam.p;
+    sb.b[2] = c->d_wrap.p;
+    sb.b[3] = c->d_fb.p;
+    return sb;
+}
+
+// history slots for the current layout (a new layout drops the history)
+static int whist_ensure(dvm_ctx *c)
+{
+    if (c->whist_gen == c->layout_gen)
+        return DVM_OK;
+    c->whist_off.assign(c->n_inst, 0);
+    c->whist_len.assign(c->n_inst, 0);
+    c->whist_n.assign(c->n_inst, 0);
+    c->whist_d0.assign(c->n_inst, 0.0);
+    c->whist_d1.assign(c->n_inst, 0.0);
+    c->whist_par.assign((size_t)c->n_inst * 4, 0.0);
+    long long tot = 0, lmax = 1;
+    for (int i = 0; i < c->n_inst; ++i) {
+        c->whist_off[i] = tot;
+        c->whist_len[i] = c->inst[i].has_geom ? state_segments(c, i, 0, 0, nullptr, nullptr) : 0;
+        tot += c->whist_len[i];
+        lmax = std::max(lmax, c->whist_len[i]);
+    }
+    for (auto &b : c->whist)
+        HIPCHK(b.alloc((size_t)std::max<long long>(tot, 1)));
+    HIPCHK(c->wvec.alloc((size_t)lmax));
+    c->whist_gen = c->layout_gen;
+    return DVM_OK;
+}
+
+// segment table of instance i's current state (the inputs of its next sweep)
+static int whist_segs(dvm_ctx *c, int i, const SolveState &s, long long *len, int *nseg)
+{
+    std::vector<VSeg> sc;
+    *len = state_segments(c, i, (int)(s.iter & 1), 0, nullptr, &sc);
+    *nseg = (int)sc.size();
+    if (c->wseg.n < sc.size())
+        HIPCHK(c->wseg.alloc(sc.size()));
+    if (!sc.empty())
+        HIPCHK(hipMemcpyAsync(c->wseg.p, sc.data(), sc.size() * sizeof(VSeg), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DVM_OK;
+}
+
+static void whist_params(const dvm_ctx *c, int i, double *par)
+{
+    par[0] = c->inst[i].alpha;
+    par[1] = c->driving[i].drive;
+    par[2] = c->driving[i].u_bot;
+    par[3] = c->driving[i].u_top;
+}
+
+// after a converged uniform-delta solve: its state becomes x_1
+static int whist_save(dvm_ctx *c, int i, const SolveState &s)
+{
+    int rc = whist_ensure(c);
+    if (rc)
+        return rc;
+    long long len = 0;
+    int nseg = 0;
+    if ((rc = whist_segs(c, i, s, &len, &nseg)))
+        return rc;
+    if (len != c->whist_len[i] || len == 0) {
+        c->whist_n[i] = 0;
+        return DVM_OK;
+    }
+    double par[4];
+    whist_params(c, i, par);
+    if (c->whist_n[i] > 0 && !std::equal(par, par + 4, &c->whist_par[(size_t)i * 4]))
+        c->whist_n[i] = 0;                    // other parameters: start a new history
+    double *h0 = c->whist[0].p + c->whist_off[i], *h1 = c->whist[1].p + c->whist_off[i];
+    if (c->whist_n[i] > 0)
+        HIPCHK(hipMemcpyAsync(h1, h0, (size_t)len * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(launch_gather(c->wseg.p, nseg, fwd_state_bufs(c), h0, nullptr, c->stream));
+    c->whist_d1[i] = c->whist_d0[i];
+    c->whist_d0[i] = c->inst[i].delta;
+    c->whist_n[i] = std::min(c->whist_n[i] + 1, 2);
+    std::copy(par, par + 4, &c->whist_par[(size_t)i * 4]);
+    return DVM_OK;
+}
+
+// before a warm solve at delta: x <- x + theta (x_1 - x_2) where it applies
+static int whist_start(dvm_ctx *c, int i, const SolveState &s, double delta)
+{
+    if (c->whist_gen != c->layout_gen || c->whist_n[i] < 2)
+        return DVM_OK;
+    double par[4];
+    whist_params(c, i, par);
+    const double d1 = c->whist_d0[i], d2 = c->whist_d1[i];
+    if (!std::equal(par, par + 4, &c->whist_par[(size_t)i * 4]) || !(d1 > 0.0 && d2 > 0.0 && delta > 0.0) ||
+        d1 == d2 || delta == d1)
+        return DVM_OK;
+    const double theta = std::log(delta / d1) / std::log(d1 / d2);
+    if (!(theta > 0.0 && theta <= 2.0))
+        return DVM_OK;
+    long long len = 0;
+    int nseg = 0;
+    int rc = whist_segs(c, i, s, &len, &nseg);
+    if (rc)
+        return rc;
+    if (len != c->whist_len[i])
+        return DVM_OK;
+    const StateBufs sb = fwd_state_bufs(c);
+    const double *h0 = c->whist[0].p + c->whist_off[i], *h1 = c->whist[1].p + c->whist_off[i];
+    HIPCHK(launch_gather(c->wseg.p, nseg, sb, c->wvec.p, nullptr, c->stream));
+    HIPCHK(launch_axpy(c->wvec.p, h0, theta, (size_t)len, c->stream));
+    HIPCHK(launch_axpy(c->wvec.p, h1, -theta, (size_t)len, c->stream));
+    HIPCHK(launch_scatter(c->wseg.p, nseg, sb, c->wvec.p, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (debug_on())
+        std::fprintf(stderr, "[dvm continuation] inst %d: delta %.4g from %.4g and %.4g, theta %.3f\n", i, delta,
+                     d1, d2, theta);
+    return DVM_OK;
+}
+
 static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_field,
                     double alpha, dvm_info *info, bool warm, int depth = 0)
 {
@@ -3206,6 +3348,7 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     std::vector<long long> iter0(c->n_inst, 0);
+    std::vector<char> kept(c->n_inst, 0);
     for (int i = 0; i < c->n_inst; ++i) {
         SolveState &s = st[i];
         bool mine = i >= i0 && i < i1;
@@ -3213,6 +3356,7 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
             s = SolveState{};
         if (mine) {
             bool keep = warm && c->inst[i].has_state;
+            kept[i] = keep ? 1 : 0;
             if (!keep) {
                 const InstDev &d = c->idev[i];
                 size_t n = (size_t)d.nx * d.ny;
@@ -3244,6 +3388,13 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
     }
     HIPCHK(hipMemcpyAsync(c->d_st.p, st.data(), c->n_inst * sizeof(SolveState), hipMemcpyHostToDevice,
                           c->stream));
+    if (c->cfg.warm_extrapolate > 0 && !delta_is_field)
+        for (int i = i0; i < i1; ++i)
+            if (kept[i]) {
+                int rc = whist_start(c, i, st[i], c->inst[i].delta);
+                if (rc)
+                    return rc;
+            }
     // the record of the first sweep (from zero or the warm moments); the stop
     // statistics it gathers are discarded
     HIPCHK(launch_record<double>(rec_args(c), c->max_cells, c->n_inst, c->stream));
@@ -3310,6 +3461,11 @@ static int do_solve(dvm_ctx *c, int instance, const double *delta, int delta_is_
             o.schedule = c->idev[i].tp == c->idev[i].nx && c->idev[i].nx > 1 ? DVM_SCHED_WRAP : DVM_SCHED_SKEW;
         }
         c->inst[i].converged = s.status == STATUS_CONVERGED;
+        if (c->cfg.warm_extrapolate > 0 && !delta_is_field && s.status == STATUS_CONVERGED) {
+            int rs = whist_save(c, i, s);
+            if (rs)
+                return rs;
+        }
         if (s.status == STATUS_DIVERGED)
             rc = fail(DVM_EDIVERGED, "instance " + std::to_string(i) + " produced non-finite iterates");
         else if (rc == DVM_OK && s.status != STATUS_CONVERGED)
@@ -3540,6 +3696,8 @@ int dvm_create(dvm_ctx **out, int nv, int n_instances, const dvm_config *cfg, vo
         return fail(DVM_EINVAL, "persistent must be 0 or 1");
     if (c.krylov_deflate > VCOMB_OUT - 2)
         return fail(DVM_EINVAL, "krylov_deflate must be at most 31");
+    if (c.warm_extrapolate != 0 && c.warm_extrapolate != 1)
+        return fail(DVM_EINVAL, "warm_extrapolate must be 0 or 1");
     int V = c.vel_per_lane ? c.vel_per_lane : 4;
     int G = c.waves_per_block ? c.waves_per_block : 8;
     bool okvg = (V == 4 && G == 8) || (V == 8 && G == 4) || (V == 4 && G == 4) || (V == 2 && G == 8);

@@ -54,7 +54,7 @@ class dvm_config(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
                 ("profile", ctypes.c_int), ("schedule", ctypes.c_int),
                 ("accel", ctypes.c_int), ("krylov_dim", ctypes.c_int), ("persistent", ctypes.c_int),
-                ("krylov_deflate", ctypes.c_int)]
+                ("krylov_deflate", ctypes.c_int), ("warm_extrapolate", ctypes.c_int)]
 
 
 class dvm_prof(ctypes.Structure):
@@ -203,12 +203,13 @@ class Solver:
                  waves_per_block: int = 0, profile: bool = False, schedule: int = DVM_SCHED_AUTO,
                  accel: int = DVM_ACCEL_AUTO, krylov_dim: int = 0, tune_cache: str | None = None,
                  stream=None, allocator: TorchAllocator | None = None, persistent: bool = False,
-                 krylov_deflate: int = 0):
+                 krylov_deflate: int = 0, warm_extrapolate: bool = False):
         lib = load_library()
         tc = tune_cache.encode() if tune_cache else None
         cfg = dvm_config(precision, tol, max_iter, block_iters, int(use_graphs),
                          vel_per_lane, waves_per_block, tc, int(profile), int(schedule),
-                         int(accel), int(krylov_dim), int(persistent), int(krylov_deflate))
+                         int(accel), int(krylov_dim), int(persistent), int(krylov_deflate),
+                         int(warm_extrapolate))
         h = ctypes.c_void_p()
         s = stream if stream is not None else _current_stream()
         self.allocator = allocator          # kept alive until dvm_destroy
@@ -294,7 +295,9 @@ class Solver:
 
     def delta_sweep(self, instance: int, deltas, alpha: float = 1.0):
         """Solve one instance along a rarefaction sweep, each solve starting
-        from the previous solution; returns (Q per delta, SolveInfo per delta)."""
+        from the previous solution (from the state extrapolated in log(delta)
+        through the last two when the Solver was built with
+        warm_extrapolate=True); returns (Q per delta, SolveInfo per delta)."""
         Qs, infos = [], []
         for i, d in enumerate(deltas):
             infos.append(self.solve(instance, float(d), alpha, warm=i > 0))

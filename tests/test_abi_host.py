@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(lib):
 def _ctx(lib, nv=8, n=1, **kw):
     cfg = dvm.dvm_config(kw.get("precision", 0), kw.get("tol", 1e-8), kw.get("max_iter", 1000),
                          kw.get("block_iters", 0), 1, kw.get("vel", 0), kw.get("waves", 0), None, 0,
-                         kw.get("schedule", 0), 0, 0, kw.get("persistent", 0), kw.get("deflate", 0))
+                         kw.get("schedule", 0), 0, 0, kw.get("persistent", 0), kw.get("deflate", 0), kw.get("wx", 0))
     h = ctypes.c_void_p()
     rc = lib.dvm_create(ctypes.byref(h), nv, n, ctypes.byref(cfg), None,
                         kw.get("alloc", dvm._ALLOC_FN()), kw.get("free", dvm._FREE_FN()), None)
@@ -56,6 +56,7 @@ def test_create_validates_arguments(lib):
     assert _ctx(lib, schedule=3)[0] == dvm.DVM_EINVAL
     assert _ctx(lib, persistent=2)[0] == dvm.DVM_EINVAL
     assert _ctx(lib, deflate=32)[0] == dvm.DVM_EINVAL
+    assert _ctx(lib, wx=2)[0] == dvm.DVM_EINVAL
     for d in (-1, 8, 31):
         rc, h = _ctx(lib, deflate=d)
         assert rc == dvm.DVM_OK

@@ -44,3 +44,34 @@ def test_porous_sweep_permeability(dvm):
     assert np.allclose(got["ka_ratio"], ref["ka_ratio"], rtol=1e-7, atol=0)
     # k_a decreases towards k_inf as the flow becomes continuum
     assert np.all(np.diff(got["k_a"]) < 0) and got["k_inf"] < got["k_a"][-1]
+
+
+def test_delta_sweep_continuation(dvm):
+    """Warm starts extrapolated in log(delta) through the last two solutions
+    (warm_extrapolate): every delta of the sweep reaches the same fixed point
+    as with plain warm starts, in fewer sweeps over the sweep; a second
+    sweep from the rarefied end again (direction reversed: no
+    extrapolation at its first warm step) and a sweep with alpha changed
+    half-way (history restarted) also stay exact."""
+    g = porous_discs(96, 0.6, 1003)
+    deltas = [0.03, 0.1, 0.3, 1.0, 3.0, 10.0]
+    res = {}
+    for cont in (False, True):
+        s = dvm.Solver(16, 1, tol=1e-10, warm_extrapolate=cont)
+        s.set_geometry(0, g.mask, True, 96.0)
+        Qs, infos = s.delta_sweep(0, deltas)
+        assert all(i.status == "converged" for i in infos)
+        res[cont] = (Qs, sum(i.iters for i in infos))
+        if cont:
+            Q2, inf2 = s.delta_sweep(0, deltas[:3])
+            assert all(i.status == "converged" for i in inf2)
+            np.testing.assert_allclose(Q2, Qs[:3], rtol=2e-9, atol=0)
+            q_a = [s.solve(0, d, 0.8, warm=True).status for d in deltas[3:5]]
+            assert q_a == ["converged"] * 2
+        s.close()
+    (Qp, ip), (Qc, ic) = res[False], res[True]
+    np.testing.assert_allclose(Qc, Qp, rtol=2e-9, atol=0)
+    assert ic < ip, (ic, ip)
+    for d, q in zip(deltas[::2], Qc[::2]):
+        ref = oracle.si_solve(g.mask, d, 16, periodic_y=True, cells_per_H=96.0, tol=1e-12)
+        assert abs(q - ref.Q) <= 1e-8 * abs(ref.Q), (d, q, ref.Q)
