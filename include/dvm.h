@@ -61,7 +61,8 @@ extern "C" {
                                method); GMRES takes over an instance whose
                                iteration stops contracting, and is tried on
                                one that contracts slowly (q > 0.98 with over
-                               300 iterations to go), kept while its cycles
+                               150 iterations to go; 300 for the FP64 tails
+                               of DVM_FP32_REFINE), kept while its cycles
                                together reduce the residual 1.5 x faster than
                                the plain iteration per unit of work (sweeps,
                                the orthogonalisation counted in sweep

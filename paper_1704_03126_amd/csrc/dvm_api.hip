@@ -1448,14 +1448,15 @@ static int extrapolate32(dvm_ctx *c, const std::vector<int> &cand, const std::ve
 }
 
 // GMRES trial under AUTO: the plain iteration must be predicted to need more
-// than this many further iterations.  FP64 iteration: 300 (with deflated
+// than this many further iterations.  FP64 solver: 150 (with deflated
 // restarts GMRES pays off sooner; measured on the bench workloads: time to
 // solution of the uneven batch in FP64 10.9 s at 1000, 7.5 s at 300, 7.3 s at
-// 150; the porous sweep's step 11.8 / 9.8 / 8.4 s; the refinement's FP64
-// tails slower below 300).  FP32 correction iteration: 1000 (its GMRES adds
-// an FP64 residual sweep per cycle; the batch's refinement took 6.8 s at
-// 1000 and 6.9 s at 300).
-constexpr double TRIAL_MIN_ITERS64 = 300.0;
+// 150; the porous sweep's step 11.8 / 9.8 / 8.4 s).  The FP64 tails of the
+// refinement: 300 (the batch's refinement took 7.1 s at 150, 6.8 s at 300).
+// FP32 correction iteration: 1000 (its GMRES adds an FP64 residual sweep per
+// cycle; 6.8 s at 1000 and 6.9 s at 300).
+constexpr double TRIAL_MIN_ITERS64 = 150.0;
+constexpr double TRIAL_MIN_ITERS64_TAIL = 300.0;
 constexpr double TRIAL_MIN_ITERS32 = 1000.0;
 
 // Replay blocks of iterations until no instance of [i0, i1) is active.  A
@@ -1470,8 +1471,9 @@ constexpr double TRIAL_MIN_ITERS32 = 1000.0;
 // first case.
 // With no_trial given (AUTO), an instance whose contraction per iteration has
 // settled above 0.98 (no extrapolation there) with more than
-// TRIAL_MIN_ITERS64 iterations still to go is stopped for a GMRES trial
-// (stalled = 3); its rate is left in c->trial_q.
+// TRIAL_MIN_ITERS64 (refinement tails: TRIAL_MIN_ITERS64_TAIL) iterations
+// still to go is stopped for a GMRES trial (stalled = 3); its rate is left in
+// c->trial_q.
 static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &iter0, int kind,
                       std::vector<SolveState> &st, std::vector<char> *stalled = nullptr,
                       const std::vector<char> *grow_only = nullptr,
@@ -1603,7 +1605,9 @@ static int run_blocks(dvm_ctx *c, int i0, int i1, const std::vector<long long> &
                     eps_at[i] = st[i].eps;
                     e.clear();
                 } else if (kind != 2 && stalled && no_trial && !(*no_trial)[i] && qa > 0.98 && qa < 1.0 &&
-                           settled && std::log(tol / err) / std::log(qa) > TRIAL_MIN_ITERS64) {
+                           settled && std::log(tol / err) / std::log(qa) >
+                                          (c->cfg.precision == DVM_FP32_REFINE ? TRIAL_MIN_ITERS64_TAIL
+                                                                               : TRIAL_MIN_ITERS64)) {
                     st[i].active = 0;
                     (*stalled)[i] = 3;
                     c->trial_q[i] = qa;
